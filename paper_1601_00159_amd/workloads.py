@@ -1,0 +1,188 @@
+"""Seeded synthetic workloads for the batched skip-list index.
+
+This module only draws random inputs; it holds none of the index's own
+arithmetic (no height rule, no search, no ordering of queries), so both the GPU
+path and the CPU checker can consume the same arrays.
+
+The paper measures on YCSB-generated query streams with uniform or Zipfian key
+choice and update ratios of 0 / 5% / 50% (Section 6, parameter table and
+Section 6.6).  YCSB itself is not used here: these generators reproduce its
+shapes -- uniform or Zipf(theta) choice over the loaded keys, fresh uniform keys
+for inserts, fixed op mixes -- at the sizes of the workloads below.
+
+Every array comes from ``numpy.random.Generator(PCG64(SeedSequence([base,
+stream, batch])))`` with ``base = 0x50490000 + 16 * workload_id``; streams:
+0 loaded keys, 1 ops, 2 query keys, 3 values, 4 arrivals, 5 choice of source.
+"""
+from dataclasses import dataclass, field
+from typing import List, Optional
+
+import numpy as np
+
+SEARCH, INSERT, DELETE = 0, 1, 2
+KEY_SPACE = 1 << 63  # loaded and fresh keys are uniform in [0, 2^63)
+
+ST_LOAD, ST_OPS, ST_QKEYS, ST_VALS, ST_ARRIVAL, ST_SOURCE = range(6)
+
+
+def rng_for(base: int, stream: int, batch: int = 0) -> np.random.Generator:
+    return np.random.Generator(np.random.PCG64(np.random.SeedSequence([base, stream, batch])))
+
+
+def workload_base(workload_id: int) -> int:
+    return 0x50490000 + 16 * workload_id
+
+
+def unique_uniform_keys(n: int, rng: np.random.Generator, hi: int = KEY_SPACE) -> np.ndarray:
+    """n distinct uint64 keys uniform in [0, hi), in random order."""
+    keys = np.zeros(0, dtype=np.uint64)
+    while keys.size < n:
+        need = n - keys.size
+        draw = rng.integers(0, hi, size=need + need // 64 + 16, dtype=np.uint64)
+        keys = np.unique(np.concatenate([keys, draw]))
+    if keys.size > n:
+        keys = rng.choice(keys, size=n, replace=False)
+    return rng.permutation(keys)
+
+
+def uniform_values(n: int, rng: np.random.Generator) -> np.ndarray:
+    return rng.integers(0, np.iinfo(np.uint64).max, size=n, dtype=np.uint64, endpoint=True)
+
+
+class Zipf:
+    """Zipf(theta) over ranks 0..n-1, P(r) proportional to (r+1)^-theta,
+    sampled exactly by inverse CDF on a float64 cumulative table."""
+
+    def __init__(self, n: int, theta: float):
+        self.n = int(n)
+        self.theta = float(theta)
+        w = np.arange(1, self.n + 1, dtype=np.float64) ** (-self.theta)
+        self.cdf = np.cumsum(w)
+        self.cdf /= self.cdf[-1]
+
+    def pmf(self, r):
+        r = np.asarray(r)
+        prev = np.where(r > 0, self.cdf[np.maximum(r - 1, 0)], 0.0)
+        return self.cdf[r] - prev
+
+    def sample(self, size: int, rng: np.random.Generator) -> np.ndarray:
+        u = rng.random(size)
+        r = np.searchsorted(self.cdf, u, side="right")
+        return np.minimum(r, self.n - 1).astype(np.int64)
+
+
+def draw_ops(n: int, mix, rng: np.random.Generator) -> np.ndarray:
+    """iid ops with probabilities mix = (p_search, p_insert, p_delete)."""
+    p = np.asarray(mix, dtype=np.float64)
+    p = p / p.sum()
+    return rng.choice(np.array([SEARCH, INSERT, DELETE], dtype=np.uint8), size=n, p=p)
+
+
+@dataclass
+class Batch:
+    ops: np.ndarray
+    keys: np.ndarray
+    vals: np.ndarray
+
+    def __len__(self):
+        return int(self.ops.size)
+
+
+@dataclass
+class Workload:
+    name: str
+    load_keys: np.ndarray
+    load_vals: np.ndarray
+    batches: List[Batch] = field(default_factory=list)
+    note: str = ""
+
+
+def mixed_uniform(workload_id: int, n_load: int, n_query: int, n_batches: int = 1,
+                  mix=(0.8, 0.1, 0.1), p_loaded: float = 0.5, name: str = "mixed-uniform") -> Workload:
+    """Load n_load distinct uniform keys; batches of iid ops with the given
+    mix; each query key is, with probability p_loaded, a uniformly chosen
+    loaded key and otherwise a fresh uniform key in [0, 2^63)."""
+    base = workload_base(workload_id)
+    lk = unique_uniform_keys(n_load, rng_for(base, ST_LOAD))
+    lv = uniform_values(n_load, rng_for(base, ST_VALS, 1 << 20))
+    batches = []
+    for b in range(n_batches):
+        ops = draw_ops(n_query, mix, rng_for(base, ST_OPS, b))
+        src = rng_for(base, ST_SOURCE, b).random(n_query) < p_loaded
+        rq = rng_for(base, ST_QKEYS, b)
+        fresh = rq.integers(0, KEY_SPACE, size=n_query, dtype=np.uint64)
+        pick = lk[rq.integers(0, max(n_load, 1), size=n_query)] if n_load else fresh
+        keys = np.where(src, pick, fresh).astype(np.uint64)
+        vals = uniform_values(n_query, rng_for(base, ST_VALS, b))
+        batches.append(Batch(ops, keys, vals))
+    return Workload(name, lk, lv, batches,
+                    note=f"load {n_load} uniform keys; {n_batches} x {n_query} queries, mix {mix}, "
+                         f"{p_loaded:.0%} of keys drawn from the loaded set")
+
+
+def search_only(workload_id: int, n_load: int, n_query: int, n_batches: int,
+                theta: Optional[float] = None, name: str = "search") -> Workload:
+    """All-SEARCH batches; keys uniform over the loaded keys (theta None) or
+    Zipf(theta) over them (rank r -> the r-th loaded key, which is a seeded
+    random permutation of the key space)."""
+    base = workload_base(workload_id)
+    lk = unique_uniform_keys(n_load, rng_for(base, ST_LOAD))
+    lv = uniform_values(n_load, rng_for(base, ST_VALS, 1 << 20))
+    z = Zipf(n_load, theta) if theta else None
+    batches = []
+    for b in range(n_batches):
+        rq = rng_for(base, ST_QKEYS, b)
+        idx = z.sample(n_query, rq) if z is not None else rq.integers(0, n_load, size=n_query)
+        keys = lk[idx]
+        batches.append(Batch(np.zeros(n_query, dtype=np.uint8), keys, np.zeros(n_query, dtype=np.uint64)))
+    dist = f"Zipf theta={theta}" if theta else "uniform"
+    return Workload(name, lk, lv, batches,
+                    note=f"load {n_load} uniform keys; {n_batches} x {n_query} SEARCH, keys {dist} over loaded keys")
+
+
+def write_heavy(workload_id: int, n_load: int, n_query: int, n_batches: int,
+                theta: float = 0.99, mix=(0.4, 0.5, 0.1), name: str = "write-heavy") -> Workload:
+    """INSERT keys are fresh uniform keys; SEARCH and DELETE keys are
+    Zipf(theta) over the originally loaded keys."""
+    base = workload_base(workload_id)
+    lk = unique_uniform_keys(n_load, rng_for(base, ST_LOAD))
+    lv = uniform_values(n_load, rng_for(base, ST_VALS, 1 << 20))
+    z = Zipf(n_load, theta)
+    batches = []
+    for b in range(n_batches):
+        ops = draw_ops(n_query, mix, rng_for(base, ST_OPS, b))
+        rq = rng_for(base, ST_QKEYS, b)
+        fresh = rq.integers(0, KEY_SPACE, size=n_query, dtype=np.uint64)
+        hot = lk[z.sample(n_query, rq)]
+        keys = np.where(ops == INSERT, fresh, hot).astype(np.uint64)
+        vals = uniform_values(n_query, rng_for(base, ST_VALS, b))
+        batches.append(Batch(ops, keys, vals))
+    return Workload(name, lk, lv, batches,
+                    note=f"load {n_load} uniform keys; {n_batches} x {n_query} queries mix {mix} "
+                         f"(S/I/D), inserts fresh uniform, others Zipf theta={theta}")
+
+
+# --- the named workloads -----------------------------------------------------
+
+def plain_pi(scale: int = 20) -> Workload:
+    """2^scale loaded keys, one batch of 2^scale queries, 80/10/10, half of the
+    query keys drawn from the loaded set (full size: scale 20)."""
+    return mixed_uniform(1, 1 << scale, 1 << scale, 1, (0.8, 0.1, 0.1), 0.5, name=f"plain-pi-2^{scale}")
+
+
+def read_scaling(theta: Optional[float] = None, load_log2: int = 24, query_log2: int = 22,
+                 n_batches: int = 32) -> Workload:
+    return search_only(2, 1 << load_log2, 1 << query_log2, n_batches, theta,
+                       name=f"search-2^{load_log2}-{'zipf' + str(theta) if theta else 'uniform'}")
+
+
+def write_skew(load_log2: int = 26, query_log2: int = 22, n_batches: int = 16) -> Workload:
+    return write_heavy(3, 1 << load_log2, 1 << query_log2, n_batches, 0.99, (0.4, 0.5, 0.1),
+                       name=f"write-skew-2^{load_log2}")
+
+
+def headline(theta: Optional[float] = None, load_log2: int = 26, query_log2: int = 22,
+             n_batches: int = 32) -> Workload:
+    """64M-key search workload: 2^26 loaded keys, batches of 2^22 SEARCH."""
+    return search_only(6, 1 << load_log2, 1 << query_log2, n_batches, theta,
+                       name=f"search-2^{load_log2}-{'zipf' + str(theta) if theta else 'uniform'}")
