@@ -1,0 +1,199 @@
+#!/usr/bin/env python3
+"""Throughput of the batched skip-list index on one MI355X.
+
+Workload (default): 2^26 distinct uniform uint64 keys bulk-loaded; batches of
+2^22 SEARCH queries with keys uniform over the loaded keys (Zipf(theta) with
+--theta).  A step is one pi_execute_batch: ordering, descent, ownership,
+apply, counters -- the whole hot path -- over one batch already resident in
+HBM.  Prints one JSON line.
+
+    python bench.py [--steps K] [--warmup W] [--theta 0.99] [--no-cpu-baseline]
+"""
+import argparse
+import hashlib
+import json
+import os
+import platform
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, GB/s
+METRIC = "Mqueries/s at 64M uint64 keys + % HBM peak; p50/p99 batch latency"
+
+
+def log(*a):
+    print("[bench]", *a, file=sys.stderr, flush=True)
+
+
+def kernel_source_hash():
+    h = hashlib.sha256()
+    for f in ("batch.hip", "pi_internal.h"):
+        with open(os.path.join(ROOT, "paper_1601_00159_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def load_traffic(workload_name):
+    """HBM bytes per descent launch from the committed rocprofv3 counter
+    summary, or None when the kernel has changed since it was taken."""
+    p = os.path.join(ROOT, "profiles", "descend_traffic.json")
+    if not os.path.exists(p):
+        return None
+    with open(p) as f:
+        d = json.load(f)
+    if d.get("kernel_hash") != kernel_source_hash() or d.get("workload") != workload_name:
+        return None
+    return d.get("bytes_per_launch")
+
+
+def cpu_baseline(w, sample_queries, budget_s=12.0):
+    """The CPU oracle (single-threaded Pugh skip list) on a bounded sample of
+    the same workload: the full index, the first `sample_queries` queries of
+    the first timed batch, in chunks until `budget_s` seconds of work."""
+    import numpy as np
+
+    from oracle.skiplist import SkipList
+
+    t0 = time.perf_counter()
+    sk = np.sort(w.load_keys)
+    order = np.argsort(w.load_keys, kind="stable")
+    sv = w.load_vals[order]
+    orc = SkipList()
+    orc.bulk_load_sorted(sk, sv)
+    log(f"oracle built in {time.perf_counter() - t0:.1f}s")
+    b = w.batches[0]
+    done, elapsed = 0, 0.0
+    chunk = 1 << 18
+    while done < min(sample_queries, len(b)) and elapsed < budget_s:
+        s = slice(done, done + chunk)
+        t = time.perf_counter()
+        orc.execute_batch(b.ops[s], b.keys[s], b.vals[s])
+        elapsed += time.perf_counter() - t
+        done += b.ops[s].size
+    orc.close()
+    return {"value": done / elapsed / 1e6, "unit": "Mqueries/s", "cores": 1, "kind": "oracle",
+            "sample": f"{done} SEARCH queries of one batch against the full {w.load_keys.size}-key index "
+                      f"(single-threaded Pugh skip list, {elapsed:.1f}s timed; host {platform.processor() or platform.machine()}, "
+                      f"{os.cpu_count()} logical CPUs)"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=32)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--theta", type=float, default=None)
+    ap.add_argument("--load-log2", type=int, default=26)
+    ap.add_argument("--batch-log2", type=int, default=22)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-bytemodel", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the index shards by key range "
+              "across GPUs, which this build does not run.", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    from paper_1601_00159_amd import bytemodel
+    from paper_1601_00159_amd import workloads as W
+    from paper_1601_00159_amd.index import Index, to_device_u64, to_device_u8
+
+    assert torch.cuda.is_available(), "bench needs a GPU"
+    dev = torch.device("cuda", 0)
+    K, WU = args.steps, args.warmup
+    t0 = time.perf_counter()
+    w = W.headline(args.theta, args.load_log2, args.batch_log2, n_batches=K + WU)
+    log(f"workload {w.name}: {w.note}; generated in {time.perf_counter() - t0:.1f}s")
+    Q = 1 << args.batch_log2
+
+    d_ops = [to_device_u8(b.ops, dev) for b in w.batches]
+    d_keys = [to_device_u64(b.keys, dev) for b in w.batches]
+    d_vals = [to_device_u64(b.vals, dev) for b in w.batches]
+    out_v = torch.empty(Q, dtype=torch.int64, device=dev)
+    out_s = torch.empty(Q, dtype=torch.uint8, device=dev)
+
+    ix = Index(device=0, profile=1)
+    t0 = time.perf_counter()
+    ix.bulk_load(w.load_keys, w.load_vals)
+    torch.cuda.synchronize()
+    load_s = time.perf_counter() - t0
+    st = ix.stats()
+    log(f"bulk load of {st['live_nodes']} keys: {load_s:.2f}s; levels 2..{st['n_levels']}, LDS from {st['lds_from']}")
+
+    for i in range(WU):
+        ix.execute_raw(d_ops[i], d_keys[i], d_vals[i], out_v, out_s)
+    torch.cuda.synchronize()
+    ix.profile(reset=True)
+
+    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(K)]
+    start, end = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    wall0 = time.perf_counter()
+    start.record()
+    for i in range(K):
+        j = WU + i
+        evs[i][0].record()
+        ix.execute_raw(d_ops[j], d_keys[j], d_vals[j], out_v, out_s)
+        evs[i][1].record()
+    end.record()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - wall0
+    total_ms = start.elapsed_time(end)
+    lat = np.array([a.elapsed_time(b) for a, b in evs])
+    prof = ix.profile(reset=True)
+    log(f"timed {K} batches: {total_ms:.2f} ms on the GPU clock, {wall * 1e3:.2f} ms wall")
+
+    # answers of the last timed batch against the loaded map (cheap check)
+    last = w.batches[WU + K - 1]
+    sorted_keys = np.sort(w.load_keys)
+    pos = np.searchsorted(sorted_keys, last.keys)
+    hit_ok = bool((out_s.cpu().numpy() == 1).all())
+    ord_ = np.argsort(w.load_keys, kind="stable")
+    want_v = w.load_vals[ord_][pos]
+    val_ok = bool(np.array_equal(out_v.cpu().numpy().view(np.uint64), want_v))
+    log(f"last batch answers: all present={hit_ok}, values match={val_ok}")
+
+    value = K * Q / (total_ms / 1e3) / 1e6
+    desc_ms = prof["descend_ms"] / max(prof["batches"], 1)
+    roof = None
+    if not args.no_bytemodel:
+        t0 = time.perf_counter()
+        bm = bytemodel.descent_bytes(sorted_keys, np.sort(w.batches[WU].keys), lds_from=st["lds_from"])
+        log(f"byte model: {bm['per_query']:.1f} B/query ({time.perf_counter() - t0:.1f}s)")
+        achieved = bm["bytes"] / (desc_ms / 1e3) / 1e9
+        traffic = load_traffic(w.name)
+        roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
+                "kernel": "k_descend", "kernel_ms": round(desc_ms, 4),
+                "algorithmic_bytes_per_launch": bm["bytes"], "bytes_per_query": round(bm["per_query"], 2)}
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        cpu = cpu_baseline(w, sample_queries=Q)
+
+    line = {
+        "metric": METRIC, "value": round(value, 2), "unit": "Mqueries/s", "n_gpus": 1, "steps": K,
+        "warmup": WU, "ms_per_step": round(total_ms / K, 4), "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "u64", "data": "synthetic",
+        "config": {"workload": w.name, "loaded_keys": int(w.load_keys.size), "batch_queries": Q,
+                   "op_mix": "100% SEARCH", "key_distribution": f"zipf {args.theta}" if args.theta else "uniform",
+                   "parallelism": "single GPU"},
+        "latency_ms": {"p50": round(float(np.percentile(lat, 50)), 4),
+                       "p99": round(float(np.percentile(lat, 99)), 4)},
+        "stages_ms_per_batch": {k: round(prof[k] / max(prof["batches"], 1), 4)
+                                for k in ("sort_ms", "descend_ms", "own_ms", "link_ms")},
+        "correct_last_batch": hit_ok and val_ok,
+        "roofline": roof,
+        "cpu_baseline": cpu,
+    }
+    ix.close()
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

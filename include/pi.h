@@ -1,0 +1,207 @@
+/*
+ * pi.h -- C ABI of the MI355X (gfx950) batched skip-list index.
+ *
+ * The index is the structure of "PI: a Parallel in-memory skip list based
+ * Index" (Xie, Cai, Jagadish, Ooi, Wong): a storage layer (a key-ordered list
+ * of data nodes, Definition 1) under an index layer (levels >= 2, each a
+ * contiguous sorted key array, Section 3.1 and Section 4.1).  A batch of
+ * search / insert / delete queries (Definition 2) is answered by the steps of
+ * Algorithm 1: order the batch by key (Definition 3), descend the index layer
+ * level by level for every query (Algorithm 2) to its interception
+ * (Definition 4), give every storage node that will change exactly one owner
+ * (the purpose of Algorithm 3), apply the changes without latches
+ * (Algorithm 4, Section 3.2.4), and rebuild the index layer once enough
+ * updates have accumulated (Section 4.1 and Section 4.3.5).
+ *
+ * Results are exactly those of applying the batch's queries one by one in
+ * arrival order:
+ *   SEARCH k    -> (PI_R_PRESENT, value of k) if k is present, else (PI_R_ABSENT, 0)
+ *   INSERT k v  -> the same answer, then k maps to v
+ *   DELETE k    -> the same answer, then k is absent
+ *   op not in {0,1,2} or k == UINT64_MAX -> (PI_R_INVALID, 0), no effect
+ * (the answers of INSERT and DELETE -- previous value if the key was live --
+ * are this library's reading; the paper returns 1/null for delete.)
+ *
+ * Memory and streams.  Every pointer named d_* is DEVICE memory on the
+ * index's device, owned by the caller; it must stay valid until the work
+ * enqueued on the given stream has completed.  Inputs are only read.  All
+ * device work is enqueued on the stream argument (a hipStream_t; NULL is the
+ * null stream); calls that return host values synchronise that stream and say
+ * so.  The library owns, allocates (hipMalloc) and frees its own device
+ * memory.  A handle is not thread-safe: calls on one handle must be ordered by
+ * the caller.
+ *
+ * Errors.  Every entry point returns a pi_status.  Argument and capacity
+ * errors are detected on the host before anything is enqueued and leave the
+ * index unchanged.  A failing HIP call marks the handle failed: every later
+ * call returns PI_ERR_DEVICE.  pi_last_error() describes the last error.
+ */
+#ifndef PI_H
+#define PI_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct pi_index pi_index; /* opaque; owns all device state */
+typedef int32_t pi_status;
+typedef void *pi_stream; /* a hipStream_t */
+
+enum {
+    PI_OK = 0,
+    PI_ERR_INVALID_ARG = -1,
+    PI_ERR_OUT_OF_MEMORY = -2,
+    PI_ERR_STATE = -3,
+    PI_ERR_DEVICE = -4,
+    PI_ERR_CAPACITY = -5
+};
+
+/* query type t of Definition 2 */
+enum { PI_OP_SEARCH = 0, PI_OP_INSERT = 1, PI_OP_DELETE = 2 };
+
+/* per-query answer status */
+enum { PI_R_ABSENT = 0, PI_R_PRESENT = 1, PI_R_INVALID = 255 };
+
+/* Rebuild policies for the index layer (Section 4.3.5: rebuilt once the
+ * number of insertions and deletions passes a threshold). */
+enum {
+    PI_REBUILD_THRESHOLD = 0, /* rebuild when changes >= fraction * live nodes */
+    PI_REBUILD_NEVER = 1,     /* only pi_repair() rebuilds */
+    PI_REBUILD_ALWAYS = 2     /* rebuild after every batch that changed the structure */
+};
+
+typedef struct {
+    uint32_t struct_size;     /* sizeof(pi_config) */
+    int32_t device;           /* HIP device ordinal */
+    uint32_t max_height;      /* cap on tower heights, 2..32 (default 24) */
+    uint32_t log2_inv_p;      /* promotion probability p = 2^-log2_inv_p, 1..8 (default 1) */
+    uint64_t height_seed;     /* seed of the height rule (default 0x9E3779B97F4A7C15) */
+    float rebuild_fraction;   /* threshold as a fraction of live nodes (default 0.15) */
+    uint32_t rebuild_policy;  /* PI_REBUILD_* (default PI_REBUILD_THRESHOLD) */
+    uint64_t capacity_hint;   /* fixed storage capacity in nodes, counting the head and tail
+                                 sentinels; 0 = grow on demand */
+    uint32_t lds_levels;      /* index levels kept in LDS by the descent: 0 = auto */
+    uint32_t profile;         /* 1 = time every stage with HIP events (pi_get_profile) */
+    uint32_t reserved[6];
+} pi_config;
+
+/* Accumulated device time per stage of pi_execute_batch (profile = 1). */
+typedef struct {
+    uint64_t batches;         /* batches timed since the last reset */
+    uint64_t rebuilds;        /* rebuilds timed since the last reset */
+    double sort_ms;           /* ordering of the batch by key */
+    double descend_ms;        /* index descent + storage walk (answers of read-only batches) */
+    double own_ms;            /* ownership scan, answers, in-place updates */
+    double link_ms;           /* allocation and linking of new nodes, counters */
+    double rebuild_ms;        /* index-layer rebuilds */
+} pi_profile;
+
+typedef struct {
+    uint64_t batches;         /* batches executed */
+    uint64_t queries;         /* queries executed */
+    uint64_t hits;            /* answers with status PRESENT */
+    uint64_t invalid;         /* answers with status INVALID */
+    uint64_t new_nodes;       /* storage nodes created by inserts */
+    uint64_t deletes;         /* live -> deleted transitions */
+    uint64_t revives;         /* deleted -> live transitions (insert on a flagged node) */
+    uint64_t changes;         /* new nodes + live->deleted since the last rebuild */
+    uint64_t repairs;         /* index-layer rebuilds */
+    uint64_t live_nodes;      /* keys currently present */
+    uint64_t base_nodes;      /* nodes in the sorted base region */
+    uint64_t overflow_nodes;  /* nodes appended since the last rebuild */
+    uint64_t capacity;        /* storage node capacity */
+    uint32_t n_levels;        /* highest non-empty level (1 = no index levels) */
+    uint32_t lds_from;        /* lowest level kept in LDS by the descent */
+    uint64_t level_size[33];  /* keys on level l, l = 2..32 */
+} pi_stats;
+
+/* Fills *cfg with the defaults listed above. */
+pi_status pi_config_default(pi_config *cfg);
+
+/* Creates an empty index on cfg->device (cfg NULL = defaults).  On success
+ * *out receives the handle.  Errors: PI_ERR_INVALID_ARG (bad field or NULL
+ * out), PI_ERR_DEVICE, PI_ERR_OUT_OF_MEMORY. */
+pi_status pi_create(const pi_config *cfg, pi_index **out);
+
+/* Frees every resource of the index (synchronises its device).  NULL is a
+ * no-op. */
+pi_status pi_destroy(pi_index *idx);
+
+/* Bottom-up construction of an EMPTY index (Section 3.1: one scan of the
+ * ordered data fills every index level).  d_keys/d_values: n pairs in device
+ * memory, any order; a duplicated key keeps its LAST value (as if the pairs
+ * were inserted in order); pairs whose key is UINT64_MAX are skipped.
+ * Synchronises the stream.  Errors: PI_ERR_STATE if the index is not empty,
+ * PI_ERR_INVALID_ARG (NULL with n > 0, n >= 2^31), PI_ERR_OUT_OF_MEMORY. */
+pi_status pi_bulk_load(pi_index *idx, const uint64_t *d_keys, const uint64_t *d_values,
+                       uint64_t n, pi_stream stream);
+
+/* Answers a batch of n queries (Algorithm 1) and applies its updates.
+ * d_ops u8[n] (PI_OP_*), d_keys u64[n], d_values u64[n] (read only for
+ * INSERT queries, but always required), arrival order.
+ * d_out_values u64[n], d_out_status u8[n] receive one answer per query in
+ * arrival order.  Work is enqueued on the stream; the call does not wait for
+ * it except when the storage must grow or the index layer is rebuilt (then it
+ * synchronises).  n = 0 is a no-op.  Errors: PI_ERR_INVALID_ARG (NULL
+ * pointers with n > 0, n >= 2^31), PI_ERR_CAPACITY (capacity_hint fixed and
+ * too small for the worst case of this batch; nothing enqueued),
+ * PI_ERR_OUT_OF_MEMORY, PI_ERR_DEVICE. */
+pi_status pi_execute_batch(pi_index *idx, const uint8_t *d_ops, const uint64_t *d_keys,
+                           const uint64_t *d_values, uint64_t n, uint64_t *d_out_values,
+                           uint8_t *d_out_status, pi_stream stream);
+
+/* Rebuilds the storage base region and every index level now, whatever the
+ * policy (Section 4.1: rebuild from the storage layer, bottom-up, drop
+ * deleted nodes).  Synchronises the stream. */
+pi_status pi_repair(pi_index *idx, pi_stream stream);
+
+/* Writes the live (key, value) pairs in increasing key order into
+ * d_keys/d_values (capacity cap pairs) and their number into *n_out (host).
+ * Does not change the index.  Synchronises the stream.  Errors:
+ * PI_ERR_CAPACITY when cap is too small (*n_out still receives the count). */
+pi_status pi_export(pi_index *idx, uint64_t *d_keys, uint64_t *d_values, uint64_t cap,
+                    uint64_t *n_out, pi_stream stream);
+
+/* Copies the counters into *out (host).  Synchronises the index's device. */
+pi_status pi_get_stats(pi_index *idx, pi_stats *out);
+
+/* Copies the stage times accumulated since the last reset into *out (host)
+ * and, when reset is nonzero, clears them.  All zero unless the index was
+ * created with profile = 1.  Synchronises the index's device. */
+pi_status pi_get_profile(pi_index *idx, pi_profile *out, int32_t reset);
+
+/* Message of the last error on this handle ("" if none).  NULL handle gives
+ * the message of the last pi_create failure. */
+const char *pi_last_error(const pi_index *idx);
+
+/* ---- inspection entry points used by the parity tests ------------------- */
+
+/* Interception of every key (Definition 4) on the CURRENT index layer: the
+ * largest key <= d_keys[i] among the keys of height > 1 that the index layer
+ * holds.  d_icpt_keys u64[n] receives that key, d_is_head u8[n] receives 1
+ * when there is none (the head of the list) and 0 otherwise. */
+pi_status pi_debug_interceptions(pi_index *idx, const uint64_t *d_keys, uint64_t n,
+                                 uint64_t *d_icpt_keys, uint8_t *d_is_head, pi_stream stream);
+
+/* Copies level `level` (2..max_height) of the index layer: its keys in order
+ * into d_keys (u64) and, for every key, the position of the same key on the
+ * level below (level 2: the storage slot) into d_down (u32).  *n_out (host)
+ * receives the number of keys.  Synchronises.  PI_ERR_CAPACITY if cap is too
+ * small. */
+pi_status pi_debug_level(pi_index *idx, uint32_t level, uint64_t *d_keys, uint32_t *d_down,
+                         uint64_t cap, uint64_t *n_out, pi_stream stream);
+
+/* Stable sort of n keys by value, as the batch's ordering step does it
+ * (Definition 3; equal keys keep input order): d_sorted_keys u64[n] and
+ * d_perm u32[n] (input position of each output).  Uses the index's
+ * workspace. */
+pi_status pi_debug_sort(pi_index *idx, const uint64_t *d_keys, uint64_t n,
+                        uint64_t *d_sorted_keys, uint32_t *d_perm, pi_stream stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* PI_H */

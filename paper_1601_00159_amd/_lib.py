@@ -1,0 +1,103 @@
+"""ctypes binding of libpi (include/pi.h): same names, argument marshalling
+only.  Every computation runs in the HIP kernels of libpi.so; there is no
+other code path, and importing this module fails if the library was not
+built."""
+import ctypes
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libpi.so")
+
+PI_OK = 0
+PI_ERR_INVALID_ARG = -1
+PI_ERR_OUT_OF_MEMORY = -2
+PI_ERR_STATE = -3
+PI_ERR_DEVICE = -4
+PI_ERR_CAPACITY = -5
+
+PI_OP_SEARCH, PI_OP_INSERT, PI_OP_DELETE = 0, 1, 2
+PI_R_ABSENT, PI_R_PRESENT, PI_R_INVALID = 0, 1, 255
+PI_REBUILD_THRESHOLD, PI_REBUILD_NEVER, PI_REBUILD_ALWAYS = 0, 1, 2
+
+STATUS_NAMES = {PI_OK: "PI_OK", PI_ERR_INVALID_ARG: "PI_ERR_INVALID_ARG",
+                PI_ERR_OUT_OF_MEMORY: "PI_ERR_OUT_OF_MEMORY", PI_ERR_STATE: "PI_ERR_STATE",
+                PI_ERR_DEVICE: "PI_ERR_DEVICE", PI_ERR_CAPACITY: "PI_ERR_CAPACITY"}
+
+
+class pi_config(ctypes.Structure):
+    _fields_ = [("struct_size", ctypes.c_uint32), ("device", ctypes.c_int32),
+                ("max_height", ctypes.c_uint32), ("log2_inv_p", ctypes.c_uint32),
+                ("height_seed", ctypes.c_uint64), ("rebuild_fraction", ctypes.c_float),
+                ("rebuild_policy", ctypes.c_uint32), ("capacity_hint", ctypes.c_uint64),
+                ("lds_levels", ctypes.c_uint32), ("profile", ctypes.c_uint32),
+                ("reserved", ctypes.c_uint32 * 6)]
+
+
+class pi_profile(ctypes.Structure):
+    _fields_ = [("batches", ctypes.c_uint64), ("rebuilds", ctypes.c_uint64),
+                ("sort_ms", ctypes.c_double), ("descend_ms", ctypes.c_double),
+                ("own_ms", ctypes.c_double), ("link_ms", ctypes.c_double),
+                ("rebuild_ms", ctypes.c_double)]
+
+
+class pi_stats(ctypes.Structure):
+    _fields_ = [(n, ctypes.c_uint64) for n in (
+        "batches", "queries", "hits", "invalid", "new_nodes", "deletes", "revives", "changes",
+        "repairs", "live_nodes", "base_nodes", "overflow_nodes", "capacity")] + [
+        ("n_levels", ctypes.c_uint32), ("lds_from", ctypes.c_uint32),
+        ("level_size", ctypes.c_uint64 * 33)]
+
+
+EXPORTED = ["pi_config_default", "pi_create", "pi_destroy", "pi_bulk_load", "pi_execute_batch",
+            "pi_repair", "pi_export", "pi_get_stats", "pi_get_profile", "pi_last_error", "pi_debug_interceptions",
+            "pi_debug_level", "pi_debug_sort"]
+
+
+class PiError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"{STATUS_NAMES.get(status, status)}: {msg}")
+        self.status = status
+
+
+def load(path: str = LIB_PATH):
+    if not os.path.exists(path):
+        raise RuntimeError(f"libpi.so not built ({path}); run __graft_entry__.build()")
+    lib = ctypes.CDLL(path)
+    vp, u64, u32, i32 = ctypes.c_void_p, ctypes.c_uint64, ctypes.c_uint32, ctypes.c_int32
+    sig = {
+        "pi_config_default": ([ctypes.POINTER(pi_config)], i32),
+        "pi_create": ([ctypes.POINTER(pi_config), ctypes.POINTER(vp)], i32),
+        "pi_destroy": ([vp], i32),
+        "pi_bulk_load": ([vp, vp, vp, u64, vp], i32),
+        "pi_execute_batch": ([vp, vp, vp, vp, u64, vp, vp, vp], i32),
+        "pi_repair": ([vp, vp], i32),
+        "pi_export": ([vp, vp, vp, u64, ctypes.POINTER(u64), vp], i32),
+        "pi_get_stats": ([vp, ctypes.POINTER(pi_stats)], i32),
+        "pi_get_profile": ([vp, ctypes.POINTER(pi_profile), i32], i32),
+        "pi_last_error": ([vp], ctypes.c_char_p),
+        "pi_debug_interceptions": ([vp, vp, u64, vp, vp, vp], i32),
+        "pi_debug_level": ([vp, u32, vp, vp, u64, ctypes.POINTER(u64), vp], i32),
+        "pi_debug_sort": ([vp, vp, u64, vp, vp, vp], i32),
+    }
+    for name, (args, res) in sig.items():
+        f = getattr(lib, name)
+        f.argtypes = args
+        f.restype = res
+    return lib
+
+
+_LIB = None
+
+
+def lib():
+    global _LIB
+    if _LIB is None:
+        _LIB = load()
+    return _LIB
+
+
+def check(status, handle=None):
+    if status != PI_OK:
+        msg = lib().pi_last_error(handle)
+        raise PiError(status, msg.decode() if msg else "")
+    return status

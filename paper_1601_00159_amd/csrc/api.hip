@@ -1,0 +1,382 @@
+// C ABI of libpi (declared in include/pi.h): argument checks, device
+// selection, storage capacity, the rebuild policy and error reporting.
+#include <algorithm>
+#include <cstring>
+#include <mutex>
+#include <string>
+
+#include "index.h"
+
+struct pi_index {
+    pi::Index ix;
+};
+
+namespace pi {
+
+void DevBuf::ensure(size_t need) {
+    if (need <= bytes && p) return;
+    if (p) {
+        PI_HIP(hipFree(p));
+        p = nullptr;
+        bytes = 0;
+    }
+    const size_t b = std::max<size_t>(need, 256);
+    void *q = nullptr;
+    hipError_t e = hipMalloc(&q, b);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        throw Error{PI_ERR_OUT_OF_MEMORY, "hipMalloc of " + std::to_string(b) + " bytes failed"};
+    }
+    p = q;
+    bytes = b;
+}
+
+void DevBuf::release() {
+    if (p) (void)hipFree(p);
+    p = nullptr;
+    bytes = 0;
+}
+
+}  // namespace pi
+
+namespace {
+
+std::mutex g_create_err_mu;
+std::string g_create_err;
+
+constexpr uint64_t MAX_BATCH = (1ull << 31) - 1;
+
+struct DeviceGuard {
+    int prev = -1;
+    explicit DeviceGuard(int dev) {
+        if (hipGetDevice(&prev) != hipSuccess) prev = -1;
+        if (prev != dev) PI_HIP(hipSetDevice(dev));
+    }
+    ~DeviceGuard() {
+        int cur = -1;
+        if (prev >= 0 && hipGetDevice(&cur) == hipSuccess && cur != prev) (void)hipSetDevice(prev);
+    }
+};
+
+template <class F>
+pi_status guarded(pi_index *h, F &&f) {
+    if (!h) return PI_ERR_INVALID_ARG;
+    pi::Index &ix = h->ix;
+    if (ix.failed) return PI_ERR_DEVICE;
+    try {
+        DeviceGuard g(ix.device);
+        pi_status r = f(ix);
+        if (r == PI_OK) ix.err.clear();
+        return r;
+    } catch (const pi::Error &e) {
+        ix.err = e.msg;
+        if (e.code == PI_ERR_DEVICE) ix.failed = true;
+        return e.code;
+    } catch (const std::exception &e) {
+        ix.err = e.what();
+        ix.failed = true;
+        return PI_ERR_DEVICE;
+    }
+}
+
+pi_status fail(pi::Index &ix, pi_status code, const char *msg) {
+    ix.err = msg;
+    return code;
+}
+
+void release_all(pi::Index &ix) {
+    ix.st.release();
+    ix.arena_key.release();
+    ix.arena_down.release();
+    ix.sortws.release();
+    ix.scanws.release();
+    ix.bws.release();
+    for (auto &b : ix.tmp) b.release();
+    if (ix.dstate) (void)hipFree(ix.dstate);
+    if (ix.hstate) (void)hipHostFree(ix.hstate);
+    if (ix.hcounts) (void)hipHostFree(ix.hcounts);
+    if (ix.ev_state) (void)hipEventDestroy(ix.ev_state);
+    ix.prof.release();
+    ix.dstate = nullptr;
+    ix.hstate = nullptr;
+    ix.hcounts = nullptr;
+    ix.ev_state = nullptr;
+}
+
+// Rebuild decision from the last counters the host has (never waits).
+void maybe_rebuild(pi::Index &ix, hipStream_t s) {
+    if (ix.cfg.rebuild_policy != PI_REBUILD_THRESHOLD || !ix.state_enqueued) return;
+    if (hipEventQuery(ix.ev_state) != hipSuccess) {
+        (void)hipGetLastError();
+        return;
+    }
+    const pi::DevState &h = *ix.hstate;
+    const double thr = std::max(1.0, (double)ix.cfg.rebuild_fraction * (double)std::max<uint64_t>(ix.live_at_rebuild, 1));
+    if ((double)h.changes >= thr) pi::rebuild(ix, s);
+}
+
+void ensure_capacity(pi::Index &ix, const uint8_t *ops, const uint64_t *keys, uint64_t n, hipStream_t s) {
+    if (ix.used_upper + n <= ix.st.cap) return;
+    pi::DevState cur;
+    pi::read_state(ix, s, &cur);  // refreshes used_upper
+    if (cur.nused + n <= ix.st.cap) return;
+    if (ix.cfg.capacity_hint) {
+        const uint64_t ins = pi::count_inserts(ix, ops, keys, n, s);
+        if (cur.nused + ins > ix.st.cap)
+            throw pi::Error{PI_ERR_CAPACITY, "batch may need " + std::to_string(ins) + " new nodes; " +
+                                                 std::to_string(ix.st.cap - cur.nused) + " slots free"};
+        return;
+    }
+    pi::grow_storage(ix, std::max<uint64_t>(cur.nused + n, ix.st.cap * 2), s);
+}
+
+}  // namespace
+
+extern "C" {
+
+pi_status pi_config_default(pi_config *cfg) {
+    if (!cfg) return PI_ERR_INVALID_ARG;
+    std::memset(cfg, 0, sizeof(*cfg));
+    cfg->struct_size = sizeof(pi_config);
+    cfg->device = 0;
+    cfg->max_height = 24;
+    cfg->log2_inv_p = 1;
+    cfg->height_seed = 0x9E3779B97F4A7C15ull;
+    cfg->rebuild_fraction = 0.15f;
+    cfg->rebuild_policy = PI_REBUILD_THRESHOLD;
+    cfg->capacity_hint = 0;
+    cfg->lds_levels = 0;
+    cfg->profile = 0;
+    return PI_OK;
+}
+
+pi_status pi_create(const pi_config *cfg_in, pi_index **out) {
+    auto set_err = [](const std::string &m) {
+        std::lock_guard<std::mutex> g(g_create_err_mu);
+        g_create_err = m;
+    };
+    if (!out) {
+        set_err("out is NULL");
+        return PI_ERR_INVALID_ARG;
+    }
+    *out = nullptr;
+    pi_config cfg;
+    pi_config_default(&cfg);
+    if (cfg_in) {
+        if (cfg_in->struct_size != sizeof(pi_config)) {
+            set_err("pi_config.struct_size mismatch");
+            return PI_ERR_INVALID_ARG;
+        }
+        cfg = *cfg_in;
+    }
+    if (cfg.max_height < 2 || cfg.max_height > 32 || cfg.log2_inv_p < 1 || cfg.log2_inv_p > 8 ||
+        !(cfg.rebuild_fraction >= 0.0f) || cfg.rebuild_policy > PI_REBUILD_ALWAYS ||
+        cfg.capacity_hint > (1ull << 32) - 16) {
+        set_err("invalid pi_config field");
+        return PI_ERR_INVALID_ARG;
+    }
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess || cfg.device < 0 || cfg.device >= ndev) {
+        (void)hipGetLastError();
+        set_err("no such HIP device");
+        return PI_ERR_INVALID_ARG;
+    }
+    pi_index *h = new (std::nothrow) pi_index;
+    if (!h) return PI_ERR_OUT_OF_MEMORY;
+    pi::Index &ix = h->ix;
+    ix.cfg = cfg;
+    ix.device = cfg.device;
+    ix.prof.on = cfg.profile != 0;
+    try {
+        DeviceGuard g(ix.device);
+        hipDeviceProp_t prop;
+        PI_HIP(hipGetDeviceProperties(&prop, ix.device));
+        ix.num_cus = prop.multiProcessorCount;
+        PI_HIP(hipMalloc(&ix.dstate, sizeof(pi::DevState)));
+        PI_HIP(hipHostMalloc(&ix.hstate, sizeof(pi::DevState), hipHostMallocDefault));
+        PI_HIP(hipHostMalloc(&ix.hcounts, 64 * sizeof(uint64_t), hipHostMallocDefault));
+        PI_HIP(hipEventCreateWithFlags(&ix.ev_state, hipEventDisableTiming));
+        std::memset(ix.hstate, 0, sizeof(pi::DevState));
+        const uint64_t cap = std::max<uint64_t>(cfg.capacity_hint ? cfg.capacity_hint : (1u << 16), 4);
+        ix.st.alloc(cap);
+        pi::init_empty(ix, nullptr);
+        PI_HIP(hipDeviceSynchronize());
+    } catch (const pi::Error &e) {
+        set_err(e.msg);
+        release_all(ix);
+        delete h;
+        return e.code;
+    }
+    *out = h;
+    return PI_OK;
+}
+
+pi_status pi_destroy(pi_index *h) {
+    if (!h) return PI_OK;
+    {
+        int prev = -1;
+        (void)hipGetDevice(&prev);
+        (void)hipSetDevice(h->ix.device);
+        (void)hipDeviceSynchronize();
+        release_all(h->ix);
+        if (prev >= 0) (void)hipSetDevice(prev);
+    }
+    delete h;
+    return PI_OK;
+}
+
+pi_status pi_bulk_load(pi_index *h, const uint64_t *d_keys, const uint64_t *d_values, uint64_t n, pi_stream stream) {
+    return guarded(h, [&](pi::Index &ix) -> pi_status {
+        if (n > MAX_BATCH) return fail(ix, PI_ERR_INVALID_ARG, "n too large");
+        if (n > 0 && (!d_keys || !d_values)) return fail(ix, PI_ERR_INVALID_ARG, "NULL input");
+        hipStream_t s = (hipStream_t)stream;
+        pi::DevState cur;
+        pi::read_state(ix, s, &cur);
+        if (cur.n_live != 0 || cur.nused != ix.nbase + 2 || ix.nbase != 0)
+            return fail(ix, PI_ERR_STATE, "bulk load needs an empty index");
+        pi::bulk_load(ix, d_keys, d_values, n, s);
+        ix.state_enqueued = false;
+        return PI_OK;
+    });
+}
+
+pi_status pi_execute_batch(pi_index *h, const uint8_t *d_ops, const uint64_t *d_keys, const uint64_t *d_values,
+                           uint64_t n, uint64_t *d_out_values, uint8_t *d_out_status, pi_stream stream) {
+    return guarded(h, [&](pi::Index &ix) -> pi_status {
+        if (n == 0) return PI_OK;
+        if (n > MAX_BATCH) return fail(ix, PI_ERR_INVALID_ARG, "n too large");
+        if (!d_ops || !d_keys || !d_values || !d_out_values || !d_out_status)
+            return fail(ix, PI_ERR_INVALID_ARG, "NULL pointer");
+        hipStream_t s = (hipStream_t)stream;
+        maybe_rebuild(ix, s);
+        ensure_capacity(ix, d_ops, d_keys, n, s);
+        pi::execute_batch(ix, d_ops, d_keys, d_values, n, d_out_values, d_out_status, s);
+        ix.used_upper = std::min<uint64_t>(ix.used_upper + n, ~0ull);
+        PI_HIP(hipMemcpyAsync(ix.hstate, ix.dstate, sizeof(pi::DevState), hipMemcpyDeviceToHost, s));
+        PI_HIP(hipEventRecord(ix.ev_state, s));
+        ix.state_enqueued = true;
+        if (ix.cfg.rebuild_policy == PI_REBUILD_ALWAYS) {
+            pi::DevState cur;
+            pi::read_state(ix, s, &cur);
+            if (cur.changes > 0) pi::rebuild(ix, s);
+        }
+        return PI_OK;
+    });
+}
+
+pi_status pi_repair(pi_index *h, pi_stream stream) {
+    return guarded(h, [&](pi::Index &ix) -> pi_status {
+        pi::rebuild(ix, (hipStream_t)stream);
+        ix.state_enqueued = false;
+        return PI_OK;
+    });
+}
+
+pi_status pi_export(pi_index *h, uint64_t *d_keys, uint64_t *d_values, uint64_t cap, uint64_t *n_out,
+                    pi_stream stream) {
+    return guarded(h, [&](pi::Index &ix) -> pi_status {
+        if (!n_out) return fail(ix, PI_ERR_INVALID_ARG, "n_out is NULL");
+        if (cap > 0 && (!d_keys || !d_values)) return fail(ix, PI_ERR_INVALID_ARG, "NULL output");
+        pi::DevState cur;
+        pi::read_state(ix, (hipStream_t)stream, &cur);
+        *n_out = cur.n_live;
+        if (cur.n_live > cap) return fail(ix, PI_ERR_CAPACITY, "export capacity too small");
+        *n_out = pi::export_live(ix, d_keys, d_values, cap, (hipStream_t)stream);
+        return PI_OK;
+    });
+}
+
+pi_status pi_get_stats(pi_index *h, pi_stats *out) {
+    return guarded(h, [&](pi::Index &ix) -> pi_status {
+        if (!out) return fail(ix, PI_ERR_INVALID_ARG, "out is NULL");
+        PI_HIP(hipDeviceSynchronize());
+        pi::DevState cur;
+        pi::read_state(ix, nullptr, &cur);
+        std::memset(out, 0, sizeof(*out));
+        out->batches = cur.batches;
+        out->queries = cur.queries;
+        out->hits = cur.hits;
+        out->invalid = cur.invalid;
+        out->new_nodes = cur.new_nodes;
+        out->deletes = cur.deletes;
+        out->revives = cur.revives;
+        out->changes = cur.changes;
+        out->repairs = ix.repairs;
+        out->live_nodes = cur.n_live;
+        out->base_nodes = ix.nbase;
+        out->overflow_nodes = cur.nused - (ix.nbase + 2);
+        out->capacity = ix.st.cap;
+        out->n_levels = (uint32_t)ix.desc.top;
+        out->lds_from = (uint32_t)ix.desc.lds_from;
+        for (int l = 2; l <= ix.desc.top && l < 33; l++) out->level_size[l] = ix.desc.n[l];
+        return PI_OK;
+    });
+}
+
+pi_status pi_get_profile(pi_index *h, pi_profile *out, int32_t reset) {
+    return guarded(h, [&](pi::Index &ix) -> pi_status {
+        if (!out) return fail(ix, PI_ERR_INVALID_ARG, "out is NULL");
+        PI_HIP(hipDeviceSynchronize());
+        ix.prof.drain(true);
+        *out = ix.prof.acc;
+        if (reset) ix.prof.acc = pi_profile{};
+        return PI_OK;
+    });
+}
+
+const char *pi_last_error(const pi_index *h) {
+    if (!h) {
+        std::lock_guard<std::mutex> g(g_create_err_mu);
+        return g_create_err.c_str();
+    }
+    return h->ix.err.c_str();
+}
+
+pi_status pi_debug_interceptions(pi_index *h, const uint64_t *d_keys, uint64_t n, uint64_t *d_icpt_keys,
+                                 uint8_t *d_is_head, pi_stream stream) {
+    return guarded(h, [&](pi::Index &ix) -> pi_status {
+        if (n == 0) return PI_OK;
+        if (n > MAX_BATCH) return fail(ix, PI_ERR_INVALID_ARG, "n too large");
+        if (!d_keys || !d_icpt_keys || !d_is_head) return fail(ix, PI_ERR_INVALID_ARG, "NULL pointer");
+        pi::debug_interceptions(ix, d_keys, n, d_icpt_keys, d_is_head, (hipStream_t)stream);
+        return PI_OK;
+    });
+}
+
+pi_status pi_debug_level(pi_index *h, uint32_t level, uint64_t *d_keys, uint32_t *d_down, uint64_t cap,
+                         uint64_t *n_out, pi_stream stream) {
+    return guarded(h, [&](pi::Index &ix) -> pi_status {
+        if (!n_out) return fail(ix, PI_ERR_INVALID_ARG, "n_out is NULL");
+        if (level < 2 || level > ix.cfg.max_height) return fail(ix, PI_ERR_INVALID_ARG, "bad level");
+        hipStream_t s = (hipStream_t)stream;
+        const uint64_t n = (int)level <= ix.desc.top ? ix.desc.n[level] : 0;
+        *n_out = n;
+        if (n > cap) return fail(ix, PI_ERR_CAPACITY, "level larger than cap");
+        if (n > 0) {
+            if (!d_keys || !d_down) return fail(ix, PI_ERR_INVALID_ARG, "NULL output");
+            const uint64_t o = ix.desc.off[level] + 1;
+            PI_HIP(hipMemcpyAsync(d_keys, ix.arena_key.as<uint64_t>() + o, n * 8, hipMemcpyDeviceToDevice, s));
+            PI_HIP(hipMemcpyAsync(d_down, ix.arena_down.as<uint32_t>() + o, n * 4, hipMemcpyDeviceToDevice, s));
+        }
+        PI_HIP(hipStreamSynchronize(s));
+        return PI_OK;
+    });
+}
+
+pi_status pi_debug_sort(pi_index *h, const uint64_t *d_keys, uint64_t n, uint64_t *d_sorted_keys, uint32_t *d_perm,
+                        pi_stream stream) {
+    return guarded(h, [&](pi::Index &ix) -> pi_status {
+        if (n == 0) return PI_OK;
+        if (n > MAX_BATCH) return fail(ix, PI_ERR_INVALID_ARG, "n too large");
+        if (!d_keys || !d_sorted_keys || !d_perm) return fail(ix, PI_ERR_INVALID_ARG, "NULL pointer");
+        hipStream_t s = (hipStream_t)stream;
+        const uint64_t *sk = nullptr;
+        const uint32_t *si = nullptr;
+        pi::sort_keys_with_index(ix.sortws, d_keys, nullptr, n, nullptr, s, &sk, &si);
+        PI_HIP(hipMemcpyAsync(d_sorted_keys, sk, n * 8, hipMemcpyDeviceToDevice, s));
+        PI_HIP(hipMemcpyAsync(d_perm, si, n * 4, hipMemcpyDeviceToDevice, s));
+        return PI_OK;
+    });
+}
+
+}  // extern "C"

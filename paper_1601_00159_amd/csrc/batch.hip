@@ -1,0 +1,614 @@
+// One batch of queries (Algorithm 1) on gfx950.
+//
+//   order      stable radix sort of the batch by key (Definition 3); invalid
+//              queries sort last with key +infinity
+//   descend    k_descend: every query walks the index layer from the top
+//              level down (Algorithm 2), level by level for the whole wave
+//              (group processing, Section 4.3.4), the upper levels read from
+//              an LDS copy, to its interception (Definition 4), then along the
+//              storage list to the node with the largest key <= its key
+//              (getNode of Algorithm 4).  For a batch without updates this
+//              kernel writes the final answers.
+//   ownership  queries with equal keys are adjacent and in arrival order; a
+//              segmented scan over the sorted batch gives each query the last
+//              INSERT/DELETE before it on the same key, hence its answer, and
+//              gives each key group one owner -- the group's last query --
+//              which alone writes that key's node.  This replaces the
+//              message-based hand-over of Algorithm 3: after it, no storage
+//              node has two writers (the invariant of Section 3.2.4).
+//   apply      owners update values and delete flags in place (Algorithm 4
+//              flags instead of unlinking); keys that end the batch live but
+//              have no node get one in a key-sorted run appended to the
+//              storage; new nodes sharing a predecessor are chained and only
+//              the first writes the predecessor's successor.  No atomics, no
+//              latches.
+//   rebuild    the index layer is not touched by updates; it is rebuilt from
+//              the storage layer when enough changes accumulate (Section 4.1,
+//              Section 4.3.5), by the host between batches.
+#include <algorithm>
+
+#include "index.h"
+
+namespace pi {
+namespace {
+
+constexpr int DT = 256;          // descent block
+constexpr int OT = 256;          // ownership block
+constexpr int OI = 4;            // items per thread (blocked)
+constexpr int OTILE = OT * OI;
+constexpr int ONW = OT / 64;
+constexpr uint32_t WALK_LIMIT = 1u << 24;  // bound on storage nodes walked by one query
+
+// ---------------------------------------------------------------- descent --
+
+// Walks the index layer for key q.  Returns the storage slot of the
+// interception (HEAD_SLOT if no indexed key is <= q) and its key.
+__device__ __forceinline__ uint32_t descend_index(uint64_t q, const IndexDesc &d, const uint64_t *__restrict__ lkey,
+                                                  const uint32_t *__restrict__ ldown, const uint64_t *s_k,
+                                                  const uint32_t *s_d, uint64_t &ikey) {
+    uint32_t pos = 0;  // head entry of the top level
+    uint64_t last = 0;
+    for (int l = d.top; l >= 2; l--) {
+        if (l >= d.lds_from) {
+            const uint64_t *K = s_k + d.lds_off[l];
+            const uint32_t *D = s_d + d.lds_off[l];
+            uint64_t kn = K[pos + 1];
+            while (kn <= q) {
+                pos++;
+                last = kn;
+                kn = K[pos + 1];
+            }
+            pos = D[pos];
+        } else {
+            const uint64_t *K = lkey + d.off[l];
+            const uint32_t *D = ldown + d.off[l];
+            uint64_t kn = K[pos + 1];
+            while (kn <= q) {
+                pos++;
+                last = kn;
+                kn = K[pos + 1];
+            }
+            pos = D[pos];
+        }
+    }
+    ikey = last;
+    return pos;
+}
+
+__device__ __forceinline__ void stage_levels(const IndexDesc &d, const uint64_t *__restrict__ lkey,
+                                             const uint32_t *__restrict__ ldown, uint64_t *s_k, uint32_t *s_d) {
+    for (int l = d.top; l >= d.lds_from && l >= 2; l--) {
+        const uint32_t len = d.n[l] + 1 + LEVEL_PAD;
+        const uint64_t *K = lkey + d.off[l];
+        const uint32_t *D = ldown + d.off[l];
+        for (uint32_t j = threadIdx.x; j < len; j += blockDim.x) {
+            s_k[d.lds_off[l] + j] = K[j];
+            s_d[d.lds_off[l] + j] = D[j];
+        }
+    }
+    __syncthreads();
+}
+
+// MODE 0: sorted batch.  MODE 1: interception of arbitrary keys (inspection).
+template <int MODE>
+__global__ __launch_bounds__(DT) void k_descend(IndexDesc desc, const uint64_t *__restrict__ lkey,
+                                                const uint32_t *__restrict__ ldown, const uint64_t *__restrict__ skey,
+                                                const uint64_t *__restrict__ sval, const uint32_t *__restrict__ snext,
+                                                const uint8_t *__restrict__ smeta, const uint64_t *__restrict__ sk,
+                                                const uint32_t *__restrict__ sidx, uint32_t n, DevState *st,
+                                                uint64_t *__restrict__ out_vals, uint8_t *__restrict__ out_status,
+                                                uint64_t *__restrict__ res_val, uint8_t *__restrict__ res_flags,
+                                                uint32_t *__restrict__ loc, uint32_t *__restrict__ locnext) {
+    extern __shared__ uint64_t s_dyn[];
+    uint64_t *s_k = s_dyn;
+    uint32_t *s_d = reinterpret_cast<uint32_t *>(s_dyn + desc.lds_entries);
+    stage_levels(desc, lkey, ldown, s_k, s_d);
+
+    const bool mixed = MODE == 0 && st->b_writers != 0;
+    const bool links = MODE == 0 && st->has_links != 0;
+    const bool dead = MODE == 0 && st->has_dead != 0;
+
+    const uint32_t ntiles = (n + DT - 1) / DT;
+    const uint32_t c = xcd_chunk(blockIdx.x, gridDim.x);
+    const uint32_t t0 = (uint32_t)((uint64_t)c * ntiles / gridDim.x);
+    const uint32_t t1 = (uint32_t)((uint64_t)(c + 1) * ntiles / gridDim.x);
+    uint32_t hits = 0, invalid = 0;
+    for (uint32_t t = t0; t < t1; t++) {
+        const uint32_t i = t * DT + threadIdx.x;
+        if (i >= n) continue;
+        uint64_t q = sk[i];
+        if (MODE == 1) {
+            if (q == KEY_MAX) q = KEY_MAX - 1;  // +infinity is never indexed; keep the scan inside the pads
+            uint64_t ik = 0;
+            const uint32_t slot = descend_index(q, desc, lkey, ldown, s_k, s_d, ik);
+            out_vals[i] = slot == HEAD_SLOT ? 0 : ik;
+            out_status[i] = slot == HEAD_SLOT ? 1 : 0;
+            continue;
+        }
+        const uint32_t id = sidx[i];
+        if (q == KEY_MAX) {
+            out_vals[id] = 0;
+            out_status[id] = PI_R_INVALID;
+            invalid++;
+            continue;
+        }
+        uint64_t ck = 0;
+        uint32_t cur = descend_index(q, desc, lkey, ldown, s_k, s_d, ck);
+        // storage walk to the last node with key <= q
+        uint32_t nxt;
+        uint8_t mc = 0;
+        for (uint32_t steps = 0;; steps++) {
+            if (steps >= WALK_LIMIT) {  // a well-formed list never gets here
+                atomicAdd(&st->errors, 1u);
+                break;
+            }
+            nxt = cur + 1;
+            if (links) {
+                mc = smeta[cur];
+                if (mc & META_LINK) nxt = snext[cur];
+            }
+            const uint64_t kn = skey[nxt];
+            if (kn > q) break;
+            cur = nxt;
+            ck = kn;
+        }
+        const bool exists = cur != HEAD_SLOT && ck == q;
+        bool live = false;
+        uint64_t v = 0;
+        if (exists) {
+            if (dead && !links) mc = smeta[cur];
+            live = !(mc & META_DEL);
+            if (live) v = sval[cur];
+        }
+        if (!mixed) {
+            out_vals[id] = v;
+            out_status[id] = live ? PI_R_PRESENT : PI_R_ABSENT;
+            hits += live;
+        } else {
+            res_val[i] = v;
+            res_flags[i] = (uint8_t)((exists ? 1 : 0) | (live ? 2 : 0));
+            loc[i] = cur;
+            locnext[i] = nxt;
+        }
+    }
+    if (MODE == 0) {
+        hits = wave_sum_u32(hits);
+        invalid = wave_sum_u32(invalid);
+        if (lane_id() == 0) {
+            if (hits) atomicAdd(&st->b_hits, hits);
+            if (invalid) atomicAdd(&st->b_invalid, invalid);
+        }
+    }
+}
+
+// -------------------------------------------------------------- ownership --
+
+// Segmented "last writer" scan element: f = a key group starts here,
+// v = sorted index of the last INSERT/DELETE seen (-1 none).
+struct Seg {
+    uint32_t f;
+    int32_t v;
+};
+
+__device__ __forceinline__ Seg seg_op(Seg a, Seg b) {
+    Seg r;
+    r.f = a.f | b.f;
+    r.v = b.f ? b.v : (a.v > b.v ? a.v : b.v);
+    return r;
+}
+
+__device__ __forceinline__ Seg wave_incl_scan_seg(Seg x) {
+    const int lane = lane_id();
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        Seg y;
+        y.f = __shfl_up(x.f, o, 64);
+        y.v = __shfl_up(x.v, o, 64);
+        if (lane >= o) x = seg_op(y, x);
+    }
+    return x;
+}
+
+// exclusive block scan of one Seg per thread; also returns the block total
+__device__ __forceinline__ Seg block_excl_scan_seg(Seg x, Seg *s_w, Seg *total) {
+    const int tid = threadIdx.x;
+    const int w = tid >> 6;
+    const Seg inc = wave_incl_scan_seg(x);
+    Seg ex;
+    ex.f = __shfl_up(inc.f, 1, 64);
+    ex.v = __shfl_up(inc.v, 1, 64);
+    if (lane_id() == 0) {
+        ex.f = 0;
+        ex.v = -1;
+    }
+    if (lane_id() == 63) s_w[w] = inc;
+    __syncthreads();
+    Seg pre{0, -1};
+    for (int i = 0; i < w; i++) pre = seg_op(pre, s_w[i]);
+    Seg tot{0, -1};
+    for (int i = 0; i < ONW; i++) tot = seg_op(tot, s_w[i]);
+    *total = tot;
+    __syncthreads();
+    return seg_op(pre, ex);
+}
+
+__device__ __forceinline__ Seg element(const uint64_t *__restrict__ sk, const uint32_t *__restrict__ sidx,
+                                       const uint8_t *__restrict__ ops, uint32_t i, uint64_t q) {
+    Seg e;
+    e.f = (i == 0 || sk[i - 1] != q) ? 1u : 0u;
+    const uint8_t op = ops[sidx[i]];
+    e.v = (q != KEY_MAX && (op == PI_OP_INSERT || op == PI_OP_DELETE)) ? (int32_t)i : -1;
+    return e;
+}
+
+__global__ __launch_bounds__(OT) void k_own_reduce(const uint64_t *__restrict__ sk, const uint32_t *__restrict__ sidx,
+                                                   const uint8_t *__restrict__ ops, uint32_t n,
+                                                   const DevState *st, Seg *__restrict__ agg) {
+    if (st->b_writers == 0) return;
+    __shared__ Seg s_w[ONW];
+    const uint32_t base = blockIdx.x * OTILE + threadIdx.x * OI;
+    Seg run{0, -1};
+    for (int e = 0; e < OI; e++) {
+        const uint32_t i = base + e;
+        if (i < n) run = seg_op(run, element(sk, sidx, ops, i, sk[i]));
+    }
+    Seg tot;
+    block_excl_scan_seg(run, s_w, &tot);
+    if (threadIdx.x == 0) agg[blockIdx.x] = tot;
+}
+
+// single block: exclusive scan of the tile aggregates (in place)
+__global__ __launch_bounds__(OT) void k_own_prefix(Seg *__restrict__ agg, uint32_t ntiles, const DevState *st) {
+    if (st->b_writers == 0) return;
+    __shared__ Seg s_w[ONW];
+    Seg carry{0, -1};
+    for (uint32_t base = 0; base < ntiles; base += OT * 4) {
+        Seg v[4];
+        Seg run{0, -1};
+        for (int j = 0; j < 4; j++) {
+            const uint32_t i = base + threadIdx.x * 4 + j;
+            v[j] = i < ntiles ? agg[i] : Seg{0, -1};
+            run = seg_op(run, v[j]);
+        }
+        Seg tot;
+        Seg pre = seg_op(carry, block_excl_scan_seg(run, s_w, &tot));
+        for (int j = 0; j < 4; j++) {
+            const uint32_t i = base + threadIdx.x * 4 + j;
+            if (i < ntiles) agg[i] = pre;
+            pre = seg_op(pre, v[j]);
+        }
+        carry = seg_op(carry, tot);
+    }
+}
+
+__global__ __launch_bounds__(OT) void k_own_apply(const uint64_t *__restrict__ sk, const uint32_t *__restrict__ sidx,
+                                                  const uint8_t *__restrict__ ops, const uint64_t *__restrict__ vals,
+                                                  uint32_t n, const Seg *__restrict__ carry_in,
+                                                  const uint64_t *__restrict__ res_val,
+                                                  const uint8_t *__restrict__ res_flags,
+                                                  const uint32_t *__restrict__ loc, uint64_t *__restrict__ sval,
+                                                  uint8_t *__restrict__ smeta, uint64_t *__restrict__ out_vals,
+                                                  uint8_t *__restrict__ out_status, uint32_t *__restrict__ newflag,
+                                                  int32_t *__restrict__ gw, DevState *st) {
+    if (st->b_writers == 0) return;
+    __shared__ Seg s_w[ONW];
+    const uint32_t base = blockIdx.x * OTILE + threadIdx.x * OI;
+    Seg el[OI];
+    uint64_t qk[OI];
+    Seg run{0, -1};
+    for (int e = 0; e < OI; e++) {
+        const uint32_t i = base + e;
+        if (i < n) {
+            qk[e] = sk[i];
+            el[e] = element(sk, sidx, ops, i, qk[e]);
+        } else {
+            qk[e] = KEY_MAX;
+            el[e] = Seg{0, -1};
+        }
+        run = seg_op(run, el[e]);
+    }
+    Seg tot;
+    Seg pre = seg_op(carry_in[blockIdx.x], block_excl_scan_seg(run, s_w, &tot));
+    uint32_t hits = 0, dels = 0, revs = 0;
+    for (int e = 0; e < OI; e++) {
+        const uint32_t i = base + e;
+        if (i >= n) break;
+        const int32_t excl = el[e].f ? -1 : pre.v;
+        pre = seg_op(pre, el[e]);
+        const int32_t incl = pre.v;
+        const uint64_t q = qk[e];
+        if (q == KEY_MAX) {  // invalid: answered by the descent, no effect
+            newflag[i] = 0;
+            continue;
+        }
+        const uint32_t id = sidx[i];
+        const uint8_t fl = res_flags[i];
+        // answer: the state left by the last update before i on this key,
+        // else the state found in storage
+        uint64_t v;
+        bool present;
+        if (excl >= 0) {
+            const uint32_t jd = sidx[excl];
+            present = ops[jd] == PI_OP_INSERT;
+            v = present ? vals[jd] : 0;
+        } else {
+            present = (fl & 2) != 0;
+            v = res_val[i];
+        }
+        out_vals[id] = v;
+        out_status[id] = present ? PI_R_PRESENT : PI_R_ABSENT;
+        hits += present;
+        // the group's last query owns the key's node
+        const bool last = (i + 1 == n) || sk[i + 1] != q;
+        uint32_t nf = 0;
+        if (last && incl >= 0) {
+            const uint32_t jd = sidx[incl];
+            const uint32_t node = loc[i];
+            const bool exists = fl & 1, live = (fl & 2) != 0;
+            if (ops[jd] == PI_OP_INSERT) {
+                if (exists) {
+                    sval[node] = vals[jd];
+                    if (!live) {
+                        smeta[node] = smeta[node] & (uint8_t)~META_DEL;
+                        revs++;
+                    }
+                } else {
+                    nf = 1;
+                    gw[i] = incl;
+                }
+            } else if (exists && live) {
+                smeta[node] = smeta[node] | META_DEL;
+                dels++;
+            }
+        }
+        newflag[i] = nf;
+    }
+    hits = wave_sum_u32(hits);
+    dels = wave_sum_u32(dels);
+    revs = wave_sum_u32(revs);
+    if (lane_id() == 0) {
+        if (hits) atomicAdd(&st->b_hits, hits);
+        if (dels) atomicAdd(&st->b_deletes, dels);
+        if (revs) atomicAdd(&st->b_revives, revs);
+    }
+}
+
+// compacts the new nodes (key order) with their predecessor
+__global__ void k_new_gather(const uint64_t *__restrict__ sk, const uint32_t *__restrict__ sidx,
+                             const uint64_t *__restrict__ vals, const uint32_t *__restrict__ newflag,
+                             const uint32_t *__restrict__ newpos, const int32_t *__restrict__ gw,
+                             const uint32_t *__restrict__ loc, const uint32_t *__restrict__ locnext, uint32_t n,
+                             const DevState *st, uint64_t *__restrict__ nk, uint64_t *__restrict__ nv,
+                             uint32_t *__restrict__ npred, uint32_t *__restrict__ npnext) {
+    if (st->b_writers == 0) return;
+    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n || !newflag[i]) return;
+    const uint32_t r = newpos[i];
+    nk[r] = sk[i];
+    nv[r] = vals[sidx[gw[i]]];
+    npred[r] = loc[i];
+    npnext[r] = locnext[i];
+}
+
+// writes the new nodes and links them (Algorithm 4 insertNode)
+__global__ void k_link(const uint64_t *__restrict__ nk, const uint64_t *__restrict__ nv,
+                       const uint32_t *__restrict__ npred, const uint32_t *__restrict__ npnext, DevState *st,
+                       uint64_t *__restrict__ skey, uint64_t *__restrict__ sval, uint32_t *__restrict__ snext,
+                       uint8_t *__restrict__ smeta) {
+    const uint32_t nnew = st->b_new;
+    const uint32_t r = blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= nnew) return;
+    const uint32_t slot = (uint32_t)st->nused + r;
+    const uint32_t pr = npred[r];
+    skey[slot] = nk[r];
+    sval[slot] = nv[r];
+    smeta[slot] = META_LINK;
+    snext[slot] = (r + 1 < nnew && npred[r + 1] == pr) ? slot + 1 : npnext[r];
+    if (r == 0 || npred[r - 1] != pr) {
+        snext[pr] = slot;
+        smeta[pr] = smeta[pr] | META_LINK;
+    }
+}
+
+__global__ void k_batch_begin(DevState *st, uint32_t n) {
+    if (threadIdx.x != 0) return;
+    st->b_writers = st->b_new = st->b_deletes = st->b_revives = st->b_hits = st->b_invalid = 0;
+    st->b_n = n;
+}
+
+__global__ void k_batch_end(DevState *st) {
+    if (threadIdx.x != 0) return;
+    const unsigned int nn = st->b_new;
+    st->nused += nn;
+    st->n_live = st->n_live + nn + st->b_revives - st->b_deletes;
+    st->changes += nn + st->b_deletes;
+    if (nn) st->has_links = 1;
+    if (st->b_deletes) st->has_dead = 1;
+    st->batches += 1;
+    st->queries += st->b_n;
+    st->hits += st->b_hits;
+    st->invalid += st->b_invalid;
+    st->new_nodes += nn;
+    st->deletes += st->b_deletes;
+    st->revives += st->b_revives;
+}
+
+__global__ void k_count_inserts(const uint8_t *__restrict__ ops, const uint64_t *__restrict__ keys, uint32_t n,
+                                unsigned int *cnt) {
+    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    uint32_t c = (i < n && ops[i] == PI_OP_INSERT && keys[i] != KEY_MAX) ? 1u : 0u;
+    c = wave_sum_u32(c);
+    if (lane_id() == 0 && c) atomicAdd(cnt, c);
+}
+
+__global__ void k_zero_u32(unsigned int *p) {
+    if (threadIdx.x == 0) *p = 0;
+}
+
+uint32_t blocks_for(uint64_t n, int t) { return (uint32_t)((n + t - 1) / t); }
+
+uint32_t descent_grid(const Index &ix, uint64_t n) {
+    const uint32_t ntiles = blocks_for(n, DT);
+    // persistent blocks: enough to fill every CU several times over
+    uint32_t g = (uint32_t)ix.num_cus * 8;
+    if (g > ntiles) g = ntiles;
+    if (g >= 8) g &= ~7u;
+    return g ? g : 1;
+}
+
+}  // namespace
+
+void BatchWorkspace::ensure(uint64_t m) {
+    if (m <= n) return;
+    const uint64_t c = m;
+    res_val.ensure(c * 8);
+    res_flags.ensure(c);
+    loc.ensure(c * 4);
+    locnext.ensure(c * 4);
+    newflag.ensure(c * 4);
+    newpos.ensure(c * 4);
+    gw.ensure(c * 4);
+    const uint64_t nt = (c + OTILE - 1) / OTILE + 1;
+    agg.ensure(nt * sizeof(Seg));
+    nk.ensure(c * 8);
+    nv.ensure(c * 8);
+    npred.ensure(c * 4);
+    npnext.ensure(c * 4);
+    n = m;
+}
+
+void BatchWorkspace::release() {
+    DevBuf *all[] = {&res_val, &res_flags, &loc, &locnext, &newflag, &newpos, &gw, &agg, &carry, &nk, &nv, &npred, &npnext};
+    for (DevBuf *b : all) b->release();
+    n = 0;
+}
+
+uint64_t count_inserts(Index &ix, const uint8_t *ops, const uint64_t *keys, uint64_t n, hipStream_t s) {
+    ix.tmp[5].ensure(16);
+    unsigned int *cnt = ix.tmp[5].as<unsigned int>();
+    hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(64), 0, s, cnt);
+    hipLaunchKernelGGL(k_count_inserts, dim3(blocks_for(n, 256)), dim3(256), 0, s, ops, keys, (uint32_t)n, cnt);
+    PI_LAUNCH_CHECK();
+    unsigned int h = 0;
+    PI_HIP(hipMemcpyAsync(ix.hcounts, cnt, 4, hipMemcpyDeviceToHost, s));
+    PI_HIP(hipStreamSynchronize(s));
+    h = *reinterpret_cast<unsigned int *>(ix.hcounts);
+    return h;
+}
+
+void execute_batch(Index &ix, const uint8_t *ops, const uint64_t *keys, const uint64_t *vals, uint64_t n,
+                   uint64_t *out_vals, uint8_t *out_status, hipStream_t s) {
+    ix.bws.ensure(n);
+    const uint64_t *sk = nullptr;
+    const uint32_t *sidx = nullptr;
+    DevState *st = ix.dstate;
+    Profiler::Rec rec{};
+    auto mark = [&](int k) {
+        if (!ix.prof.on) return;
+        rec.e[k] = ix.prof.take();
+        PI_HIP(hipEventRecord(rec.e[k], s));
+    };
+    mark(0);
+    hipLaunchKernelGGL(k_batch_begin, dim3(1), dim3(64), 0, s, st, (uint32_t)n);
+    PI_LAUNCH_CHECK();
+    sort_keys_with_index(ix.sortws, keys, ops, n, st, s, &sk, &sidx);
+    mark(1);
+
+    BatchWorkspace &w = ix.bws;
+    const IndexDesc &d = ix.desc;
+    const size_t lds = (size_t)d.lds_entries * 12;
+    hipLaunchKernelGGL(k_descend<0>, dim3(descent_grid(ix, n)), dim3(DT), lds, s, d, ix.arena_key.as<uint64_t>(),
+                       ix.arena_down.as<uint32_t>(), ix.st.key.as<uint64_t>(), ix.st.val.as<uint64_t>(),
+                       ix.st.next.as<uint32_t>(), ix.st.meta.as<uint8_t>(), sk, sidx, (uint32_t)n, st, out_vals,
+                       out_status, w.res_val.as<uint64_t>(), w.res_flags.as<uint8_t>(), w.loc.as<uint32_t>(),
+                       w.locnext.as<uint32_t>());
+    PI_LAUNCH_CHECK();
+    mark(2);
+
+    const uint32_t otiles = blocks_for(n, OTILE);
+    Seg *agg = w.agg.as<Seg>();
+    hipLaunchKernelGGL(k_own_reduce, dim3(otiles), dim3(OT), 0, s, sk, sidx, ops, (uint32_t)n, st, agg);
+    hipLaunchKernelGGL(k_own_prefix, dim3(1), dim3(OT), 0, s, agg, otiles, st);
+    hipLaunchKernelGGL(k_own_apply, dim3(otiles), dim3(OT), 0, s, sk, sidx, ops, vals, (uint32_t)n, agg,
+                       w.res_val.as<uint64_t>(), w.res_flags.as<uint8_t>(), w.loc.as<uint32_t>(),
+                       ix.st.val.as<uint64_t>(), ix.st.meta.as<uint8_t>(), out_vals, out_status,
+                       w.newflag.as<uint32_t>(), w.gw.as<int32_t>(), st);
+    PI_LAUNCH_CHECK();
+    mark(3);
+    exclusive_scan_u32(ix.scanws, w.newflag.as<uint32_t>(), w.newpos.as<uint32_t>(), n, &st->b_new,
+                       &st->b_writers, s);
+    hipLaunchKernelGGL(k_new_gather, dim3(blocks_for(n, 256)), dim3(256), 0, s, sk, sidx, vals,
+                       w.newflag.as<uint32_t>(), w.newpos.as<uint32_t>(), w.gw.as<int32_t>(), w.loc.as<uint32_t>(),
+                       w.locnext.as<uint32_t>(), (uint32_t)n, st, w.nk.as<uint64_t>(), w.nv.as<uint64_t>(),
+                       w.npred.as<uint32_t>(), w.npnext.as<uint32_t>());
+    hipLaunchKernelGGL(k_link, dim3(blocks_for(n, 256)), dim3(256), 0, s, w.nk.as<uint64_t>(), w.nv.as<uint64_t>(),
+                       w.npred.as<uint32_t>(), w.npnext.as<uint32_t>(), st, ix.st.key.as<uint64_t>(),
+                       ix.st.val.as<uint64_t>(), ix.st.next.as<uint32_t>(), ix.st.meta.as<uint8_t>());
+    hipLaunchKernelGGL(k_batch_end, dim3(1), dim3(64), 0, s, st);
+    PI_LAUNCH_CHECK();
+    mark(4);
+    if (ix.prof.on) {
+        rec.n = 5;
+        ix.prof.pending.push_back(rec);
+        if (ix.prof.pending.size() > 4096) ix.prof.drain(false);
+    }
+}
+
+hipEvent_t Profiler::take() {
+    if (pool.empty()) {
+        hipEvent_t e;
+        PI_HIP(hipEventCreate(&e));
+        return e;
+    }
+    hipEvent_t e = pool.back();
+    pool.pop_back();
+    return e;
+}
+
+void Profiler::drain(bool wait) {
+    size_t done = 0;
+    for (; done < pending.size(); done++) {
+        Rec &r = pending[done];
+        if (wait) {
+            PI_HIP(hipEventSynchronize(r.e[r.n - 1]));
+        } else if (hipEventQuery(r.e[r.n - 1]) != hipSuccess) {
+            (void)hipGetLastError();
+            break;
+        }
+        float t[4] = {0, 0, 0, 0};
+        for (int k = 0; k + 1 < r.n; k++) PI_HIP(hipEventElapsedTime(&t[k], r.e[k], r.e[k + 1]));
+        if (r.n == 5) {
+            acc.batches++;
+            acc.sort_ms += t[0];
+            acc.descend_ms += t[1];
+            acc.own_ms += t[2];
+            acc.link_ms += t[3];
+        } else {
+            acc.rebuilds++;
+            acc.rebuild_ms += t[0];
+        }
+        for (int k = 0; k < r.n; k++) pool.push_back(r.e[k]);
+    }
+    pending.erase(pending.begin(), pending.begin() + done);
+}
+
+void Profiler::release() {
+    for (auto &r : pending)
+        for (int k = 0; k < r.n; k++) pool.push_back(r.e[k]);
+    pending.clear();
+    for (hipEvent_t e : pool) (void)hipEventDestroy(e);
+    pool.clear();
+}
+
+void debug_interceptions(Index &ix, const uint64_t *keys, uint64_t n, uint64_t *icpt_keys, uint8_t *is_head,
+                         hipStream_t s) {
+    const IndexDesc &d = ix.desc;
+    const size_t lds = (size_t)d.lds_entries * 12;
+    hipLaunchKernelGGL(k_descend<1>, dim3(descent_grid(ix, n)), dim3(DT), lds, s, d, ix.arena_key.as<uint64_t>(),
+                       ix.arena_down.as<uint32_t>(), ix.st.key.as<uint64_t>(), ix.st.val.as<uint64_t>(),
+                       ix.st.next.as<uint32_t>(), ix.st.meta.as<uint8_t>(), keys, nullptr, (uint32_t)n, ix.dstate,
+                       icpt_keys, is_head, nullptr, nullptr, nullptr, nullptr);
+    PI_LAUNCH_CHECK();
+}
+
+}  // namespace pi

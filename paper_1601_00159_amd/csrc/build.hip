@@ -1,0 +1,528 @@
+// Construction of the storage base region and the index layer.
+//
+// Section 3.1: the index layer is built bottom-up by one scan of the ordered
+// storage layer; Section 4.1: the scan can be split over workers, each
+// building its part of every level, the parts being concatenated level by
+// level.  Here a block owns a 4096-node tile of the base region: one pass
+// counts, per tile, how many of its keys reach each level (heights come from
+// the key), a column scan turns the counts into each tile's offset on each
+// level, and a second pass writes every key into all the levels it reaches,
+// with its position on the level below as the down pointer.
+//
+// A rebuild (Section 4.3.5: rebuild the whole index layer from the storage
+// layer once enough updates have accumulated, keeping only valid nodes)
+// merges the base region with the nodes created since the last rebuild,
+// drops deleted nodes, and rebuilds every level from the merged region.
+#include <algorithm>
+#include <vector>
+
+#include "index.h"
+
+namespace pi {
+namespace {
+
+constexpr int BT = 256;
+constexpr int BI = 16;
+constexpr int BTILE = BT * BI;
+constexpr int BNW = BT / 64;
+
+// ---- level construction ----------------------------------------------------
+
+__global__ __launch_bounds__(BT) void k_height_count(const uint64_t *__restrict__ skey, uint32_t nbase,
+                                                     uint64_t seed, uint32_t l2p, uint32_t maxh,
+                                                     uint32_t *__restrict__ cnt, uint32_t ntiles) {
+    __shared__ uint32_t h[MAX_LEVELS + 1];
+    const int tid = threadIdx.x;
+    if (tid <= MAX_LEVELS) h[tid] = 0;
+    __syncthreads();
+    const uint32_t base = blockIdx.x * BTILE;
+    for (int j = 0; j < BI; j++) {
+        const uint32_t b = base + j * BT + tid;
+        if (b < nbase) atomicAdd(&h[tower_height(skey[1 + b], seed, l2p, maxh)], 1u);
+    }
+    __syncthreads();
+    if (tid < MAX_LEVELS) {
+        uint32_t c = 0;
+        for (int x = tid; x <= MAX_LEVELS; x++) c += h[x];
+        cnt[(size_t)tid * ntiles + blockIdx.x] = tid >= 2 ? c : 0u;
+    }
+}
+
+__global__ __launch_bounds__(BT) void k_level_scatter(const uint64_t *__restrict__ skey, uint32_t nbase,
+                                                      uint64_t seed, uint32_t l2p, uint32_t maxh,
+                                                      const uint32_t *__restrict__ tileoff, uint32_t ntiles,
+                                                      IndexDesc desc, uint64_t *__restrict__ lkey,
+                                                      uint32_t *__restrict__ ldown) {
+    __shared__ uint32_t s_cnt[BNW][MAX_LEVELS];
+    __shared__ uint32_t s_toff[MAX_LEVELS];
+    const int tid = threadIdx.x;
+    const int lane = lane_id();
+    const int w = tid >> 6;
+    for (int j = tid; j < BNW * MAX_LEVELS; j += BT) (&s_cnt[0][0])[j] = 0;
+    if (tid < MAX_LEVELS) s_toff[tid] = tileoff[(size_t)tid * ntiles + blockIdx.x];  // rows 0,1 are zero
+    __syncthreads();
+
+    const uint32_t wbase = blockIdx.x * BTILE + w * (BI * 64);
+    uint64_t k[BI];
+    uint32_t h[BI];
+#pragma unroll
+    for (int r = 0; r < BI; r++) {
+        const uint32_t b = wbase + r * 64 + lane;
+        if (b < nbase) {
+            k[r] = skey[1 + b];
+            h[r] = tower_height(k[r], seed, l2p, maxh);
+        } else {
+            k[r] = KEY_MAX;
+            h[r] = 0;
+        }
+    }
+    // keys of this wave per level
+#pragma unroll
+    for (int r = 0; r < BI; r++) {
+        for (uint32_t l = 2;; l++) {
+            const uint64_t m = ballot64(h[r] >= l);
+            if (!m) break;
+            if (lane == 0) s_cnt[w][l] += (uint32_t)__popcll(m);
+        }
+    }
+    __syncthreads();
+    if (tid < MAX_LEVELS) {
+        uint32_t run = 0;
+        for (int ww = 0; ww < BNW; ww++) {
+            const uint32_t c = s_cnt[ww][tid];
+            s_cnt[ww][tid] = run;
+            run += c;
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < BI; r++) {
+        uint32_t prev = 1 + wbase + r * 64 + lane;  // storage slot: down pointer of level 2
+        for (uint32_t l = 2;; l++) {
+            const bool in = h[r] >= l;
+            const uint64_t m = ballot64(in);
+            if (!m) break;
+            const uint32_t before = s_cnt[w][l];
+            if (in) {
+                const uint32_t p = 1 + s_toff[l] + before + mask_rank(m);
+                lkey[desc.off[l] + p] = k[r];
+                ldown[desc.off[l] + p] = prev;
+                prev = p;
+            }
+            if (lane == 0) s_cnt[w][l] = before + (uint32_t)__popcll(m);
+        }
+    }
+}
+
+__global__ void k_level_pad(IndexDesc desc, uint64_t *__restrict__ lkey, uint32_t *__restrict__ ldown) {
+    const int l = blockIdx.x;
+    if (l < 2 || l > desc.top) return;
+    const uint64_t o = desc.off[l];
+    if (threadIdx.x == 0) {
+        lkey[o] = 0;
+        ldown[o] = 0;
+    }
+    if (threadIdx.x < LEVEL_PAD) {
+        lkey[o + desc.n[l] + 1 + threadIdx.x] = KEY_MAX;
+        ldown[o + desc.n[l] + 1 + threadIdx.x] = 0;
+    }
+}
+
+// ---- bulk load ---------------------------------------------------------------
+
+__global__ void k_last_of_run(const uint64_t *__restrict__ sk, uint32_t n, uint32_t *__restrict__ flag) {
+    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const uint64_t k = sk[i];
+    flag[i] = (k != KEY_MAX && (i + 1 == n || sk[i + 1] != k)) ? 1u : 0u;
+}
+
+__global__ void k_write_base(const uint64_t *__restrict__ sk, const uint32_t *__restrict__ sidx,
+                             const uint64_t *__restrict__ vals, const uint32_t *__restrict__ flag,
+                             const uint32_t *__restrict__ pos, uint32_t n, uint64_t *__restrict__ skey,
+                             uint64_t *__restrict__ sval, uint8_t *__restrict__ smeta) {
+    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n || !flag[i]) return;
+    const uint64_t slot = 1 + (uint64_t)pos[i];
+    skey[slot] = sk[i];
+    sval[slot] = vals[sidx[i]];
+    smeta[slot] = 0;
+}
+
+// head at slot 0 (successor slot 1), tail at nbase+1, and the counters
+__global__ void k_reset_region(uint64_t *__restrict__ skey, uint64_t *__restrict__ sval,
+                               uint32_t *__restrict__ snext, uint8_t *__restrict__ smeta, uint64_t nbase,
+                               DevState *st, int reset_stats) {
+    if (threadIdx.x != 0) return;
+    skey[0] = 0;
+    sval[0] = 0;
+    snext[0] = 0;
+    smeta[0] = 0;
+    skey[nbase + 1] = KEY_MAX;
+    sval[nbase + 1] = 0;
+    snext[nbase + 1] = 0;
+    smeta[nbase + 1] = 0;
+    st->nused = nbase + 2;
+    st->n_live = nbase;
+    st->changes = 0;
+    st->has_links = 0;
+    st->has_dead = 0;
+    if (reset_stats) {
+        st->batches = st->queries = st->hits = st->invalid = 0;
+        st->new_nodes = st->deletes = st->revives = 0;
+        st->errors = 0;
+    }
+    st->b_writers = st->b_new = st->b_deletes = st->b_revives = st->b_hits = st->b_invalid = 0;
+    st->b_n = 0;
+}
+
+// ---- merge of the base region with the overflow nodes -----------------------
+
+__global__ void k_base_live(const uint8_t *__restrict__ smeta, uint64_t nbase, uint32_t *__restrict__ flag) {
+    const uint64_t b = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (b > nbase) return;
+    flag[b] = (b < nbase && !(smeta[1 + b] & META_DEL)) ? 1u : 0u;  // flag[nbase] = 0 (sentinel)
+}
+
+__global__ void k_ovf_gather(const uint64_t *__restrict__ skey, uint64_t first, uint64_t novf,
+                             uint64_t *__restrict__ okey, uint32_t *__restrict__ oslot) {
+    const uint64_t o = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (o >= novf) return;
+    okey[o] = skey[first + o];
+    oslot[o] = (uint32_t)(first + o);
+}
+
+// For each sorted overflow node: live flag, and p = number of base keys
+// smaller than its key (binary search; keys are unique across the list).
+__global__ void k_ovf_place(const uint64_t *__restrict__ osk, const uint32_t *__restrict__ oslot, uint64_t novf,
+                            const uint64_t *__restrict__ skey, const uint8_t *__restrict__ smeta, uint64_t nbase,
+                            uint32_t *__restrict__ olive, uint32_t *__restrict__ opos,
+                            uint32_t *__restrict__ hist) {
+    const uint64_t o = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (o >= novf) return;
+    const uint64_t k = osk[o];
+    uint64_t lo = 0, hi = nbase;  // search base slots 1..nbase
+    while (lo < hi) {
+        const uint64_t mid = (lo + hi) >> 1;
+        if (skey[1 + mid] < k)
+            lo = mid + 1;
+        else
+            hi = mid;
+    }
+    const uint32_t live = (smeta[oslot[o]] & META_DEL) ? 0u : 1u;
+    olive[o] = live;
+    opos[o] = (uint32_t)lo;
+    if (live) atomicAdd(&hist[lo], 1u);
+}
+
+__global__ void k_fill_u32(uint32_t *__restrict__ p, uint64_t n, uint32_t v) {
+    const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = v;
+}
+
+// out position of live base node b = (live base before b) + (live overflow
+// nodes placed at or before b); of live overflow node o = (live base before
+// its place) + (live overflow before o).
+__global__ void k_merge_base(const uint64_t *__restrict__ skey, const uint64_t *__restrict__ sval,
+                             const uint8_t *__restrict__ smeta, uint64_t nbase, const uint32_t *__restrict__ A,
+                             const uint32_t *__restrict__ Bexcl, const uint32_t *__restrict__ H,
+                             uint64_t *__restrict__ okey, uint64_t *__restrict__ oval,
+                             uint8_t *__restrict__ ometa, uint64_t slot_off) {
+    const uint64_t b = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (b >= nbase) return;
+    if (smeta[1 + b] & META_DEL) return;
+    const uint64_t o = slot_off + A[b] + Bexcl[b] + H[b];
+    okey[o] = skey[1 + b];
+    oval[o] = sval[1 + b];
+    if (ometa) ometa[o] = 0;
+}
+
+__global__ void k_merge_ovf(const uint64_t *__restrict__ osk, const uint32_t *__restrict__ oslot, uint64_t novf,
+                            const uint64_t *__restrict__ sval, const uint32_t *__restrict__ olive,
+                            const uint32_t *__restrict__ C, const uint32_t *__restrict__ opos,
+                            const uint32_t *__restrict__ A, uint64_t *__restrict__ okey,
+                            uint64_t *__restrict__ oval, uint8_t *__restrict__ ometa, uint64_t slot_off) {
+    const uint64_t o = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (o >= novf || !olive[o]) return;
+    const uint64_t d = slot_off + A[opos[o]] + C[o];
+    okey[d] = osk[o];
+    oval[d] = sval[oslot[o]];
+    if (ometa) ometa[d] = 0;
+}
+
+uint32_t blocks_for(uint64_t n, int t) { return (uint32_t)((n + t - 1) / t); }
+
+}  // namespace
+
+void Storage::alloc(uint64_t c) {
+    cap = c;
+    key.ensure(c * sizeof(uint64_t));
+    val.ensure(c * sizeof(uint64_t));
+    next.ensure(c * sizeof(uint32_t));
+    meta.ensure(c * sizeof(uint8_t));
+}
+
+void Storage::release() {
+    key.release();
+    val.release();
+    next.release();
+    meta.release();
+    cap = 0;
+}
+
+void read_state(Index &ix, hipStream_t s, DevState *out) {
+    PI_HIP(hipMemcpyAsync(ix.hstate, ix.dstate, sizeof(DevState), hipMemcpyDeviceToHost, s));
+    PI_HIP(hipStreamSynchronize(s));
+    *out = *ix.hstate;
+    ix.used_upper = out->nused;
+    if (out->errors) throw Error{PI_ERR_DEVICE, "internal error: storage walk exceeded its bound"};
+}
+
+// Builds every index level from base slots 1..nbase.  Synchronises s.
+static void build_levels(Index &ix, hipStream_t s) {
+    IndexDesc d{};
+    d.top = 1;
+    d.lds_from = MAX_LEVELS;
+    const uint64_t nb = ix.nbase;
+    const uint32_t maxh = ix.cfg.max_height;
+    if (nb > 0) {
+        const uint32_t ntiles = blocks_for(nb, BTILE);
+        DevBuf &cnt = ix.tmp[0];
+        DevBuf &tot = ix.tmp[1];
+        cnt.ensure((size_t)MAX_LEVELS * ntiles * sizeof(uint32_t));
+        tot.ensure(MAX_LEVELS * sizeof(uint32_t));
+        hipLaunchKernelGGL(k_height_count, dim3(ntiles), dim3(BT), 0, s, ix.st.key.as<uint64_t>(), (uint32_t)nb,
+                           ix.cfg.height_seed, ix.cfg.log2_inv_p, maxh, cnt.as<uint32_t>(), ntiles);
+        PI_LAUNCH_CHECK();
+        column_scan(cnt.as<uint32_t>(), MAX_LEVELS, ntiles, tot.as<uint32_t>(), s);
+        uint32_t *htot = reinterpret_cast<uint32_t *>(ix.hcounts);
+        PI_HIP(hipMemcpyAsync(htot, tot.p, MAX_LEVELS * sizeof(uint32_t), hipMemcpyDeviceToHost, s));
+        PI_HIP(hipStreamSynchronize(s));
+        uint64_t total = 0;
+        for (int l = 2; l < MAX_LEVELS && l <= (int)maxh; l++) {
+            d.n[l] = htot[l];
+            if (htot[l] > 0) d.top = l;
+        }
+        for (int l = 2; l <= d.top; l++) {
+            d.off[l] = total;
+            total += ((uint64_t)d.n[l] + 1 + LEVEL_PAD + 15) & ~15ull;  // 128-byte aligned levels
+        }
+        if (d.top >= 2) {
+            ix.arena_key.ensure(total * sizeof(uint64_t));
+            ix.arena_down.ensure(total * sizeof(uint32_t));
+            hipLaunchKernelGGL(k_level_scatter, dim3(ntiles), dim3(BT), 0, s, ix.st.key.as<uint64_t>(),
+                               (uint32_t)nb, ix.cfg.height_seed, ix.cfg.log2_inv_p, maxh, cnt.as<uint32_t>(),
+                               ntiles, d, ix.arena_key.as<uint64_t>(), ix.arena_down.as<uint32_t>());
+            hipLaunchKernelGGL(k_level_pad, dim3(MAX_LEVELS), dim3(64), 0, s, d, ix.arena_key.as<uint64_t>(),
+                               ix.arena_down.as<uint32_t>());
+            PI_LAUNCH_CHECK();
+        }
+        // upper levels kept in LDS by the descent (Section 5.1 notes the top
+        // levels are cache resident anyway; Section 7 proposes pinning them)
+        const uint32_t budget = 2048;  // entries: 24 KB of LDS per block
+        uint32_t used = 0;
+        int from = d.top + 1;
+        const uint32_t want = ix.cfg.lds_levels ? ix.cfg.lds_levels : 64u;
+        for (int l = d.top; l >= 2 && (uint32_t)(d.top - l) < want; l--) {
+            const uint32_t e = d.n[l] + 1 + LEVEL_PAD;
+            if (used + e > budget) break;
+            d.lds_off[l] = used;
+            used += e;
+            from = l;
+        }
+        d.lds_from = from;
+        d.lds_entries = used;
+    }
+    PI_HIP(hipStreamSynchronize(s));
+    ix.desc = d;
+}
+
+void init_empty(Index &ix, hipStream_t s) {
+    ix.nbase = 0;
+    hipLaunchKernelGGL(k_reset_region, dim3(1), dim3(64), 0, s, ix.st.key.as<uint64_t>(), ix.st.val.as<uint64_t>(),
+                       ix.st.next.as<uint32_t>(), ix.st.meta.as<uint8_t>(), (uint64_t)0, ix.dstate, 1);
+    PI_LAUNCH_CHECK();
+    ix.used_upper = 2;
+    ix.live_at_rebuild = 0;
+    build_levels(ix, s);
+}
+
+void grow_storage(Index &ix, uint64_t need, hipStream_t s) {
+    if (need <= ix.st.cap) return;
+    DevState cur;
+    read_state(ix, s, &cur);
+    uint64_t ncap = std::max<uint64_t>(need, ix.st.cap + ix.st.cap / 2);
+    Storage ns;
+    ns.alloc(ncap);
+    const uint64_t used = cur.nused;
+    PI_HIP(hipMemcpyAsync(ns.key.p, ix.st.key.p, used * 8, hipMemcpyDeviceToDevice, s));
+    PI_HIP(hipMemcpyAsync(ns.val.p, ix.st.val.p, used * 8, hipMemcpyDeviceToDevice, s));
+    PI_HIP(hipMemcpyAsync(ns.next.p, ix.st.next.p, used * 4, hipMemcpyDeviceToDevice, s));
+    PI_HIP(hipMemcpyAsync(ns.meta.p, ix.st.meta.p, used, hipMemcpyDeviceToDevice, s));
+    PI_HIP(hipStreamSynchronize(s));
+    ix.st.release();
+    ix.st = ns;
+}
+
+void bulk_load(Index &ix, const uint64_t *keys, const uint64_t *vals, uint64_t n, hipStream_t s) {
+    const uint64_t *sk = nullptr;
+    const uint32_t *sidx = nullptr;
+    uint64_t nb = 0;
+    if (n > 0) {
+        sort_keys_with_index(ix.sortws, keys, nullptr, n, nullptr, s, &sk, &sidx);
+        DevBuf &flag = ix.tmp[2];
+        DevBuf &pos = ix.tmp[3];
+        DevBuf &tot = ix.tmp[1];
+        flag.ensure(n * 4);
+        pos.ensure(n * 4);
+        tot.ensure(MAX_LEVELS * 4);
+        hipLaunchKernelGGL(k_last_of_run, dim3(blocks_for(n, 256)), dim3(256), 0, s, sk, (uint32_t)n,
+                           flag.as<uint32_t>());
+        PI_LAUNCH_CHECK();
+        exclusive_scan_u32(ix.scanws, flag.as<uint32_t>(), pos.as<uint32_t>(), n, tot.as<uint32_t>(), nullptr, s);
+        uint32_t *h = reinterpret_cast<uint32_t *>(ix.hcounts);
+        PI_HIP(hipMemcpyAsync(h, tot.p, 4, hipMemcpyDeviceToHost, s));
+        PI_HIP(hipStreamSynchronize(s));
+        nb = h[0];
+        // a nonzero capacity_hint is a fixed capacity; otherwise leave room to grow
+        if (ix.cfg.capacity_hint && nb + 2 > ix.cfg.capacity_hint)
+            throw Error{PI_ERR_CAPACITY, "bulk load exceeds capacity_hint"};
+        const uint64_t want = ix.cfg.capacity_hint ? ix.cfg.capacity_hint
+                                                   : nb + 2 + std::max<uint64_t>(nb / 4, 1 << 16);
+        if (want > ix.st.cap) {
+            Storage ns;
+            ns.alloc(want);
+            ix.st.release();
+            ix.st = ns;
+        }
+        hipLaunchKernelGGL(k_write_base, dim3(blocks_for(n, 256)), dim3(256), 0, s, sk, sidx, vals,
+                           flag.as<uint32_t>(), pos.as<uint32_t>(), (uint32_t)n, ix.st.key.as<uint64_t>(),
+                           ix.st.val.as<uint64_t>(), ix.st.meta.as<uint8_t>());
+        PI_LAUNCH_CHECK();
+    }
+    ix.nbase = nb;
+    hipLaunchKernelGGL(k_reset_region, dim3(1), dim3(64), 0, s, ix.st.key.as<uint64_t>(), ix.st.val.as<uint64_t>(),
+                       ix.st.next.as<uint32_t>(), ix.st.meta.as<uint8_t>(), nb, ix.dstate, 0);
+    PI_LAUNCH_CHECK();
+    ix.used_upper = nb + 2;
+    ix.live_at_rebuild = nb;
+    build_levels(ix, s);
+}
+
+// Writes the live pairs in key order to okey/oval (+ slot_off), and, when
+// ometa is given, clears their flags.  Returns the live count.  Synchronises.
+static uint64_t merge_live(Index &ix, uint64_t *okey, uint64_t *oval, uint8_t *ometa, uint64_t slot_off,
+                           uint64_t cap, hipStream_t s, bool *too_small) {
+    DevState cur;
+    read_state(ix, s, &cur);
+    const uint64_t nb = ix.nbase;
+    const uint64_t first = nb + 2;
+    const uint64_t novf = cur.nused > first ? cur.nused - first : 0;
+    *too_small = cur.n_live > cap;
+    if (*too_small) return cur.n_live;
+    DevBuf &A = ix.tmp[0];    // base live flags -> exclusive prefix (nb+1)
+    DevBuf &H = ix.tmp[1];    // live overflow nodes placed at each base position (nb+1)
+    DevBuf &B = ix.tmp[2];    // exclusive prefix of H
+    DevBuf &C = ix.tmp[3];    // overflow live flags -> exclusive prefix
+    DevBuf &P = ix.tmp[4];    // overflow place
+    DevBuf &T = ix.tmp[5];    // totals
+    A.ensure((nb + 1) * 4);
+    H.ensure((nb + 1) * 4);
+    B.ensure((nb + 1) * 4);
+    C.ensure((novf + 1) * 4);
+    P.ensure((novf + 1) * 4);
+    T.ensure(16);
+    DevBuf flagA;
+    flagA.ensure((nb + 1) * 4);
+    hipLaunchKernelGGL(k_base_live, dim3(blocks_for(nb + 1, 256)), dim3(256), 0, s, ix.st.meta.as<uint8_t>(), nb,
+                       flagA.as<uint32_t>());
+    hipLaunchKernelGGL(k_fill_u32, dim3(blocks_for(nb + 1, 256)), dim3(256), 0, s, H.as<uint32_t>(), nb + 1, 0u);
+    PI_LAUNCH_CHECK();
+    exclusive_scan_u32(ix.scanws, flagA.as<uint32_t>(), A.as<uint32_t>(), nb + 1, T.as<uint32_t>(), nullptr, s);
+    const uint64_t *osk = nullptr;
+    const uint32_t *oslot = nullptr;
+    DevBuf olive;
+    if (novf > 0) {
+        DevBuf okey, oslot0;
+        okey.ensure(novf * 8);
+        oslot0.ensure(novf * 4);
+        olive.ensure(novf * 4);
+        hipLaunchKernelGGL(k_ovf_gather, dim3(blocks_for(novf, 256)), dim3(256), 0, s, ix.st.key.as<uint64_t>(),
+                           first, novf, okey.as<uint64_t>(), oslot0.as<uint32_t>());
+        PI_LAUNCH_CHECK();
+        sort_pairs(ix.sortws, okey.as<uint64_t>(), oslot0.as<uint32_t>(), novf, s, &osk, &oslot);
+        hipLaunchKernelGGL(k_ovf_place, dim3(blocks_for(novf, 256)), dim3(256), 0, s, osk, oslot, novf,
+                           ix.st.key.as<uint64_t>(), ix.st.meta.as<uint8_t>(), nb, olive.as<uint32_t>(),
+                           P.as<uint32_t>(), H.as<uint32_t>());
+        PI_LAUNCH_CHECK();
+        exclusive_scan_u32(ix.scanws, olive.as<uint32_t>(), C.as<uint32_t>(), novf, T.as<uint32_t>() + 1, nullptr, s);
+        PI_HIP(hipStreamSynchronize(s));
+        okey.release();
+        oslot0.release();
+    }
+    exclusive_scan_u32(ix.scanws, H.as<uint32_t>(), B.as<uint32_t>(), nb + 1, T.as<uint32_t>() + 2, nullptr, s);
+    {
+        // the flags must agree with the live counter before anything is written
+        uint32_t *ht = reinterpret_cast<uint32_t *>(ix.hcounts);
+        PI_HIP(hipMemcpyAsync(ht, T.p, 12, hipMemcpyDeviceToHost, s));
+        PI_HIP(hipStreamSynchronize(s));
+        const uint64_t live_flags = (uint64_t)ht[0] + (novf > 0 ? ht[1] : 0u);
+        if (live_flags != cur.n_live || (novf > 0 && ht[2] != ht[1]))
+            throw Error{PI_ERR_DEVICE, "internal error: live flags disagree with the live counter"};
+    }
+    if (nb > 0)
+        hipLaunchKernelGGL(k_merge_base, dim3(blocks_for(nb, 256)), dim3(256), 0, s, ix.st.key.as<uint64_t>(),
+                           ix.st.val.as<uint64_t>(), ix.st.meta.as<uint8_t>(), nb, A.as<uint32_t>(),
+                           B.as<uint32_t>(), H.as<uint32_t>(), okey, oval, ometa, slot_off);
+    if (novf > 0)
+        hipLaunchKernelGGL(k_merge_ovf, dim3(blocks_for(novf, 256)), dim3(256), 0, s, osk, oslot, novf,
+                           ix.st.val.as<uint64_t>(), olive.as<uint32_t>(), C.as<uint32_t>(), P.as<uint32_t>(),
+                           A.as<uint32_t>(), okey, oval, ometa, slot_off);
+    PI_LAUNCH_CHECK();
+    PI_HIP(hipStreamSynchronize(s));
+    flagA.release();
+    olive.release();
+    return cur.n_live;
+}
+
+uint64_t export_live(Index &ix, uint64_t *okeys, uint64_t *ovals, uint64_t cap, hipStream_t s) {
+    bool small = false;
+    const uint64_t n = merge_live(ix, okeys, ovals, nullptr, 0, cap, s, &small);
+    if (small) throw Error{PI_ERR_CAPACITY, "export capacity too small", };
+    return n;
+}
+
+void rebuild(Index &ix, hipStream_t s) {
+    Profiler::Rec rec{};
+    if (ix.prof.on) {
+        rec.n = 2;
+        rec.e[0] = ix.prof.take();
+        PI_HIP(hipEventRecord(rec.e[0], s));
+    }
+    DevState cur;
+    read_state(ix, s, &cur);
+    const uint64_t live = cur.n_live;
+    uint64_t ncap = ix.cfg.capacity_hint ? ix.cfg.capacity_hint
+                                         : std::max<uint64_t>(ix.st.cap, live + 2 + std::max<uint64_t>(live / 4, 1 << 16));
+    Storage ns;
+    ns.alloc(ncap);
+    bool small = false;
+    merge_live(ix, ns.key.as<uint64_t>(), ns.val.as<uint64_t>(), ns.meta.as<uint8_t>(), 1, ~0ull, s, &small);
+    ix.st.release();
+    ix.st = ns;
+    ix.nbase = live;
+    hipLaunchKernelGGL(k_reset_region, dim3(1), dim3(64), 0, s, ix.st.key.as<uint64_t>(), ix.st.val.as<uint64_t>(),
+                       ix.st.next.as<uint32_t>(), ix.st.meta.as<uint8_t>(), live, ix.dstate, 0);
+    PI_LAUNCH_CHECK();
+    ix.used_upper = live + 2;
+    ix.live_at_rebuild = live;
+    ix.repairs++;
+    build_levels(ix, s);
+    if (ix.prof.on) {
+        rec.e[1] = ix.prof.take();
+        PI_HIP(hipEventRecord(rec.e[1], s));
+        ix.prof.pending.push_back(rec);
+    }
+}
+
+}  // namespace pi

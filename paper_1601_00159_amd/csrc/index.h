@@ -1,0 +1,91 @@
+// Host-side state of one index and the operations of the library.
+#pragma once
+
+#include <vector>
+
+#include "pi_internal.h"
+
+namespace pi {
+
+// Storage layer (Definition 1, Section 4.1) as structure-of-arrays in HBM:
+//   slot 0            head (key -infinity; never compared)
+//   slots 1..nbase    base region, strictly increasing keys, successor of
+//                     slot i is i+1 unless META_LINK is set
+//   slot nbase+1      tail (key +infinity)
+//   slots > nbase+1   nodes created by inserts since the last rebuild, one
+//                     key-sorted run per batch, successor always in snext
+struct Storage {
+    uint64_t cap = 0;
+    DevBuf key, val, next, meta;
+    void alloc(uint64_t cap);
+    void release();
+};
+
+struct BatchWorkspace {
+    DevBuf res_val, res_flags, loc, locnext, newflag, newpos, gw, agg, carry;
+    DevBuf nk, nv, npred, npnext;
+    uint64_t n = 0;
+    void ensure(uint64_t n);
+    void release();
+};
+
+// Stage timing with HIP events on the caller's stream (pi_config.profile).
+struct Profiler {
+    bool on = false;
+    struct Rec {
+        hipEvent_t e[5];
+        int n;  // 5 = batch (begin, sorted, descended, owned, end); 2 = rebuild
+    };
+    std::vector<hipEvent_t> pool;
+    std::vector<Rec> pending;
+    pi_profile acc{};
+    hipEvent_t take();
+    void drain(bool wait);  // folds completed records into acc
+    void release();
+};
+
+struct Index {
+    pi_config cfg{};
+    int device = 0;
+    bool failed = false;
+    std::string err;
+
+    Storage st;
+    uint64_t nbase = 0;        // base-region nodes
+    uint64_t used_upper = 2;   // host upper bound of DevState::nused
+    uint64_t live_at_rebuild = 0;
+    uint64_t repairs = 0;
+
+    DevBuf arena_key, arena_down;  // index levels
+    IndexDesc desc{};
+
+    DevState *dstate = nullptr;    // device
+    DevState *hstate = nullptr;    // pinned host copy
+    hipEvent_t ev_state = nullptr;
+    bool state_enqueued = false;
+
+    SortWorkspace sortws;
+    ScanWorkspace scanws;
+    BatchWorkspace bws;
+    DevBuf tmp[6];                 // rebuild / export scratch
+    uint64_t *hcounts = nullptr;   // pinned: level totals etc.
+    int num_cus = 256;
+    Profiler prof;
+};
+
+// build.hip
+void init_empty(Index &ix, hipStream_t s);
+void bulk_load(Index &ix, const uint64_t *keys, const uint64_t *vals, uint64_t n, hipStream_t s);
+void rebuild(Index &ix, hipStream_t s);  // merge + drop deleted + rebuild levels
+uint64_t export_live(Index &ix, uint64_t *okeys, uint64_t *ovals, uint64_t cap, hipStream_t s);
+void read_state(Index &ix, hipStream_t s, DevState *out);  // synchronises s
+void grow_storage(Index &ix, uint64_t need_slots, hipStream_t s);
+
+// batch.hip
+void execute_batch(Index &ix, const uint8_t *ops, const uint64_t *keys, const uint64_t *vals, uint64_t n,
+                   uint64_t *out_vals, uint8_t *out_status, hipStream_t s);
+void debug_interceptions(Index &ix, const uint64_t *keys, uint64_t n, uint64_t *icpt_keys, uint8_t *is_head,
+                         hipStream_t s);
+uint64_t count_inserts(Index &ix, const uint8_t *ops, const uint64_t *keys, uint64_t n, hipStream_t s);
+
+}  // namespace pi

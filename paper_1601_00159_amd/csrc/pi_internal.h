@@ -1,0 +1,192 @@
+// Internal definitions shared by the HIP translation units of libpi.
+// gfx950 only: wave64, 160 KB LDS per CU, 8 XCDs.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <string>
+
+#include "pi.h"
+
+namespace pi {
+
+constexpr uint64_t KEY_MAX = ~0ull;  // +infinity pad; never a valid query key
+constexpr uint32_t HEAD_SLOT = 0;    // virtual head of the storage list (key -infinity)
+constexpr int MAX_LEVELS = 33;       // level numbers 0..32 (levels 2..32 used)
+constexpr uint32_t LEVEL_PAD = 16;   // +infinity entries after the last key of a level
+
+// storage node flag bits (one byte per node)
+constexpr uint8_t META_DEL = 1;   // F_del of Algorithm 4
+constexpr uint8_t META_LINK = 2;  // successor is snext[] (else the next slot)
+
+// ---------------------------------------------------------------------------
+// Index-layer descriptor, passed to kernels by value.  Level l (2..top) has
+// n[l] keys stored at entries off[l]+1 .. off[l]+n[l] of the level arena;
+// entry off[l] is the head (its key is never compared; its down pointer is
+// the head of the level below) and LEVEL_PAD +infinity entries follow.
+struct IndexDesc {
+    uint64_t off[MAX_LEVELS];
+    uint32_t n[MAX_LEVELS];
+    uint32_t lds_off[MAX_LEVELS];  // entry offset inside the LDS copy
+    int32_t top;                   // highest non-empty level (1 = none)
+    int32_t lds_from;              // levels >= lds_from are staged in LDS
+    uint32_t lds_entries;          // entries staged (0 = none)
+    uint32_t pad_;
+};
+
+// Device-resident counters.  Written only by kernels; the host reads a copy.
+struct DevState {
+    unsigned long long nused;    // first free storage slot
+    unsigned long long n_live;   // live keys
+    unsigned long long changes;  // new nodes + live->deleted since rebuild
+    unsigned int has_links;      // some node has META_LINK set
+    unsigned int has_dead;       // some node has META_DEL set
+    // cumulative
+    unsigned long long batches, queries, hits, invalid, new_nodes, deletes, revives;
+    // current batch
+    unsigned int b_writers, b_new, b_deletes, b_revives, b_hits, b_invalid;
+    unsigned int b_n;
+    unsigned int errors;         // internal consistency failures (must stay 0)
+};
+
+// ---------------------------------------------------------------------------
+// wave64 helpers
+
+__device__ __forceinline__ int lane_id() { return __lane_id(); }
+
+// number of set bits of m below this lane
+__device__ __forceinline__ uint32_t mask_rank(uint64_t m) {
+    return __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+}
+
+__device__ __forceinline__ uint64_t ballot64(bool p) { return __ballot(p); }
+
+__device__ __forceinline__ uint32_t wave_incl_scan_u32(uint32_t x) {
+    const int lane = lane_id();
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        uint32_t y = __shfl_up(x, o, 64);
+        if (lane >= o) x += y;
+    }
+    return x;
+}
+
+__device__ __forceinline__ uint32_t wave_sum_u32(uint32_t x) {
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) x += __shfl_xor(x, o, 64);
+    return x;
+}
+
+// Block-wide exclusive scan of one u32 per thread; NT threads (multiple of
+// 64).  s_tmp must hold NT/64 + 1 words.  Returns the exclusive prefix and
+// writes the block total to *total.  Contains __syncthreads().
+template <int NT>
+__device__ __forceinline__ uint32_t block_excl_scan_u32(uint32_t x, uint32_t *s_tmp, uint32_t *total) {
+    constexpr int NW = NT / 64;
+    const int tid = threadIdx.x;
+    const int w = tid >> 6;
+    uint32_t inc = wave_incl_scan_u32(x);
+    if (lane_id() == 63) s_tmp[w] = inc;
+    __syncthreads();
+    if (tid == 0) {
+        uint32_t run = 0;
+        for (int i = 0; i < NW; i++) {
+            uint32_t t = s_tmp[i];
+            s_tmp[i] = run;
+            run += t;
+        }
+        s_tmp[NW] = run;
+    }
+    __syncthreads();
+    uint32_t r = s_tmp[w] + inc - x;
+    *total = s_tmp[NW];
+    __syncthreads();
+    return r;
+}
+
+// XCD-aware mapping of a persistent block id to a contiguous chunk: blocks
+// are dispatched round-robin over the 8 XCDs, so consecutive chunks (adjacent
+// key ranges, which share index lines) go to blocks of the same XCD and its
+// L2.  grid must be a multiple of 8 (or smaller than 8).
+__device__ __forceinline__ uint32_t xcd_chunk(uint32_t b, uint32_t grid) {
+    if (grid < 8 || (grid & 7)) return b;
+    const uint32_t per = grid >> 3;
+    return (b & 7) * per + (b >> 3);
+}
+
+// ---------------------------------------------------------------------------
+// Height rule: z = key ^ seed; splitmix64 output finalizer (Steele, Lea,
+// Flood, OOPSLA 2014); height = 1 + min(ctz(z) / log2_inv_p, max_height-1),
+// with ctz(0) = 64.  P(height >= h) = p^(h-1), the geometric law of the
+// paper's tower heights (Section 3.2), but a pure function of the key.
+__device__ __forceinline__ uint32_t tower_height(uint64_t key, uint64_t seed, uint32_t log2_inv_p,
+                                                 uint32_t max_height) {
+    uint64_t z = key ^ seed;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    z = z ^ (z >> 31);
+    uint32_t tz = z ? (uint32_t)__builtin_ctzll(z) : 64u;
+    uint32_t extra = tz / log2_inv_p;
+    if (extra > max_height - 1) extra = max_height - 1;
+    return 1 + extra;
+}
+
+// ---------------------------------------------------------------------------
+// host-side helpers (defined in runtime.cpp)
+
+struct Error {
+    pi_status code;
+    std::string msg;
+};
+
+#define PI_HIP(call)                                                                   \
+    do {                                                                               \
+        hipError_t e_ = (call);                                                        \
+        if (e_ != hipSuccess)                                                          \
+            throw ::pi::Error{PI_ERR_DEVICE, std::string(#call) + ": " + hipGetErrorString(e_)}; \
+    } while (0)
+
+#define PI_LAUNCH_CHECK() PI_HIP(hipGetLastError())
+
+// A device buffer that only grows.
+struct DevBuf {
+    void *p = nullptr;
+    size_t bytes = 0;
+    void ensure(size_t need);
+    void release();
+    template <class T> T *as() const { return reinterpret_cast<T *>(p); }
+};
+
+// ---- sort (sort.hip) ------------------------------------------------------
+struct SortWorkspace {
+    DevBuf keys[2], idx[2], tile_hist, digit_tot;
+    void ensure(uint64_t n);
+    void release();
+};
+// Stable LSD radix sort of keys (payload = input position).  When ops is not
+// null, keys whose op is > 2 sort as KEY_MAX, and b_writers of st counts the
+// valid INSERT/DELETE queries.  Returns pointers into the workspace.
+void sort_keys_with_index(SortWorkspace &ws, const uint64_t *keys, const uint8_t *ops, uint64_t n,
+                          DevState *st, hipStream_t s, const uint64_t **out_keys,
+                          const uint32_t **out_idx);
+// Same, with an explicit u32 payload.
+void sort_pairs(SortWorkspace &ws, const uint64_t *keys, const uint32_t *payload, uint64_t n,
+                hipStream_t s, const uint64_t **out_keys, const uint32_t **out_payload);
+
+// Exclusive scan of each of ncols columns of length len stored back to back
+// (column c at cols + c*len); totals[c] receives the column sum.
+void column_scan(uint32_t *cols, uint32_t ncols, uint32_t len, uint32_t *totals, hipStream_t s);
+
+// ---- scan (scan.hip) ------------------------------------------------------
+struct ScanWorkspace {
+    DevBuf tiles;
+    void ensure(uint64_t n);
+    void release();
+};
+// out[i] = sum of in[0..i) ; *d_total = sum of all (device u32).  When
+// d_enable is not null and *d_enable == 0 the kernels do nothing.
+void exclusive_scan_u32(ScanWorkspace &ws, const uint32_t *in, uint32_t *out, uint64_t n,
+                        uint32_t *d_total, const unsigned int *d_enable, hipStream_t s);
+
+}  // namespace pi

@@ -1,0 +1,162 @@
+"""Python view of one device-resident index.  PyTorch supplies device memory
+and the current HIP stream; every step runs in libpi's kernels."""
+import ctypes
+
+import numpy as np
+import torch
+
+from . import _lib
+from ._lib import check
+
+_POLICY = {"threshold": _lib.PI_REBUILD_THRESHOLD, "never": _lib.PI_REBUILD_NEVER,
+           "always": _lib.PI_REBUILD_ALWAYS}
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr()) if t is not None and t.numel() else ctypes.c_void_p(0)
+
+
+def _stream(stream=None):
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def to_device_u64(a, device="cuda"):
+    """numpy uint64 (or int) array -> int64 CUDA tensor holding the same bits."""
+    if isinstance(a, torch.Tensor):
+        assert a.dtype in (torch.int64, torch.uint64)
+        return a.to(device).view(torch.int64).contiguous()
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=np.uint64).view(np.int64)).to(device)
+
+
+def to_device_u8(a, device="cuda"):
+    if isinstance(a, torch.Tensor):
+        return a.to(device=device, dtype=torch.uint8).contiguous()
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=np.uint8)).to(device)
+
+
+def to_numpy_u64(t):
+    return t.detach().cpu().numpy().view(np.uint64)
+
+
+class Index:
+    """A skip-list index resident on one GPU (C handle from pi_create)."""
+
+    def __init__(self, device: int = 0, max_height: int = 24, log2_inv_p: int = 1,
+                 height_seed: int = 0x9E3779B97F4A7C15, rebuild_fraction: float = 0.15,
+                 rebuild_policy: str = "threshold", capacity_hint: int = 0, lds_levels: int = 0,
+                 profile: int = 0):
+        self._L = _lib.lib()
+        cfg = _lib.pi_config()
+        check(self._L.pi_config_default(ctypes.byref(cfg)))
+        cfg.device = device
+        cfg.max_height = max_height
+        cfg.log2_inv_p = log2_inv_p
+        cfg.height_seed = height_seed
+        cfg.rebuild_fraction = rebuild_fraction
+        cfg.rebuild_policy = _POLICY[rebuild_policy]
+        cfg.capacity_hint = capacity_hint
+        cfg.lds_levels = lds_levels
+        cfg.profile = profile
+        h = ctypes.c_void_p()
+        check(self._L.pi_create(ctypes.byref(cfg), ctypes.byref(h)))
+        self._h = h
+        self.device = torch.device("cuda", device)
+
+    # ---- lifecycle
+    def close(self):
+        if getattr(self, "_h", None):
+            self._L.pi_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+    def _check(self, st):
+        return check(st, self._h)
+
+    # ---- operations
+    def bulk_load(self, keys, values, stream=None):
+        k = to_device_u64(keys, self.device)
+        v = to_device_u64(values, self.device)
+        assert k.numel() == v.numel()
+        self._check(self._L.pi_bulk_load(self._h, _ptr(k), _ptr(v), k.numel(), _stream(stream)))
+
+    def execute(self, ops, keys, values=None, out_values=None, out_status=None, stream=None):
+        """Answers one batch; returns (values int64-bits tensor, status uint8 tensor)."""
+        o = to_device_u8(ops, self.device)
+        k = to_device_u64(keys, self.device)
+        n = k.numel()
+        v = to_device_u64(values, self.device) if values is not None else torch.zeros(
+            n, dtype=torch.int64, device=self.device)
+        assert o.numel() == n and v.numel() == n
+        if out_values is None:
+            out_values = torch.empty(n, dtype=torch.int64, device=self.device)
+        if out_status is None:
+            out_status = torch.empty(n, dtype=torch.uint8, device=self.device)
+        self._check(self._L.pi_execute_batch(self._h, _ptr(o), _ptr(k), _ptr(v), n, _ptr(out_values),
+                                             _ptr(out_status), _stream(stream)))
+        return out_values, out_status
+
+    def execute_raw(self, ops_t, keys_t, vals_t, out_v, out_s, stream=None):
+        """No conversions: all arguments are device tensors already."""
+        self._check(self._L.pi_execute_batch(self._h, _ptr(ops_t), _ptr(keys_t), _ptr(vals_t),
+                                             keys_t.numel(), _ptr(out_v), _ptr(out_s), _stream(stream)))
+
+    def repair(self, stream=None):
+        self._check(self._L.pi_repair(self._h, _stream(stream)))
+
+    def export(self, stream=None):
+        n = self.stats()["live_nodes"]
+        k = torch.empty(max(n, 1), dtype=torch.int64, device=self.device)
+        v = torch.empty(max(n, 1), dtype=torch.int64, device=self.device)
+        got = ctypes.c_uint64()
+        self._check(self._L.pi_export(self._h, _ptr(k), _ptr(v), n, ctypes.byref(got), _stream(stream)))
+        return k[:got.value], v[:got.value]
+
+    def stats(self):
+        s = _lib.pi_stats()
+        self._check(self._L.pi_get_stats(self._h, ctypes.byref(s)))
+        d = {f: getattr(s, f) for f, _ in _lib.pi_stats._fields_ if f != "level_size"}
+        d["level_size"] = list(s.level_size)
+        return d
+
+    def profile(self, reset: bool = False):
+        """Stage times accumulated since the last reset (index created with profile=1)."""
+        p = _lib.pi_profile()
+        self._check(self._L.pi_get_profile(self._h, ctypes.byref(p), 1 if reset else 0))
+        return {f: getattr(p, f) for f, _ in _lib.pi_profile._fields_}
+
+    def interceptions(self, keys, stream=None):
+        k = to_device_u64(keys, self.device)
+        n = k.numel()
+        ik = torch.empty(n, dtype=torch.int64, device=self.device)
+        hd = torch.empty(n, dtype=torch.uint8, device=self.device)
+        self._check(self._L.pi_debug_interceptions(self._h, _ptr(k), n, _ptr(ik), _ptr(hd), _stream(stream)))
+        return ik, hd
+
+    def level(self, level: int, stream=None):
+        n = self.stats()["level_size"][level] if level < 33 else 0
+        k = torch.empty(max(n, 1), dtype=torch.int64, device=self.device)
+        d = torch.empty(max(n, 1), dtype=torch.int32, device=self.device)
+        got = ctypes.c_uint64()
+        self._check(self._L.pi_debug_level(self._h, level, _ptr(k), _ptr(d), n, ctypes.byref(got),
+                                           _stream(stream)))
+        return k[:got.value], d[:got.value]
+
+    def sort(self, keys, stream=None):
+        k = to_device_u64(keys, self.device)
+        n = k.numel()
+        sk = torch.empty(n, dtype=torch.int64, device=self.device)
+        perm = torch.empty(n, dtype=torch.int32, device=self.device)
+        self._check(self._L.pi_debug_sort(self._h, _ptr(k), n, _ptr(sk), _ptr(perm), _stream(stream)))
+        return sk, perm

@@ -1,0 +1,84 @@
+"""The measurement byte model: the paper's worked example, and the exact
+line count against a per-query brute-force walk on small inputs."""
+import json
+import os
+
+import numpy as np
+
+from oracle.skiplist import height_rule
+from paper_1601_00159_amd import bytemodel as BM
+
+
+def test_paper_worked_example(golden_dir):
+    g = json.load(open(os.path.join(golden_dir, "cost_model_worked_example.json")))
+    il, sl = BM.paper_cost_lines(g["N"], g["P"], g["M"], g["entry_bytes"], g["node_bytes"], g["line_bytes"])
+    assert (il, sl) == (g["expected_index_lines"], g["expected_storage_lines"])
+    assert il + sl == g["expected_total_lines"]
+    size = BM.paper_index_bytes(g["N"], g["P"], g["entry_bytes"], g["node_bytes"])
+    assert round(size / 2 ** 20) == g["expected_index_size_mb"]
+
+
+def test_vectorised_heights_match_the_oracle_rule():
+    rng = np.random.default_rng(0)
+    keys = rng.integers(0, 1 << 64, size=5000, dtype=np.uint64, endpoint=False)
+    seed = 0x9E3779B97F4A7C15
+    keys[0] = np.uint64(seed)  # mixed word 0: the cap
+    for l2p in (1, 2):
+        h = BM.heights(keys, seed, l2p, 24)
+        assert h.tolist() == [height_rule(int(k), seed, l2p, 24) for k in keys]
+
+
+def _brute_force_bytes(sk, q, lds_from, level_pad=16):
+    """Walk every query one by one on the reference layout and collect the
+    touched lines in sets."""
+    h = BM.heights(sk)
+    levels = BM.build_levels(sk, h)
+    top = max(levels) if levels else 1
+    key_lines, down_lines, skey_lines, val_lines = set(), set(), set(), set()
+    lds = 0
+    for l in levels:
+        if lds_from is not None and l >= lds_from:
+            lds += (levels[l].size + 1 + level_pad) * 12
+    for x in q.tolist():
+        pos, key = 0, None
+        for l in range(top, 1, -1):
+            lk = levels[l].tolist()
+            if key is not None:
+                pos = lk.index(key) + 1
+            else:
+                pos = 0
+            staged = lds_from is not None and l >= lds_from
+            while True:
+                nxt = pos + 1
+                if not staged:
+                    key_lines.add((l, nxt // 16))
+                if nxt <= len(lk) and lk[nxt - 1] <= x:
+                    pos = nxt
+                else:
+                    break
+            if not staged:
+                down_lines.add((l, pos // 32))
+            key = lk[pos - 1] if pos > 0 else None
+        skl = sk.tolist()
+        slot = skl.index(key) + 1 if key is not None else 0
+        while True:
+            nxt = slot + 1
+            skey_lines.add(nxt // 16)
+            if nxt <= len(skl) and skl[nxt - 1] <= x:
+                slot = nxt
+            else:
+                break
+        if slot > 0 and skl[slot - 1] == x:
+            val_lines.add(slot // 16)
+    lines = len(key_lines) + len(down_lines) + len(skey_lines) + len(val_lines)
+    return lines * 128 + lds + q.size * 21
+
+
+def test_exact_model_equals_brute_force():
+    rng = np.random.default_rng(3)
+    for n_keys, n_q, lds_from in ((3000, 500, None), (3000, 2000, 5), (700, 3000, 3)):
+        sk = np.unique(rng.integers(0, 1 << 40, size=n_keys, dtype=np.uint64))
+        q = np.sort(np.concatenate([sk[rng.integers(0, sk.size, n_q // 2)],
+                                    rng.integers(0, 1 << 40, size=n_q - n_q // 2, dtype=np.uint64)]))
+        got = BM.descent_bytes(sk, q, lds_from=lds_from)
+        assert got["bytes"] == _brute_force_bytes(sk, q, lds_from), (n_keys, n_q, lds_from)

@@ -1,0 +1,324 @@
+"""GPU parity: the HIP path (through the C ABI) against the CPU oracle.
+
+Every answer is an exact integer, so every comparison is bit-exact: per-query
+(status, value) in arrival order, the final live key/value set, the index
+levels and the interceptions.
+"""
+import json
+import os
+import sys
+
+import numpy as np
+import pytest
+import torch
+
+from oracle import mapref
+from oracle.skiplist import SkipList
+from paper_1601_00159_amd import workloads as W
+from paper_1601_00159_amd._lib import PI_ERR_CAPACITY, PI_ERR_STATE, PiError
+from paper_1601_00159_amd.index import Index, to_numpy_u64
+
+pytestmark = pytest.mark.gpu
+KMAX = (1 << 64) - 1
+OPS = {"SEARCH": 0, "INSERT": 1, "DELETE": 2}
+
+
+@pytest.fixture(autouse=True)
+def _need_gpu(request):
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    print(f"\n[case] {request.node.name}", flush=True)
+
+
+def say(*a):
+    print("  ", *a, flush=True)
+
+
+def run_gpu(ix, ops, keys, vals):
+    ov, os_ = ix.execute(ops, keys, vals)
+    torch.cuda.synchronize()
+    return to_numpy_u64(ov), os_.cpu().numpy()
+
+
+def export_np(ix):
+    k, v = ix.export()
+    return to_numpy_u64(k), to_numpy_u64(v)
+
+
+def assert_same(got_v, got_s, want_v, want_s, what=""):
+    got_v, want_v = np.asarray(got_v, dtype=np.uint64), np.asarray(want_v, dtype=np.uint64)
+    got_s, want_s = np.asarray(got_s, dtype=np.uint8), np.asarray(want_s, dtype=np.uint8)
+    bad = np.nonzero((got_s != want_s) | (got_v != want_v))[0]
+    if bad.size:
+        i = int(bad[0])
+        raise AssertionError(f"{what}: {bad.size} mismatches; first at {i}: got ({got_s[i]},{got_v[i]}) "
+                             f"want ({want_s[i]},{want_v[i]})")
+
+
+# ----------------------------------------------------------------- ordering
+
+@pytest.mark.parametrize("n", [1, 2, 63, 64, 4095, 4096, 4097, 100_003, 1 << 20])
+def test_sort_is_stable_key_order(n):
+    rng = np.random.default_rng(n)
+    keys = rng.integers(0, 1 << 64, size=n, dtype=np.uint64, endpoint=False)
+    keys[rng.random(n) < 0.3] = rng.integers(0, 50, size=1, dtype=np.uint64)[0]  # many equal keys
+    keys[rng.random(n) < 0.01] = np.uint64(KMAX)
+    with Index() as ix:
+        sk, perm = ix.sort(keys)
+        torch.cuda.synchronize()
+        want = np.argsort(keys, kind="stable")
+        assert np.array_equal(perm.cpu().numpy().astype(np.int64), want)
+        assert np.array_equal(to_numpy_u64(sk), keys[want])
+
+
+# ------------------------------------------------------------ construction
+
+def test_bulk_load_export_levels_interceptions():
+    rng = np.random.default_rng(4)
+    n = 300_001
+    keys = rng.integers(0, 1 << 63, size=n, dtype=np.uint64)
+    keys[:5000] = keys[5000:10000]  # duplicates: the last occurrence wins
+    keys[7] = np.uint64(KMAX)       # skipped
+    vals = rng.integers(0, 1 << 64, size=n, dtype=np.uint64, endpoint=False)
+    uk, uv = mapref.dedupe_last(keys, vals)
+    orc = SkipList()
+    orc.bulk_load_sorted(uk, uv)
+    with Index() as ix:
+        ix.bulk_load(keys, vals)
+        ek, ev = export_np(ix)
+        assert np.array_equal(ek, uk) and np.array_equal(ev, uv)
+        st = ix.stats()
+        assert st["live_nodes"] == uk.size == st["base_nodes"]
+        prev_keys = uk
+        for lvl in range(2, 25):
+            want = orc.level_keys(lvl)
+            lk, ld = ix.level(lvl)
+            lk, ld = to_numpy_u64(lk), ld.cpu().numpy().astype(np.int64)
+            assert np.array_equal(lk, want), lvl
+            if lk.size:
+                # the down pointer of a key is its 1-based position one level below
+                # (level 2: its storage slot, base slot i holds the i-th key)
+                assert np.array_equal(prev_keys[ld - 1], lk), lvl
+            prev_keys = lk
+            assert st["level_size"][lvl] == want.size
+        # Definition 4 against the oracle
+        q = np.concatenate([uk[rng.integers(0, uk.size, 20000)],
+                            rng.integers(0, 1 << 63, size=20000, dtype=np.uint64),
+                            np.array([0, uk[0], uk[-1], (1 << 63) + 5, KMAX - 1], dtype=np.uint64)])
+        ik, hd = ix.interceptions(q)
+        ik, hd = to_numpy_u64(ik), hd.cpu().numpy()
+        for i in range(q.size):
+            w = orc.interception(int(q[i]))
+            if w is None:
+                assert hd[i] == 1, i
+            else:
+                assert hd[i] == 0 and int(ik[i]) == w, i
+        with pytest.raises(PiError) as e:
+            ix.bulk_load(keys[:10], vals[:10])
+        assert e.value.status == PI_ERR_STATE
+
+
+# --------------------------------------------------------------- golden
+
+def _golden(golden_dir, name):
+    with open(os.path.join(golden_dir, name)) as f:
+        g = json.load(f)
+    ops = np.array([OPS[o] if isinstance(o, str) else o for o, _, _ in g["batch"]], dtype=np.uint8)
+    keys = np.array([k for _, k, _ in g["batch"]], dtype=np.uint64)
+    vals = np.array([v for _, _, v in g["batch"]], dtype=np.uint64)
+    return g, ops, keys, vals
+
+
+@pytest.mark.parametrize("policy", ["never", "always"])
+@pytest.mark.parametrize("name", ["e1_duplicates_revive.json", "e2_empty_and_edges.json"])
+def test_golden(golden_dir, name, policy):
+    g, ops, keys, vals = _golden(golden_dir, name)
+    with Index(rebuild_policy=policy) as ix:
+        if g["initial"]:
+            ix.bulk_load(np.array([k for k, _ in g["initial"]], dtype=np.uint64),
+                         np.array([v for _, v in g["initial"]], dtype=np.uint64))
+        gv, gs = run_gpu(ix, ops, keys, vals)
+        assert [[int(s), int(v)] for s, v in zip(gs, gv)] == g["expected"]
+        ek, ev = export_np(ix)
+        assert [[int(k), int(v)] for k, v in zip(ek, ev)] == g["final"]
+
+
+# ------------------------------------------------------- mixed batches
+
+def _random_batch(rng, pool, n, p_invalid=0.01):
+    ops = rng.choice(np.array([0, 1, 2], dtype=np.uint8), size=n, p=[0.5, 0.3, 0.2])
+    ops[rng.random(n) < p_invalid] = 7
+    keys = pool[rng.integers(0, pool.size, size=n)]
+    keys[rng.random(n) < p_invalid] = np.uint64(KMAX)
+    vals = rng.integers(0, 1 << 64, size=n, dtype=np.uint64, endpoint=False)
+    return ops, keys, vals
+
+
+@pytest.mark.parametrize("policy", ["never", "always", "threshold"])
+def test_mixed_batches_vs_oracle(policy):
+    rng = np.random.default_rng({"never": 1, "always": 2, "threshold": 3}[policy])
+    lk = rng.integers(0, 1 << 63, size=50_000, dtype=np.uint64)
+    lv = rng.integers(0, 1 << 64, size=50_000, dtype=np.uint64, endpoint=False)
+    pool = np.concatenate([lk[:20_000], rng.integers(0, 1 << 63, size=20_000, dtype=np.uint64),
+                           np.array([0, (1 << 64) - 2], dtype=np.uint64)])
+    orc = SkipList()
+    orc.bulk_load(lk, lv)
+    with Index(rebuild_policy=policy, rebuild_fraction=0.05) as ix:
+        ix.bulk_load(lk, lv)
+        for b in range(6):
+            n = [40_000, 1, 4097, 65_536, 12_345, 40_000][b]
+            ops, keys, vals = _random_batch(rng, pool, n)
+            say(f"batch {b} n={n}")
+            wv, ws = orc.execute_batch(ops, keys, vals)
+            gv, gs = run_gpu(ix, ops, keys, vals)
+            assert_same(gv, gs, wv, ws, f"batch {b}")
+        ek, ev = export_np(ix)
+        ok, ov = orc.export()
+        assert np.array_equal(ek, ok) and np.array_equal(ev, ov)
+        st = ix.stats()
+        assert st["live_nodes"] == len(orc)
+        if policy == "always":
+            assert st["repairs"] >= 1 and st["overflow_nodes"] == 0
+        # after a rebuild the levels are the canonical ones again
+        ix.repair()
+        for lvl in range(2, 25):
+            lk2, _ = ix.level(lvl)
+            assert np.array_equal(to_numpy_u64(lk2), orc.level_keys(lvl)), lvl
+
+
+def test_hot_keys_and_revives():
+    # one key hit by many queries of every type in one batch, plus
+    # delete/insert chains spanning the whole batch
+    rng = np.random.default_rng(9)
+    lk = np.arange(1, 2001, dtype=np.uint64) * np.uint64(1000)
+    lv = lk + np.uint64(7)
+    n = 200_000
+    ops = rng.choice(np.array([0, 1, 2], dtype=np.uint8), size=n, p=[0.4, 0.3, 0.3])
+    keys = np.where(rng.random(n) < 0.7, np.uint64(5000),
+                    rng.integers(0, 2_100_000, size=n).astype(np.uint64)).astype(np.uint64)
+    vals = np.arange(n, dtype=np.uint64)
+    orc = SkipList()
+    orc.bulk_load(lk, lv)
+    wv, ws = orc.execute_batch(ops, keys, vals)
+    with Index(rebuild_policy="never") as ix:
+        ix.bulk_load(lk, lv)
+        gv, gs = run_gpu(ix, ops, keys, vals)
+        assert_same(gv, gs, wv, ws, "hot keys")
+        ek, ev = export_np(ix)
+        ok, ov = orc.export()
+        assert np.array_equal(ek, ok) and np.array_equal(ev, ov)
+        # a second batch walks the linked nodes of the first
+        ops2, keys2, vals2 = _random_batch(rng, np.concatenate([ok, keys[:1000]]), 50_000, 0.0)
+        wv, ws = orc.execute_batch(ops2, keys2, vals2)
+        gv, gs = run_gpu(ix, ops2, keys2, vals2)
+        assert_same(gv, gs, wv, ws, "after links")
+
+
+def test_edge_cases():
+    with Index(rebuild_policy="never") as ix:
+        e8 = np.zeros(0, dtype=np.uint8)
+        e64 = np.zeros(0, dtype=np.uint64)
+        gv, gs = run_gpu(ix, e8, e64, e64)                    # empty batch
+        assert gv.size == 0
+        gv, gs = run_gpu(ix, np.array([0, 2], dtype=np.uint8), np.array([5, 5], dtype=np.uint64),
+                         np.zeros(2, dtype=np.uint64))        # empty index
+        assert gs.tolist() == [0, 0] and gv.tolist() == [0, 0]
+        gv, gs = run_gpu(ix, np.array([3, 9, 1], dtype=np.uint8),
+                         np.array([1, KMAX, KMAX], dtype=np.uint64), np.array([1, 2, 3], dtype=np.uint64))
+        assert gs.tolist() == [255, 255, 255]                 # all invalid
+        ks = np.array([0, (1 << 64) - 2, 1 << 63, 0], dtype=np.uint64)
+        gv, gs = run_gpu(ix, np.array([1, 1, 1, 0], dtype=np.uint8), ks, np.array([10, 11, 12, 0], dtype=np.uint64))
+        assert gs.tolist() == [0, 0, 0, 1] and gv.tolist() == [0, 0, 0, 10]
+        ek, ev = export_np(ix)
+        assert ek.tolist() == [0, 1 << 63, (1 << 64) - 2] and ev.tolist() == [10, 12, 11]
+        assert ix.stats()["live_nodes"] == 3
+
+
+def test_capacity_error_leaves_index_unchanged():
+    rng = np.random.default_rng(12)
+    lk = rng.integers(0, 1 << 63, size=1000, dtype=np.uint64)
+    with Index(capacity_hint=1500, rebuild_policy="never") as ix:
+        ix.bulk_load(lk, lk)
+        before = export_np(ix)
+        ops = np.ones(2000, dtype=np.uint8)
+        keys = rng.integers(0, 1 << 63, size=2000, dtype=np.uint64)
+        with pytest.raises(PiError) as e:
+            ix.execute(ops, keys, keys)
+        assert e.value.status == PI_ERR_CAPACITY
+        after = export_np(ix)
+        assert np.array_equal(before[0], after[0]) and np.array_equal(before[1], after[1])
+        # a batch that fits is still accepted
+        gv, gs = run_gpu(ix, ops[:100], keys[:100], keys[:100])
+        assert (gs == 0).all()
+
+
+@pytest.mark.parametrize("lds_levels", [1, 3, 64])
+def test_results_independent_of_lds_staging(lds_levels):
+    w = W.plain_pi(scale=16)
+    b = w.batches[0]
+    orc = SkipList()
+    orc.bulk_load(w.load_keys, w.load_vals)
+    wv, ws = orc.execute_batch(b.ops, b.keys, b.vals)
+    with Index(lds_levels=lds_levels, rebuild_policy="never") as ix:
+        ix.bulk_load(w.load_keys, w.load_vals)
+        gv, gs = run_gpu(ix, b.ops, b.keys, b.vals)
+        assert_same(gv, gs, wv, ws, f"lds_levels={lds_levels}")
+
+
+# ------------------------------------------------ the named workloads
+
+def test_plain_pi_full_size():
+    """2^20 loaded keys, one 2^20-query batch, 80/10/10, every answer and the
+    final set against the Pugh oracle."""
+    w = W.plain_pi(scale=20)
+    b = w.batches[0]
+    orc = SkipList()
+    orc.bulk_load(w.load_keys, w.load_vals)
+    wv, ws = orc.execute_batch(b.ops, b.keys, b.vals)
+    with Index() as ix:
+        ix.bulk_load(w.load_keys, w.load_vals)
+        gv, gs = run_gpu(ix, b.ops, b.keys, b.vals)
+        assert_same(gv, gs, wv, ws, "plain 2^20")
+        ek, ev = export_np(ix)
+        ok, ov = orc.export()
+        assert np.array_equal(ek, ok) and np.array_equal(ev, ov)
+
+
+@pytest.mark.parametrize("theta", [None, 0.99])
+def test_read_scaling_reduced(theta):
+    w = W.read_scaling(theta, load_log2=22, query_log2=20, n_batches=2)
+    ms = mapref.MapState(w.load_keys, w.load_vals)
+    with Index() as ix:
+        ix.bulk_load(w.load_keys, w.load_vals)
+        for b in w.batches:
+            wv, ws = ms.search_batch(b.keys)
+            gv, gs = run_gpu(ix, b.ops, b.keys, b.vals)
+            assert_same(gv, gs, wv, ws, w.name)
+
+
+def test_write_skew_reduced():
+    w = W.write_skew(load_log2=20, query_log2=18, n_batches=6)
+    ms = mapref.MapState(w.load_keys, w.load_vals)
+    with Index(rebuild_fraction=0.15) as ix:
+        ix.bulk_load(w.load_keys, w.load_vals)
+        for i, b in enumerate(w.batches):
+            wv, ws = ms.apply_batch(b.ops, b.keys, b.vals)
+            gv, gs = run_gpu(ix, b.ops, b.keys, b.vals)
+            assert_same(gv, gs, wv, ws, f"{w.name} batch {i}")
+        ek, ev = export_np(ix)
+        assert np.array_equal(ek, ms.keys) and np.array_equal(ev, ms.vals)
+        assert ix.stats()["repairs"] >= 1
+
+
+def test_headline_full_size_search():
+    """2^26 loaded keys, one batch of 2^22 uniform SEARCH queries, in the
+    launch configuration the benchmark times; every answer checked."""
+    w = W.headline(None, n_batches=1)
+    ms = mapref.MapState(w.load_keys, w.load_vals)
+    b = w.batches[0]
+    wv, ws = ms.search_batch(b.keys)
+    with Index() as ix:
+        ix.bulk_load(w.load_keys, w.load_vals)
+        gv, gs = run_gpu(ix, b.ops, b.keys, b.vals)
+        assert_same(gv, gs, wv, ws, w.name)
+        assert (gs == 1).all()
