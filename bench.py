@@ -90,6 +90,11 @@ def main():
     ap.add_argument("--batch-log2", type=int, default=22)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-bytemodel", action="store_true")
+    ap.add_argument("--calibrate-copy-mib", type=int, default=0,
+                    help="run one plain device copy of this size first (counter calibration)")
+    ap.add_argument("--queries-per-lane", type=int, default=0)
+    ap.add_argument("--blocks-per-cu", type=int, default=0)
+    ap.add_argument("--lds-budget", type=int, default=0)
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the index shards by key range "
@@ -117,7 +122,20 @@ def main():
     out_v = torch.empty(Q, dtype=torch.int64, device=dev)
     out_s = torch.empty(Q, dtype=torch.uint8, device=dev)
 
-    ix = Index(device=0, profile=1)
+    if args.calibrate_copy_mib:
+        # a plain copy of known size: its FETCH_SIZE / WRITE_SIZE counters
+        # calibrate the counters read for the index kernels
+        nb = args.calibrate_copy_mib << 20
+        src = torch.empty(nb, dtype=torch.uint8, device=dev).fill_(1)
+        dst = torch.empty(nb, dtype=torch.uint8, device=dev)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
+        log(f"calibration copy of {args.calibrate_copy_mib} MiB done")
+
+    ix = Index(device=0, profile=1, queries_per_lane=args.queries_per_lane, blocks_per_cu=args.blocks_per_cu,
+               lds_budget=args.lds_budget)
     t0 = time.perf_counter()
     ix.bulk_load(w.load_keys, w.load_vals)
     torch.cuda.synchronize()

@@ -30,7 +30,8 @@ class pi_config(ctypes.Structure):
                 ("height_seed", ctypes.c_uint64), ("rebuild_fraction", ctypes.c_float),
                 ("rebuild_policy", ctypes.c_uint32), ("capacity_hint", ctypes.c_uint64),
                 ("lds_levels", ctypes.c_uint32), ("profile", ctypes.c_uint32),
-                ("reserved", ctypes.c_uint32 * 6)]
+                ("queries_per_lane", ctypes.c_uint32), ("blocks_per_cu", ctypes.c_uint32),
+                ("lds_budget", ctypes.c_uint32), ("reserved", ctypes.c_uint32 * 3)]
 
 
 class pi_profile(ctypes.Structure):

@@ -89,6 +89,7 @@ void release_all(pi::Index &ix) {
     ix.arena_key.release();
     ix.arena_down.release();
     ix.sortws.release();
+    ix.msdws.release();
     ix.scanws.release();
     ix.bws.release();
     for (auto &b : ix.tmp) b.release();
@@ -147,6 +148,9 @@ pi_status pi_config_default(pi_config *cfg) {
     cfg->capacity_hint = 0;
     cfg->lds_levels = 0;
     cfg->profile = 0;
+    cfg->queries_per_lane = 0;
+    cfg->blocks_per_cu = 0;
+    cfg->lds_budget = 0;
     return PI_OK;
 }
 
@@ -171,7 +175,10 @@ pi_status pi_create(const pi_config *cfg_in, pi_index **out) {
     }
     if (cfg.max_height < 2 || cfg.max_height > 32 || cfg.log2_inv_p < 1 || cfg.log2_inv_p > 8 ||
         !(cfg.rebuild_fraction >= 0.0f) || cfg.rebuild_policy > PI_REBUILD_ALWAYS ||
-        cfg.capacity_hint > (1ull << 32) - 16) {
+        cfg.capacity_hint > (1ull << 32) - 64 ||
+        (cfg.queries_per_lane != 0 && cfg.queries_per_lane != 1 && cfg.queries_per_lane != 2 &&
+         cfg.queries_per_lane != 4) ||
+        cfg.lds_budget > 5000) {
         set_err("invalid pi_config field");
         return PI_ERR_INVALID_ARG;
     }
@@ -372,7 +379,7 @@ pi_status pi_debug_sort(pi_index *h, const uint64_t *d_keys, uint64_t n, uint64_
         hipStream_t s = (hipStream_t)stream;
         const uint64_t *sk = nullptr;
         const uint32_t *si = nullptr;
-        pi::sort_keys_with_index(ix.sortws, d_keys, nullptr, n, nullptr, s, &sk, &si);
+        pi::sort_batch_by_range(ix.sortws, ix.msdws, d_keys, nullptr, n, nullptr, s, &sk, &si);
         PI_HIP(hipMemcpyAsync(d_sorted_keys, sk, n * 8, hipMemcpyDeviceToDevice, s));
         PI_HIP(hipMemcpyAsync(d_perm, si, n * 4, hipMemcpyDeviceToDevice, s));
         return PI_OK;

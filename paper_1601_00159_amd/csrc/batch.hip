@@ -41,38 +41,144 @@ constexpr uint32_t WALK_LIMIT = 1u << 24;  // bound on storage nodes walked by o
 
 // ---------------------------------------------------------------- descent --
 
-// Walks the index layer for key q.  Returns the storage slot of the
-// interception (HEAD_SLOT if no indexed key is <= q) and its key.
-__device__ __forceinline__ uint32_t descend_index(uint64_t q, const IndexDesc &d, const uint64_t *__restrict__ lkey,
-                                                  const uint32_t *__restrict__ ldown, const uint64_t *s_k,
-                                                  const uint32_t *s_d, uint64_t &ikey) {
-    uint32_t pos = 0;  // head entry of the top level
-    uint64_t last = 0;
+// One level of the descent (Algorithm 2) for one query.  pos is the entry of
+// the key the query stands on (present one level up too), or the head.  The
+// first two keys after pos and the down pointers of pos, pos+1, pos+2 are
+// requested together -- the paper's wide compare of an entry, with the routing
+// table replaced by the down array -- so the common case costs one memory
+// round trip; a longer run of keys <= q continues one key at a time.  Reads
+// stay inside the level's +infinity pad because q < +infinity.
+struct Step {
+    uint64_t k1, k2;
+    uint32_t d0, d1, d2;
+};
+
+template <class KP, class DP>
+__device__ __forceinline__ Step step_load(KP K, DP D, uint32_t pos) {
+    Step s;
+    s.k1 = K[pos + 1];
+    s.k2 = K[pos + 2];
+    s.d0 = D[pos];
+    s.d1 = D[pos + 1];
+    s.d2 = D[pos + 2];
+    return s;
+}
+
+template <class KP, class DP>
+__device__ __forceinline__ uint32_t step_finish(KP K, DP D, const Step &s, uint64_t q, uint32_t pos,
+                                                uint64_t &last) {
+    if (s.k1 > q) return s.d0;
+    last = s.k1;
+    if (s.k2 > q) return s.d1;
+    last = s.k2;
+    uint32_t p = pos + 2, dp = s.d2;
+    for (;;) {
+        const uint64_t kn = K[p + 1];
+        const uint32_t dn = D[p + 1];
+        if (kn > q) return dp;
+        last = kn;
+        p++;
+        dp = dn;
+    }
+}
+
+// Level step in global memory with an 8-entry window.  Keys are read as
+// 16-byte pairs starting at the even entry at or below pos+1 (levels start on
+// 128-byte lines), down pointers as 16-byte quads starting at the multiple of
+// 4 at or below pos: one round trip covers keys pos+1 .. pos+7 (at least) and
+// down pointers pos .. pos+8.  With p = 1/2 a run of 7 keys <= q on one level
+// is rare enough that a wave of queries almost never waits for a second trip.
+// Length of the run of keys <= q starting at keys[skip] (only the leading
+// run counts: entries after the first key > q may hold anything).
+__device__ __forceinline__ uint32_t leading_le(const uint64_t (&keys)[8], uint32_t skip, uint64_t q) {
+    uint32_t m = 0;
+#pragma unroll
+    for (int i = 0; i < 8; i++) m |= (keys[i] <= q ? 1u : 0u) << i;
+    m >>= skip;
+    return (uint32_t)__builtin_ctz(~m);
+}
+
+struct Wide {
+    ulonglong2 kp[4];
+    uint4 dq[3];
+};
+
+__device__ __forceinline__ Wide wide_load(const uint64_t *__restrict__ K, const uint32_t *__restrict__ D,
+                                          uint32_t pos) {
+    Wide w;
+    const ulonglong2 *K2 = reinterpret_cast<const ulonglong2 *>(K + ((pos + 1) & ~1u));
+    const uint4 *D4 = reinterpret_cast<const uint4 *>(D + (pos & ~3u));
+#pragma unroll
+    for (int i = 0; i < 4; i++) w.kp[i] = K2[i];
+#pragma unroll
+    for (int i = 0; i < 3; i++) w.dq[i] = D4[i];
+    return w;
+}
+
+__device__ __forceinline__ uint32_t wide_finish(const uint64_t *__restrict__ K, const uint32_t *__restrict__ D,
+                                                const Wide &w, uint64_t q, uint32_t pos, uint64_t &last) {
+    const uint64_t keys[8] = {w.kp[0].x, w.kp[0].y, w.kp[1].x, w.kp[1].y,
+                              w.kp[2].x, w.kp[2].y, w.kp[3].x, w.kp[3].y};
+    const uint32_t skip = (pos + 1) & 1u;  // entry pos+1 is keys[skip]
+    const uint32_t cnt = leading_le(keys, skip, q);
+    uint32_t p = pos + cnt;
+    if (cnt > 0) {
+        const uint32_t li = skip + cnt - 1;
+        uint64_t lk = keys[0];
+#pragma unroll
+        for (int i = 1; i < 8; i++) lk = ((uint32_t)i == li) ? keys[i] : lk;
+        last = lk;
+    }
+    if (cnt < 8 - skip) {
+        const uint32_t downs[12] = {w.dq[0].x, w.dq[0].y, w.dq[0].z, w.dq[0].w, w.dq[1].x, w.dq[1].y,
+                                    w.dq[1].z, w.dq[1].w, w.dq[2].x, w.dq[2].y, w.dq[2].z, w.dq[2].w};
+        const uint32_t di = p - (pos & ~3u);
+        uint32_t d = downs[0];
+#pragma unroll
+        for (int i = 1; i < 12; i++) d = ((uint32_t)i == di) ? downs[i] : d;
+        return d;
+    }
+    for (;;) {  // long run of keys <= q: one key at a time
+        const uint64_t kn = K[p + 1];
+        if (kn > q) return D[p];
+        last = kn;
+        p++;
+    }
+}
+
+// Descends QPL independent queries together, level by level (the group
+// processing of Section 4.3.4): every query's loads for a level are issued
+// before any of them is used.  Returns, per query, the storage slot of the
+// interception (HEAD_SLOT when no indexed key is <= q) and its key.
+template <int QPL>
+__device__ __forceinline__ void descend_index(const uint64_t (&q)[QPL], const IndexDesc &d,
+                                              const uint64_t *__restrict__ lkey, const uint32_t *__restrict__ ldown,
+                                              const uint64_t *s_k, const uint32_t *s_d, uint32_t (&pos)[QPL],
+                                              uint64_t (&last)[QPL]) {
+#pragma unroll
+    for (int j = 0; j < QPL; j++) {
+        pos[j] = 0;
+        last[j] = 0;
+    }
     for (int l = d.top; l >= 2; l--) {
+        Step st[QPL];
         if (l >= d.lds_from) {
             const uint64_t *K = s_k + d.lds_off[l];
             const uint32_t *D = s_d + d.lds_off[l];
-            uint64_t kn = K[pos + 1];
-            while (kn <= q) {
-                pos++;
-                last = kn;
-                kn = K[pos + 1];
-            }
-            pos = D[pos];
+#pragma unroll
+            for (int j = 0; j < QPL; j++) st[j] = step_load(K, D, pos[j]);
+#pragma unroll
+            for (int j = 0; j < QPL; j++) pos[j] = step_finish(K, D, st[j], q[j], pos[j], last[j]);
         } else {
             const uint64_t *K = lkey + d.off[l];
             const uint32_t *D = ldown + d.off[l];
-            uint64_t kn = K[pos + 1];
-            while (kn <= q) {
-                pos++;
-                last = kn;
-                kn = K[pos + 1];
-            }
-            pos = D[pos];
+            Wide wd[QPL];
+#pragma unroll
+            for (int j = 0; j < QPL; j++) wd[j] = wide_load(K, D, pos[j]);
+#pragma unroll
+            for (int j = 0; j < QPL; j++) pos[j] = wide_finish(K, D, wd[j], q[j], pos[j], last[j]);
         }
     }
-    ikey = last;
-    return pos;
 }
 
 __device__ __forceinline__ void stage_levels(const IndexDesc &d, const uint64_t *__restrict__ lkey,
@@ -89,8 +195,83 @@ __device__ __forceinline__ void stage_levels(const IndexDesc &d, const uint64_t 
     __syncthreads();
 }
 
+struct Found {
+    uint32_t node;   // last storage node with key <= q (HEAD_SLOT if none)
+    uint32_t next;   // its successor
+    bool exists;     // node holds q
+    bool live;       // ... and is not flagged deleted
+    uint64_t val;    // its value when live
+};
+
+// getNode of Algorithm 4: from the interception, follow the storage list to
+// the last node whose key is <= q, then read its value.  Without linked nodes
+// the successor of a base node is the next slot, so a window of keys is read
+// at once.
+__device__ __forceinline__ Found walk_storage(uint64_t q, uint32_t cur, uint64_t ck, bool links, bool dead,
+                                              const uint64_t *__restrict__ skey, const uint64_t *__restrict__ sval,
+                                              const uint32_t *__restrict__ snext,
+                                              const uint8_t *__restrict__ smeta, unsigned int *errors) {
+    Found f;
+    uint8_t mc = 0;
+    if (!links) {
+        // base nodes only: the successor of slot i is i+1; same 8-entry window
+        // as the index levels, then the value of the node found
+        const ulonglong2 *S2 = reinterpret_cast<const ulonglong2 *>(skey + ((cur + 1) & ~1u));
+        ulonglong2 kp[4];
+#pragma unroll
+        for (int i = 0; i < 4; i++) kp[i] = S2[i];
+        const uint64_t keys[8] = {kp[0].x, kp[0].y, kp[1].x, kp[1].y, kp[2].x, kp[2].y, kp[3].x, kp[3].y};
+        const uint32_t skip = (cur + 1) & 1u;
+        const uint32_t cnt = leading_le(keys, skip, q);  // stops at the tail's +infinity
+        if (cnt > 0) {
+            const uint32_t li = skip + cnt - 1;
+            uint64_t lk = keys[0];
+#pragma unroll
+            for (int i = 1; i < 8; i++) lk = ((uint32_t)i == li) ? keys[i] : lk;
+            ck = lk;
+        }
+        cur += cnt;
+        if (cnt == 8 - skip) {
+            for (uint32_t steps = 0;; steps++) {
+                if (steps >= WALK_LIMIT) {
+                    atomicAdd(errors, 1u);
+                    break;
+                }
+                const uint64_t kn = skey[cur + 1];
+                if (kn > q) break;
+                cur++;
+                ck = kn;
+            }
+        }
+        if (dead && cur != HEAD_SLOT && ck == q) mc = smeta[cur];
+        f.next = cur + 1;
+    } else {
+        uint32_t nxt = cur + 1;
+        for (uint32_t steps = 0;; steps++) {
+            if (steps >= WALK_LIMIT) {  // a well-formed list never gets here
+                atomicAdd(errors, 1u);
+                break;
+            }
+            mc = smeta[cur];
+            nxt = (mc & META_LINK) ? snext[cur] : cur + 1;
+            const uint64_t kn = skey[nxt];
+            if (kn > q) break;
+            cur = nxt;
+            ck = kn;
+        }
+        f.next = nxt;
+    }
+    f.node = cur;
+    f.exists = cur != HEAD_SLOT && ck == q;
+    f.live = f.exists && !(mc & META_DEL);
+    f.val = f.live ? sval[cur] : 0;
+    return f;
+}
+
 // MODE 0: sorted batch.  MODE 1: interception of arbitrary keys (inspection).
-template <int MODE>
+// Each block owns a contiguous range of tiles of DT*QPL sorted queries; a lane
+// carries QPL queries of a tile (rows of DT) through the descent together.
+template <int MODE, int QPL>
 __global__ __launch_bounds__(DT) void k_descend(IndexDesc desc, const uint64_t *__restrict__ lkey,
                                                 const uint32_t *__restrict__ ldown, const uint64_t *__restrict__ skey,
                                                 const uint64_t *__restrict__ sval, const uint32_t *__restrict__ snext,
@@ -108,67 +289,55 @@ __global__ __launch_bounds__(DT) void k_descend(IndexDesc desc, const uint64_t *
     const bool links = MODE == 0 && st->has_links != 0;
     const bool dead = MODE == 0 && st->has_dead != 0;
 
-    const uint32_t ntiles = (n + DT - 1) / DT;
+    constexpr uint32_t TQ = DT * QPL;
+    const uint32_t ntiles = (n + TQ - 1) / TQ;
     const uint32_t c = xcd_chunk(blockIdx.x, gridDim.x);
     const uint32_t t0 = (uint32_t)((uint64_t)c * ntiles / gridDim.x);
     const uint32_t t1 = (uint32_t)((uint64_t)(c + 1) * ntiles / gridDim.x);
     uint32_t hits = 0, invalid = 0;
     for (uint32_t t = t0; t < t1; t++) {
-        const uint32_t i = t * DT + threadIdx.x;
-        if (i >= n) continue;
-        uint64_t q = sk[i];
-        if (MODE == 1) {
-            if (q == KEY_MAX) q = KEY_MAX - 1;  // +infinity is never indexed; keep the scan inside the pads
-            uint64_t ik = 0;
-            const uint32_t slot = descend_index(q, desc, lkey, ldown, s_k, s_d, ik);
-            out_vals[i] = slot == HEAD_SLOT ? 0 : ik;
-            out_status[i] = slot == HEAD_SLOT ? 1 : 0;
-            continue;
+        uint64_t q[QPL];
+        uint32_t idx[QPL];
+#pragma unroll
+        for (int j = 0; j < QPL; j++) {
+            idx[j] = t * TQ + j * DT + threadIdx.x;
+            // past the end or invalid: descend as the largest valid key (stays
+            // inside the pads), answer nothing
+            q[j] = idx[j] < n ? sk[idx[j]] : KEY_MAX;
         }
-        const uint32_t id = sidx[i];
-        if (q == KEY_MAX) {
-            out_vals[id] = 0;
-            out_status[id] = PI_R_INVALID;
-            invalid++;
-            continue;
-        }
-        uint64_t ck = 0;
-        uint32_t cur = descend_index(q, desc, lkey, ldown, s_k, s_d, ck);
-        // storage walk to the last node with key <= q
-        uint32_t nxt;
-        uint8_t mc = 0;
-        for (uint32_t steps = 0;; steps++) {
-            if (steps >= WALK_LIMIT) {  // a well-formed list never gets here
-                atomicAdd(&st->errors, 1u);
-                break;
+        uint64_t qd[QPL];
+#pragma unroll
+        for (int j = 0; j < QPL; j++) qd[j] = q[j] == KEY_MAX ? KEY_MAX - 1 : q[j];
+        uint32_t pos[QPL];
+        uint64_t ik[QPL];
+        descend_index<QPL>(qd, desc, lkey, ldown, s_k, s_d, pos, ik);
+#pragma unroll
+        for (int j = 0; j < QPL; j++) {
+            const uint32_t i = idx[j];
+            if (i >= n) continue;
+            if (MODE == 1) {
+                out_vals[i] = pos[j] == HEAD_SLOT ? 0 : ik[j];
+                out_status[i] = pos[j] == HEAD_SLOT ? 1 : 0;
+                continue;
             }
-            nxt = cur + 1;
-            if (links) {
-                mc = smeta[cur];
-                if (mc & META_LINK) nxt = snext[cur];
+            const uint32_t id = sidx[i];
+            if (q[j] == KEY_MAX) {
+                out_vals[id] = 0;
+                out_status[id] = PI_R_INVALID;
+                invalid++;
+                continue;
             }
-            const uint64_t kn = skey[nxt];
-            if (kn > q) break;
-            cur = nxt;
-            ck = kn;
-        }
-        const bool exists = cur != HEAD_SLOT && ck == q;
-        bool live = false;
-        uint64_t v = 0;
-        if (exists) {
-            if (dead && !links) mc = smeta[cur];
-            live = !(mc & META_DEL);
-            if (live) v = sval[cur];
-        }
-        if (!mixed) {
-            out_vals[id] = v;
-            out_status[id] = live ? PI_R_PRESENT : PI_R_ABSENT;
-            hits += live;
-        } else {
-            res_val[i] = v;
-            res_flags[i] = (uint8_t)((exists ? 1 : 0) | (live ? 2 : 0));
-            loc[i] = cur;
-            locnext[i] = nxt;
+            const Found f = walk_storage(q[j], pos[j], ik[j], links, dead, skey, sval, snext, smeta, &st->errors);
+            if (!mixed) {
+                out_vals[id] = f.val;
+                out_status[id] = f.live ? PI_R_PRESENT : PI_R_ABSENT;
+                hits += f.live;
+            } else {
+                res_val[i] = f.val;
+                res_flags[i] = (uint8_t)((f.exists ? 1 : 0) | (f.live ? 2 : 0));
+                loc[i] = f.node;
+                locnext[i] = f.next;
+            }
         }
     }
     if (MODE == 0) {
@@ -447,13 +616,43 @@ __global__ void k_zero_u32(unsigned int *p) {
 
 uint32_t blocks_for(uint64_t n, int t) { return (uint32_t)((n + t - 1) / t); }
 
-uint32_t descent_grid(const Index &ix, uint64_t n) {
-    const uint32_t ntiles = blocks_for(n, DT);
-    // persistent blocks: enough to fill every CU several times over
-    uint32_t g = (uint32_t)ix.num_cus * 8;
+template <int MODE, int QPL>
+void launch_descend_q(Index &ix, hipStream_t s, const uint64_t *sk, const uint32_t *sidx, uint64_t n,
+                      uint64_t *out_vals, uint8_t *out_status, uint64_t *res_val, uint8_t *res_flags, uint32_t *loc,
+                      uint32_t *locnext) {
+    const IndexDesc &d = ix.desc;
+    const size_t lds = (size_t)d.lds_entries * 12;
+    const uint32_t ntiles = blocks_for(n, DT * QPL);
+    // persistent blocks: as many as can be resident at once
+    int per_cu = 0;
+    PI_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_descend<MODE, QPL>, DT, lds));
+    if (ix.cfg.blocks_per_cu) per_cu = std::min<int>(per_cu, (int)ix.cfg.blocks_per_cu);
+    uint32_t g = (uint32_t)ix.num_cus * (uint32_t)std::max(per_cu, 1);
     if (g > ntiles) g = ntiles;
     if (g >= 8) g &= ~7u;
-    return g ? g : 1;
+    if (!g) g = 1;
+    hipLaunchKernelGGL((k_descend<MODE, QPL>), dim3(g), dim3(DT), lds, s, d, ix.arena_key.as<uint64_t>(),
+                       ix.arena_down.as<uint32_t>(), ix.st.key.as<uint64_t>(), ix.st.val.as<uint64_t>(),
+                       ix.st.next.as<uint32_t>(), ix.st.meta.as<uint8_t>(), sk, sidx, (uint32_t)n, ix.dstate,
+                       out_vals, out_status, res_val, res_flags, loc, locnext);
+    PI_LAUNCH_CHECK();
+}
+
+template <int MODE>
+void launch_descend(Index &ix, hipStream_t s, const uint64_t *sk, const uint32_t *sidx, uint64_t n,
+                    uint64_t *out_vals, uint8_t *out_status, uint64_t *res_val, uint8_t *res_flags, uint32_t *loc,
+                    uint32_t *locnext) {
+    switch (ix.cfg.queries_per_lane) {
+        case 1:
+            launch_descend_q<MODE, 1>(ix, s, sk, sidx, n, out_vals, out_status, res_val, res_flags, loc, locnext);
+            break;
+        case 4:
+            launch_descend_q<MODE, 4>(ix, s, sk, sidx, n, out_vals, out_status, res_val, res_flags, loc, locnext);
+            break;
+        default:
+            launch_descend_q<MODE, 2>(ix, s, sk, sidx, n, out_vals, out_status, res_val, res_flags, loc, locnext);
+            break;
+    }
 }
 
 }  // namespace
@@ -511,17 +710,12 @@ void execute_batch(Index &ix, const uint8_t *ops, const uint64_t *keys, const ui
     mark(0);
     hipLaunchKernelGGL(k_batch_begin, dim3(1), dim3(64), 0, s, st, (uint32_t)n);
     PI_LAUNCH_CHECK();
-    sort_keys_with_index(ix.sortws, keys, ops, n, st, s, &sk, &sidx);
+    sort_batch_by_range(ix.sortws, ix.msdws, keys, ops, n, st, s, &sk, &sidx);
     mark(1);
 
     BatchWorkspace &w = ix.bws;
-    const IndexDesc &d = ix.desc;
-    const size_t lds = (size_t)d.lds_entries * 12;
-    hipLaunchKernelGGL(k_descend<0>, dim3(descent_grid(ix, n)), dim3(DT), lds, s, d, ix.arena_key.as<uint64_t>(),
-                       ix.arena_down.as<uint32_t>(), ix.st.key.as<uint64_t>(), ix.st.val.as<uint64_t>(),
-                       ix.st.next.as<uint32_t>(), ix.st.meta.as<uint8_t>(), sk, sidx, (uint32_t)n, st, out_vals,
-                       out_status, w.res_val.as<uint64_t>(), w.res_flags.as<uint8_t>(), w.loc.as<uint32_t>(),
-                       w.locnext.as<uint32_t>());
+    launch_descend<0>(ix, s, sk, sidx, n, out_vals, out_status, w.res_val.as<uint64_t>(), w.res_flags.as<uint8_t>(),
+                      w.loc.as<uint32_t>(), w.locnext.as<uint32_t>());
     PI_LAUNCH_CHECK();
     mark(2);
 
@@ -602,13 +796,7 @@ void Profiler::release() {
 
 void debug_interceptions(Index &ix, const uint64_t *keys, uint64_t n, uint64_t *icpt_keys, uint8_t *is_head,
                          hipStream_t s) {
-    const IndexDesc &d = ix.desc;
-    const size_t lds = (size_t)d.lds_entries * 12;
-    hipLaunchKernelGGL(k_descend<1>, dim3(descent_grid(ix, n)), dim3(DT), lds, s, d, ix.arena_key.as<uint64_t>(),
-                       ix.arena_down.as<uint32_t>(), ix.st.key.as<uint64_t>(), ix.st.val.as<uint64_t>(),
-                       ix.st.next.as<uint32_t>(), ix.st.meta.as<uint8_t>(), keys, nullptr, (uint32_t)n, ix.dstate,
-                       icpt_keys, is_head, nullptr, nullptr, nullptr, nullptr);
-    PI_LAUNCH_CHECK();
+    launch_descend<1>(ix, s, keys, nullptr, n, icpt_keys, is_head, nullptr, nullptr, nullptr, nullptr);
 }
 
 }  // namespace pi

@@ -254,12 +254,15 @@ uint32_t blocks_for(uint64_t n, int t) { return (uint32_t)((n + t - 1) / t); }
 
 }  // namespace
 
+// STORAGE_SLACK slots past the capacity keep the speculative reads of the
+// storage walk (up to two slots past a node) inside the allocation.
 void Storage::alloc(uint64_t c) {
     cap = c;
-    key.ensure(c * sizeof(uint64_t));
-    val.ensure(c * sizeof(uint64_t));
-    next.ensure(c * sizeof(uint32_t));
-    meta.ensure(c * sizeof(uint8_t));
+    const uint64_t phys = c + STORAGE_SLACK;
+    key.ensure(phys * sizeof(uint64_t));
+    val.ensure(phys * sizeof(uint64_t));
+    next.ensure(phys * sizeof(uint32_t));
+    meta.ensure(phys * sizeof(uint8_t));
 }
 
 void Storage::release() {
@@ -319,7 +322,7 @@ static void build_levels(Index &ix, hipStream_t s) {
         }
         // upper levels kept in LDS by the descent (Section 5.1 notes the top
         // levels are cache resident anyway; Section 7 proposes pinning them)
-        const uint32_t budget = 2048;  // entries: 24 KB of LDS per block
+        const uint32_t budget = ix.cfg.lds_budget ? ix.cfg.lds_budget : 4096;  // 4096 entries: 48 KB per block
         uint32_t used = 0;
         int from = d.top + 1;
         const uint32_t want = ix.cfg.lds_levels ? ix.cfg.lds_levels : 64u;

@@ -65,6 +65,7 @@ struct Index {
     bool state_enqueued = false;
 
     SortWorkspace sortws;
+    MsdWorkspace msdws;
     ScanWorkspace scanws;
     BatchWorkspace bws;
     DevBuf tmp[6];                 // rebuild / export scratch

@@ -15,6 +15,7 @@ constexpr uint64_t KEY_MAX = ~0ull;  // +infinity pad; never a valid query key
 constexpr uint32_t HEAD_SLOT = 0;    // virtual head of the storage list (key -infinity)
 constexpr int MAX_LEVELS = 33;       // level numbers 0..32 (levels 2..32 used)
 constexpr uint32_t LEVEL_PAD = 16;   // +infinity entries after the last key of a level
+constexpr uint64_t STORAGE_SLACK = 16;  // allocated storage slots beyond the capacity
 
 // storage node flag bits (one byte per node)
 constexpr uint8_t META_DEL = 1;   // F_del of Algorithm 4
@@ -132,8 +133,25 @@ __device__ __forceinline__ uint32_t tower_height(uint64_t key, uint64_t seed, ui
     return 1 + extra;
 }
 
+// Key -> 24-bit position inside the batch's key span [lo, ...]: the top 24
+// significant bits of key - lo (keys below lo map to 0, above the span to
+// 2^24-1).  Monotone in the key, so ordering by it, then by key among equal
+// positions, orders by key.
+constexpr uint32_t RANGE_BITS = 24;
+struct RangeMap {
+    uint64_t lo;
+    uint32_t shift;
+    uint32_t pad_;
+};
+
+__device__ __forceinline__ uint32_t range_pos(uint64_t k, const RangeMap &m) {
+    if (k <= m.lo) return 0;
+    const uint64_t r = (k - m.lo) >> m.shift;
+    return r > ((1u << RANGE_BITS) - 1) ? ((1u << RANGE_BITS) - 1) : (uint32_t)r;
+}
+
 // ---------------------------------------------------------------------------
-// host-side helpers (defined in runtime.cpp)
+// host-side helpers
 
 struct Error {
     pi_status code;
@@ -173,6 +191,23 @@ void sort_keys_with_index(SortWorkspace &ws, const uint64_t *keys, const uint8_t
 // Same, with an explicit u32 payload.
 void sort_pairs(SortWorkspace &ws, const uint64_t *keys, const uint32_t *payload, uint64_t n,
                 hipStream_t s, const uint64_t **out_keys, const uint32_t **out_payload);
+
+// Ordering of a query batch: partition by key range, then LDS sort of each
+// range (msd.hip).  Same contract as sort_keys_with_index.
+struct MsdWorkspace {
+    DevBuf partials, map, big, nbig, dirty;
+    void ensure(uint64_t n);
+    void release();
+};
+void sort_batch_by_range(SortWorkspace &ws, MsdWorkspace &mw, const uint64_t *keys, const uint8_t *ops, uint64_t n,
+                         DevState *st, hipStream_t s, const uint64_t **out_keys, const uint32_t **out_idx);
+
+// One stable 8-bit LSD pass (hist, column scan, scatter).  The digit is
+// (key >> shift) & 255, or, when map is not null, (range_pos(key) >> shift)
+// & 255.  idx_in null = input positions; ops not null = keys whose op is
+// invalid count as KEY_MAX, and st->b_writers counts INSERT/DELETE queries.
+void radix_pass(SortWorkspace &ws, const uint64_t *kin, const uint32_t *iin, const uint8_t *ops, uint32_t n,
+                uint32_t shift, const RangeMap *map, DevState *st, uint64_t *kout, uint32_t *iout, hipStream_t s);
 
 // Exclusive scan of each of ncols columns of length len stored back to back
 // (column c at cols + c*len); totals[c] receives the column sum.

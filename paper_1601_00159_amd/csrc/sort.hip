@@ -18,21 +18,41 @@
 namespace pi {
 namespace {
 
-constexpr int ST = 256;           // threads per block
-constexpr int SI = 16;            // items per thread
+constexpr int ST = 512;           // threads per block
+constexpr int SI = 8;             // items per thread
 constexpr int STILE = ST * SI;    // items per tile
+constexpr int CT = 256;           // column-scan block
 constexpr int RBITS = 8;
 constexpr int R = 1 << RBITS;     // digits per pass
 constexpr int NW = ST / 64;       // waves per block
 
-static_assert(R == ST, "one digit per thread in the per-digit steps");
+static_assert(R <= ST, "one digit per thread in the per-digit steps");
+
+struct Digit {
+    RangeMap map;
+    uint32_t shift;
+    bool ranged;
+    __device__ __forceinline__ uint32_t operator()(uint64_t k) const {
+        const uint64_t x = ranged ? (uint64_t)range_pos(k, map) : k;
+        return (uint32_t)(x >> shift) & (R - 1);
+    }
+};
+
+__device__ __forceinline__ Digit make_digit(uint32_t shift, const RangeMap *map) {
+    Digit d;
+    d.shift = shift;
+    d.ranged = map != nullptr;
+    if (map) d.map = *map;
+    return d;
+}
 
 __global__ __launch_bounds__(ST) void k_hist(const uint64_t *__restrict__ keys, const uint8_t *__restrict__ ops,
-                                             uint32_t n, uint32_t shift, uint32_t *__restrict__ tile_hist,
-                                             uint32_t ntiles, DevState *st) {
+                                             uint32_t n, uint32_t shift, const RangeMap *map,
+                                             uint32_t *__restrict__ tile_hist, uint32_t ntiles, DevState *st) {
     __shared__ uint32_t h[R];
+    const Digit dg = make_digit(shift, map);
     const int tid = threadIdx.x;
-    h[tid] = 0;
+    if (tid < R) h[tid] = 0;
     __syncthreads();
     const uint32_t base = blockIdx.x * STILE;
     uint32_t writers = 0;
@@ -48,23 +68,23 @@ __global__ __launch_bounds__(ST) void k_hist(const uint64_t *__restrict__ keys, 
                 else if (op != PI_OP_SEARCH && k != KEY_MAX)
                     writers++;
             }
-            atomicAdd(&h[(uint32_t)(k >> shift) & (R - 1)], 1u);
+            atomicAdd(&h[dg(k)], 1u);
         }
     }
     __syncthreads();
-    tile_hist[(size_t)tid * ntiles + blockIdx.x] = h[tid];
+    if (tid < R) tile_hist[(size_t)tid * ntiles + blockIdx.x] = h[tid];
     if (st) {
         const uint32_t w = wave_sum_u32(writers);
         if (lane_id() == 0 && w) atomicAdd(&st->b_writers, w);
     }
 }
 
-__global__ __launch_bounds__(ST) void k_colscan(uint32_t *__restrict__ tile_hist, uint32_t ntiles,
+__global__ __launch_bounds__(CT) void k_colscan(uint32_t *__restrict__ tile_hist, uint32_t ntiles,
                                                 uint32_t *__restrict__ digit_tot) {
-    __shared__ uint32_t s_tmp[NW + 1];
+    __shared__ uint32_t s_tmp[CT / 64 + 1];
     uint32_t *col = tile_hist + (size_t)blockIdx.x * ntiles;
     uint32_t carry = 0;
-    for (uint32_t base = 0; base < ntiles; base += ST * 8) {
+    for (uint32_t base = 0; base < ntiles; base += CT * 8) {
         uint32_t v[8];
         uint32_t sum = 0;
 #pragma unroll
@@ -74,7 +94,7 @@ __global__ __launch_bounds__(ST) void k_colscan(uint32_t *__restrict__ tile_hist
             sum += v[j];
         }
         uint32_t tot;
-        uint32_t run = carry + block_excl_scan_u32<ST>(sum, s_tmp, &tot);
+        uint32_t run = carry + block_excl_scan_u32<CT>(sum, s_tmp, &tot);
 #pragma unroll
         for (int j = 0; j < 8; j++) {
             const uint32_t i = base + threadIdx.x * 8 + j;
@@ -89,10 +109,11 @@ __global__ __launch_bounds__(ST) void k_colscan(uint32_t *__restrict__ tile_hist
 __global__ __launch_bounds__(ST) void k_scatter(const uint64_t *__restrict__ keys_in,
                                                 const uint32_t *__restrict__ idx_in,
                                                 const uint8_t *__restrict__ ops, uint32_t n, uint32_t shift,
-                                                const uint32_t *__restrict__ tile_hist, uint32_t ntiles,
-                                                const uint32_t *__restrict__ digit_tot,
+                                                const RangeMap *map, const uint32_t *__restrict__ tile_hist,
+                                                uint32_t ntiles, const uint32_t *__restrict__ digit_tot,
                                                 uint64_t *__restrict__ keys_out, uint32_t *__restrict__ idx_out) {
     __shared__ uint32_t s_cnt[NW][R];
+    const Digit dg = make_digit(shift, map);
     __shared__ uint32_t s_tstart[R];
     __shared__ uint32_t s_gstart[R];
     __shared__ uint32_t s_tmp[NW + 1];
@@ -105,8 +126,8 @@ __global__ __launch_bounds__(ST) void k_scatter(const uint64_t *__restrict__ key
     for (int j = tid; j < NW * R; j += ST) (&s_cnt[0][0])[j] = 0;
     {
         uint32_t tot;
-        const uint32_t ex = block_excl_scan_u32<ST>(digit_tot[tid], s_tmp, &tot);
-        s_gstart[tid] = ex + tile_hist[(size_t)tid * ntiles + blockIdx.x];
+        const uint32_t ex = block_excl_scan_u32<ST>(tid < R ? digit_tot[tid] : 0u, s_tmp, &tot);
+        if (tid < R) s_gstart[tid] = ex + tile_hist[(size_t)tid * ntiles + blockIdx.x];
     }
     __syncthreads();
 
@@ -131,7 +152,7 @@ __global__ __launch_bounds__(ST) void k_scatter(const uint64_t *__restrict__ key
 #pragma unroll
     for (int r = 0; r < SI; r++) {
         const bool valid = (wbase + r * 64 + lane) < n;
-        const uint32_t d = (uint32_t)(k[r] >> shift) & (R - 1);
+        const uint32_t d = dg(k[r]);
         uint64_t m = ballot64(valid);
 #pragma unroll
         for (int b = 0; b < RBITS; b++) {
@@ -147,20 +168,23 @@ __global__ __launch_bounds__(ST) void k_scatter(const uint64_t *__restrict__ key
     {
         const uint32_t d = tid;
         uint32_t run = 0;
+        if (tid < R) {
 #pragma unroll
-        for (int ww = 0; ww < NW; ww++) {
-            const uint32_t c = s_cnt[ww][d];
-            s_cnt[ww][d] = run;
-            run += c;
+            for (int ww = 0; ww < NW; ww++) {
+                const uint32_t c = s_cnt[ww][d];
+                s_cnt[ww][d] = run;
+                run += c;
+            }
         }
         uint32_t tot;
-        s_tstart[d] = block_excl_scan_u32<ST>(run, s_tmp, &tot);
+        const uint32_t ex = block_excl_scan_u32<ST>(run, s_tmp, &tot);
+        if (tid < R) s_tstart[d] = ex;
     }
     __syncthreads();
 #pragma unroll
     for (int r = 0; r < SI; r++) {
         if ((wbase + r * 64 + lane) < n) {
-            const uint32_t d = (uint32_t)(k[r] >> shift) & (R - 1);
+            const uint32_t d = dg(k[r]);
             const uint32_t p = s_tstart[d] + s_cnt[w][d] + rk[r];
             s_key[p] = k[r];
             s_idx[p] = v[r];
@@ -173,7 +197,7 @@ __global__ __launch_bounds__(ST) void k_scatter(const uint64_t *__restrict__ key
         const uint32_t p = j * ST + tid;
         if (p < cnt) {
             const uint64_t kk = s_key[p];
-            const uint32_t d = (uint32_t)(kk >> shift) & (R - 1);
+            const uint32_t d = dg(kk);
             const uint32_t o = s_gstart[d] + (p - s_tstart[d]);
             keys_out[o] = kk;
             idx_out[o] = s_idx[p];
@@ -201,11 +225,11 @@ void sort_impl(SortWorkspace &ws, const uint64_t *keys, const uint32_t *payload,
         const uint32_t shift = pass * RBITS;
         uint64_t *kout = ws.keys[pass & 1].as<uint64_t>();
         uint32_t *iout = ws.idx[pass & 1].as<uint32_t>();
-        hipLaunchKernelGGL(k_hist, dim3(ntiles), dim3(ST), 0, s, kin, opin, nn, shift, hist, ntiles,
-                           pass == 0 ? st : nullptr);
-        hipLaunchKernelGGL(k_colscan, dim3(R), dim3(ST), 0, s, hist, ntiles, tot);
-        hipLaunchKernelGGL(k_scatter, dim3(ntiles), dim3(ST), 0, s, kin, iin, opin, nn, shift, hist, ntiles, tot,
-                           kout, iout);
+        hipLaunchKernelGGL(k_hist, dim3(ntiles), dim3(ST), 0, s, kin, opin, nn, shift, (const RangeMap *)nullptr,
+                           hist, ntiles, pass == 0 ? st : nullptr);
+        hipLaunchKernelGGL(k_colscan, dim3(R), dim3(CT), 0, s, hist, ntiles, tot);
+        hipLaunchKernelGGL(k_scatter, dim3(ntiles), dim3(ST), 0, s, kin, iin, opin, nn, shift,
+                           (const RangeMap *)nullptr, hist, ntiles, tot, kout, iout);
         PI_LAUNCH_CHECK();
         kin = kout;
         iin = iout;
@@ -237,9 +261,22 @@ void SortWorkspace::release() {
     digit_tot.release();
 }
 
+void radix_pass(SortWorkspace &ws, const uint64_t *kin, const uint32_t *iin, const uint8_t *ops, uint32_t n,
+                uint32_t shift, const RangeMap *map, DevState *st, uint64_t *kout, uint32_t *iout, hipStream_t s) {
+    if (n == 0) return;
+    const uint32_t ntiles = (n + STILE - 1) / STILE;
+    uint32_t *hist = ws.tile_hist.as<uint32_t>();
+    uint32_t *tot = ws.digit_tot.as<uint32_t>();
+    hipLaunchKernelGGL(k_hist, dim3(ntiles), dim3(ST), 0, s, kin, ops, n, shift, map, hist, ntiles, st);
+    hipLaunchKernelGGL(k_colscan, dim3(R), dim3(CT), 0, s, hist, ntiles, tot);
+    hipLaunchKernelGGL(k_scatter, dim3(ntiles), dim3(ST), 0, s, kin, iin, ops, n, shift, map, hist, ntiles, tot,
+                       kout, iout);
+    PI_LAUNCH_CHECK();
+}
+
 void column_scan(uint32_t *cols, uint32_t ncols, uint32_t len, uint32_t *totals, hipStream_t s) {
     if (ncols == 0) return;
-    hipLaunchKernelGGL(k_colscan, dim3(ncols), dim3(ST), 0, s, cols, len, totals);
+    hipLaunchKernelGGL(k_colscan, dim3(ncols), dim3(CT), 0, s, cols, len, totals);
     PI_LAUNCH_CHECK();
 }
 

@@ -57,12 +57,36 @@ def assert_same(got_v, got_s, want_v, want_s, what=""):
 
 # ----------------------------------------------------------------- ordering
 
-@pytest.mark.parametrize("n", [1, 2, 63, 64, 4095, 4096, 4097, 100_003, 1 << 20])
-def test_sort_is_stable_key_order(n):
+def _sort_case(kind, n, rng):
+    if kind == "uniform+dups":
+        keys = rng.integers(0, 1 << 64, size=n, dtype=np.uint64, endpoint=False)
+        keys[rng.random(n) < 0.3] = rng.integers(0, 50, size=1, dtype=np.uint64)[0]  # a hot key
+        keys[rng.random(n) < 0.01] = np.uint64(KMAX)
+    elif kind == "clustered":
+        # nearly all keys in one 16-bit slice of the span: one huge group of
+        # distinct keys (no dominant key)
+        keys = rng.integers(0, 1 << 20, size=n, dtype=np.uint64)
+        keys[0] = np.uint64(1 << 63)
+    elif kind == "hot-in-cluster":
+        # a dominant key with large runs of other keys on both sides of it
+        keys = rng.integers(0, 1 << 20, size=n, dtype=np.uint64)
+        keys[rng.random(n) < 0.6] = np.uint64(1 << 19)
+        keys[0] = np.uint64(1 << 63)
+    elif kind == "two-hot":
+        keys = rng.integers(0, 1 << 63, size=n, dtype=np.uint64)
+        r = rng.random(n)
+        keys[r < 0.4] = np.uint64(12345)
+        keys[(r >= 0.4) & (r < 0.75)] = np.uint64(12346)
+    else:
+        raise ValueError(kind)
+    return keys
+
+
+@pytest.mark.parametrize("kind,n", [("uniform+dups", m) for m in (1, 2, 63, 64, 4095, 4096, 4097, 100_003, 1 << 20)]
+                         + [("clustered", 70_001), ("hot-in-cluster", 150_001), ("two-hot", 200_003)])
+def test_sort_is_stable_key_order(kind, n):
     rng = np.random.default_rng(n)
-    keys = rng.integers(0, 1 << 64, size=n, dtype=np.uint64, endpoint=False)
-    keys[rng.random(n) < 0.3] = rng.integers(0, 50, size=1, dtype=np.uint64)[0]  # many equal keys
-    keys[rng.random(n) < 0.01] = np.uint64(KMAX)
+    keys = _sort_case(kind, n, rng)
     with Index() as ix:
         sk, perm = ix.sort(keys)
         torch.cuda.synchronize()
