@@ -95,6 +95,7 @@ def main():
     ap.add_argument("--queries-per-lane", type=int, default=0)
     ap.add_argument("--blocks-per-cu", type=int, default=0)
     ap.add_argument("--lds-budget", type=int, default=0)
+    ap.add_argument("--descent-block", type=int, default=0)
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the index shards by key range "
@@ -135,7 +136,7 @@ def main():
         log(f"calibration copy of {args.calibrate_copy_mib} MiB done")
 
     ix = Index(device=0, profile=1, queries_per_lane=args.queries_per_lane, blocks_per_cu=args.blocks_per_cu,
-               lds_budget=args.lds_budget)
+               lds_budget=args.lds_budget, descent_block=args.descent_block)
     t0 = time.perf_counter()
     ix.bulk_load(w.load_keys, w.load_vals)
     torch.cuda.synchronize()

@@ -84,10 +84,11 @@ typedef struct {
                                  sentinels; 0 = grow on demand */
     uint32_t lds_levels;      /* index levels kept in LDS by the descent: 0 = auto */
     uint32_t profile;         /* 1 = time every stage with HIP events (pi_get_profile) */
-    uint32_t queries_per_lane;/* descent: queries carried by one lane, 1, 2 or 4 (0 = auto: 2) */
+    uint32_t queries_per_lane;/* descent: queries carried by one lane, 1, 2 or 4 (0 = 1) */
     uint32_t blocks_per_cu;   /* descent: cap on resident blocks per CU (0 = occupancy limit) */
-    uint32_t lds_budget;      /* descent: index entries staged in LDS per block, <= 5000 (0 = 4096) */
-    uint32_t reserved[3];
+    uint32_t lds_budget;      /* descent: index entries staged in LDS per block, <= 13000 (0 = 12000) */
+    uint32_t descent_block;   /* descent: threads per block, 256, 512 or 1024 (0 = 1024) */
+    uint32_t reserved[2];
 } pi_config;
 
 /* Accumulated device time per stage of pi_execute_batch (profile = 1). */

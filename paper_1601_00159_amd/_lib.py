@@ -31,7 +31,8 @@ class pi_config(ctypes.Structure):
                 ("rebuild_policy", ctypes.c_uint32), ("capacity_hint", ctypes.c_uint64),
                 ("lds_levels", ctypes.c_uint32), ("profile", ctypes.c_uint32),
                 ("queries_per_lane", ctypes.c_uint32), ("blocks_per_cu", ctypes.c_uint32),
-                ("lds_budget", ctypes.c_uint32), ("reserved", ctypes.c_uint32 * 3)]
+                ("lds_budget", ctypes.c_uint32), ("descent_block", ctypes.c_uint32),
+                ("reserved", ctypes.c_uint32 * 2)]
 
 
 class pi_profile(ctypes.Structure):

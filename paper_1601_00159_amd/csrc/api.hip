@@ -151,6 +151,7 @@ pi_status pi_config_default(pi_config *cfg) {
     cfg->queries_per_lane = 0;
     cfg->blocks_per_cu = 0;
     cfg->lds_budget = 0;
+    cfg->descent_block = 0;
     return PI_OK;
 }
 
@@ -178,7 +179,9 @@ pi_status pi_create(const pi_config *cfg_in, pi_index **out) {
         cfg.capacity_hint > (1ull << 32) - 64 ||
         (cfg.queries_per_lane != 0 && cfg.queries_per_lane != 1 && cfg.queries_per_lane != 2 &&
          cfg.queries_per_lane != 4) ||
-        cfg.lds_budget > 5000) {
+        cfg.lds_budget > 13000 ||
+        (cfg.descent_block != 0 && cfg.descent_block != 256 && cfg.descent_block != 512 &&
+         cfg.descent_block != 1024)) {
         set_err("invalid pi_config field");
         return PI_ERR_INVALID_ARG;
     }

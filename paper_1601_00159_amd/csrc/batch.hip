@@ -32,7 +32,6 @@
 namespace pi {
 namespace {
 
-constexpr int DT = 256;          // descent block
 constexpr int OT = 256;          // ownership block
 constexpr int OI = 4;            // items per thread (blocked)
 constexpr int OTILE = OT * OI;
@@ -269,9 +268,11 @@ __device__ __forceinline__ Found walk_storage(uint64_t q, uint32_t cur, uint64_t
 }
 
 // MODE 0: sorted batch.  MODE 1: interception of arbitrary keys (inspection).
-// Each block owns a contiguous range of tiles of DT*QPL sorted queries; a lane
-// carries QPL queries of a tile (rows of DT) through the descent together.
-template <int MODE, int QPL>
+// Each block of DT threads owns a contiguous range of tiles of DT*QPL sorted
+// queries; a lane carries QPL queries of a tile (rows of DT) through the
+// descent together.  All waves of the block share one LDS copy of the upper
+// levels.
+template <int MODE, int QPL, int DT>
 __global__ __launch_bounds__(DT) void k_descend(IndexDesc desc, const uint64_t *__restrict__ lkey,
                                                 const uint32_t *__restrict__ ldown, const uint64_t *__restrict__ skey,
                                                 const uint64_t *__restrict__ sval, const uint32_t *__restrict__ snext,
@@ -616,41 +617,63 @@ __global__ void k_zero_u32(unsigned int *p) {
 
 uint32_t blocks_for(uint64_t n, int t) { return (uint32_t)((n + t - 1) / t); }
 
-template <int MODE, int QPL>
+template <int MODE, int QPL, int DT>
 void launch_descend_q(Index &ix, hipStream_t s, const uint64_t *sk, const uint32_t *sidx, uint64_t n,
                       uint64_t *out_vals, uint8_t *out_status, uint64_t *res_val, uint8_t *res_flags, uint32_t *loc,
                       uint32_t *locnext) {
     const IndexDesc &d = ix.desc;
     const size_t lds = (size_t)d.lds_entries * 12;
+    auto kern = k_descend<MODE, QPL, DT>;
+    if (lds > 65536) PI_HIP(hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
     const uint32_t ntiles = blocks_for(n, DT * QPL);
     // persistent blocks: as many as can be resident at once
     int per_cu = 0;
-    PI_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_descend<MODE, QPL>, DT, lds));
+    PI_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, DT, lds));
+    if (per_cu < 1)
+        throw Error{PI_ERR_INVALID_ARG, "descent configuration cannot be resident (queries_per_lane x descent_block "
+                                        "x lds_budget too large)"};
     if (ix.cfg.blocks_per_cu) per_cu = std::min<int>(per_cu, (int)ix.cfg.blocks_per_cu);
     uint32_t g = (uint32_t)ix.num_cus * (uint32_t)std::max(per_cu, 1);
     if (g > ntiles) g = ntiles;
     if (g >= 8) g &= ~7u;
     if (!g) g = 1;
-    hipLaunchKernelGGL((k_descend<MODE, QPL>), dim3(g), dim3(DT), lds, s, d, ix.arena_key.as<uint64_t>(),
-                       ix.arena_down.as<uint32_t>(), ix.st.key.as<uint64_t>(), ix.st.val.as<uint64_t>(),
-                       ix.st.next.as<uint32_t>(), ix.st.meta.as<uint8_t>(), sk, sidx, (uint32_t)n, ix.dstate,
-                       out_vals, out_status, res_val, res_flags, loc, locnext);
+    hipLaunchKernelGGL(kern, dim3(g), dim3(DT), lds, s, d, ix.arena_key.as<uint64_t>(), ix.arena_down.as<uint32_t>(),
+                       ix.st.key.as<uint64_t>(), ix.st.val.as<uint64_t>(), ix.st.next.as<uint32_t>(),
+                       ix.st.meta.as<uint8_t>(), sk, sidx, (uint32_t)n, ix.dstate, out_vals, out_status, res_val,
+                       res_flags, loc, locnext);
     PI_LAUNCH_CHECK();
+}
+
+template <int MODE, int DT>
+void launch_descend_b(Index &ix, hipStream_t s, const uint64_t *sk, const uint32_t *sidx, uint64_t n,
+                      uint64_t *out_vals, uint8_t *out_status, uint64_t *res_val, uint8_t *res_flags, uint32_t *loc,
+                      uint32_t *locnext) {
+    switch (ix.cfg.queries_per_lane) {
+        case 2:
+            launch_descend_q<MODE, 2, DT>(ix, s, sk, sidx, n, out_vals, out_status, res_val, res_flags, loc, locnext);
+            break;
+        case 4:
+            launch_descend_q<MODE, 4, DT>(ix, s, sk, sidx, n, out_vals, out_status, res_val, res_flags, loc, locnext);
+            break;
+        default:
+            launch_descend_q<MODE, 1, DT>(ix, s, sk, sidx, n, out_vals, out_status, res_val, res_flags, loc, locnext);
+            break;
+    }
 }
 
 template <int MODE>
 void launch_descend(Index &ix, hipStream_t s, const uint64_t *sk, const uint32_t *sidx, uint64_t n,
                     uint64_t *out_vals, uint8_t *out_status, uint64_t *res_val, uint8_t *res_flags, uint32_t *loc,
                     uint32_t *locnext) {
-    switch (ix.cfg.queries_per_lane) {
-        case 1:
-            launch_descend_q<MODE, 1>(ix, s, sk, sidx, n, out_vals, out_status, res_val, res_flags, loc, locnext);
+    switch (ix.cfg.descent_block) {
+        case 256:
+            launch_descend_b<MODE, 256>(ix, s, sk, sidx, n, out_vals, out_status, res_val, res_flags, loc, locnext);
             break;
-        case 4:
-            launch_descend_q<MODE, 4>(ix, s, sk, sidx, n, out_vals, out_status, res_val, res_flags, loc, locnext);
+        case 512:
+            launch_descend_b<MODE, 512>(ix, s, sk, sidx, n, out_vals, out_status, res_val, res_flags, loc, locnext);
             break;
         default:
-            launch_descend_q<MODE, 2>(ix, s, sk, sidx, n, out_vals, out_status, res_val, res_flags, loc, locnext);
+            launch_descend_b<MODE, 1024>(ix, s, sk, sidx, n, out_vals, out_status, res_val, res_flags, loc, locnext);
             break;
     }
 }

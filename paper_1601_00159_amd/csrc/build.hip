@@ -322,7 +322,7 @@ static void build_levels(Index &ix, hipStream_t s) {
         }
         // upper levels kept in LDS by the descent (Section 5.1 notes the top
         // levels are cache resident anyway; Section 7 proposes pinning them)
-        const uint32_t budget = ix.cfg.lds_budget ? ix.cfg.lds_budget : 4096;  // 4096 entries: 48 KB per block
+        const uint32_t budget = ix.cfg.lds_budget ? ix.cfg.lds_budget : 12000;  // 12000 entries: 141 KB per block
         uint32_t used = 0;
         int from = d.top + 1;
         const uint32_t want = ix.cfg.lds_levels ? ix.cfg.lds_levels : 64u;

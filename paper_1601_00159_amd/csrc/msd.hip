@@ -10,7 +10,8 @@
 //   3. k_fixup, in place: windows of ~1920 entries widened to whole groups;
 //      a group of equal u holds keys that may differ and must be ordered by
 //      (key, input position) -- insertion sort in LDS for the usual tiny
-//      groups, a bitonic network for a window with a larger group
+//      groups, a bitonic network for a window with a larger group.  Skipped
+//      for batches without updates (the grouping by u is their order).
 //   4. windows too large for one block (a group of one hot key repeated many
 //      times): k_big_check (all blocks) tests whether the window holds a
 //      single key -- then it is already in input order and nothing moves;
@@ -241,9 +242,13 @@ __device__ __forceinline__ void window_bounds(const uint64_t *__restrict__ k, ui
     e = e0 < n ? (range_pos(k[e0 - 1], map) == range_pos(k[e0], map) ? group_end(k, n, map, e0 - 1) : e0) : n;
 }
 
+// A batch without INSERT/DELETE (st->b_writers == 0) needs the order only for
+// locality -- no node gets a writer and no answer depends on the order of
+// different keys -- so it stops at the grouping by u; st == nullptr always
+// orders fully.
 __global__ __launch_bounds__(WT) void k_fixup(uint64_t *__restrict__ kk, uint32_t *__restrict__ vv, uint32_t n,
                                               const RangeMap *__restrict__ mapp, uint32_t *__restrict__ big,
-                                              unsigned int *nbig, unsigned int *dirty) {
+                                              unsigned int *nbig, unsigned int *dirty, const DevState *st) {
     __shared__ uint64_t s_k[WMAX];
     __shared__ uint32_t s_v[WMAX];
     __shared__ uint32_t s_h[WMAX + 1];  // group heads, in order
@@ -252,6 +257,7 @@ __global__ __launch_bounds__(WT) void k_fixup(uint64_t *__restrict__ kk, uint32_
     __shared__ unsigned int s_gmax;
     const RangeMap map = *mapp;
     if (blockIdx.x * WNOM >= n) return;
+    if (st && st->b_writers == 0) return;
     if (threadIdx.x < 64) {
         uint32_t s, e;
         window_bounds(kk, n, map, blockIdx.x, s, e);
@@ -712,7 +718,7 @@ void sort_batch_by_range(SortWorkspace &ws, MsdWorkspace &mw, const uint64_t *ke
     radix_pass(ws, kb, ib, nullptr, nn, 16, map, nullptr, ka, ia, s);
     const uint32_t nwin = (nn + WNOM - 1) / WNOM;
     hipLaunchKernelGGL(k_fixup, dim3(nwin), dim3(WT), 0, s, ka, ia, nn, map, mw.big.as<uint32_t>(),
-                       mw.nbig.as<unsigned int>(), mw.dirty.as<unsigned int>());
+                       mw.nbig.as<unsigned int>(), mw.dirty.as<unsigned int>(), (const DevState *)st);
     hipLaunchKernelGGL(k_big_check, dim3(1024), dim3(WT), 0, s, ka, mw.big.as<uint32_t>(), mw.nbig.as<unsigned int>(),
                        mw.dirty.as<unsigned int>());
     hipLaunchKernelGGL(k_big_fixup, dim3(BIG_GRID), dim3(WT), 0, s, ka, ia, kb, ib, mw.big.as<uint32_t>(),
