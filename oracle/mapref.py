@@ -122,3 +122,17 @@ class MapState:
         st = np.where(inval, INVALID, st).astype(np.uint8)
         val = np.where(inval, 0, val).astype(np.uint64)
         return val, st
+
+    def range_batch(self, lo, hi):
+        """Range searches on the sorted arrays (the plain definition: every key
+        k with lo <= k <= hi): (counts, keys, values), concatenated in range
+        order."""
+        lo = np.asarray(lo, dtype=np.uint64)
+        hi = np.asarray(hi, dtype=np.uint64)
+        a = np.searchsorted(self.keys, lo, side="left")
+        b = np.searchsorted(self.keys, hi, side="right")
+        b = np.where(lo <= hi, np.maximum(a, b), a)
+        counts = (b - a).astype(np.uint64)
+        idx = np.concatenate([np.arange(x, y) for x, y in zip(a.tolist(), b.tolist())] or
+                             [np.zeros(0, dtype=np.int64)]).astype(np.int64)
+        return counts, self.keys[idx], self.vals[idx]

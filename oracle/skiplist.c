@@ -281,6 +281,39 @@ uint64_t orc_export(const orc_list *s, uint64_t *keys, uint64_t *vals, uint64_t 
     return i;
 }
 
+/* Range search (the paper's range query of Section 4.3, SEARCH only): the
+ * pairs with lo <= key <= hi, in key order -- the descent to the first key
+ * >= lo, then the storage-level walk until a key passes hi.  Writes at most
+ * cap of them and returns how many there are (none when lo > hi). */
+uint64_t orc_range(const orc_list *s, uint64_t lo, uint64_t hi, uint64_t *keys, uint64_t *vals, uint64_t cap)
+{
+    uint64_t c = 0;
+    if (lo > hi) return 0;
+    for (orc_node *n = descend(s, lo, NULL); n && n->key <= hi; n = n->fwd[0], c++) {
+        if (c < cap) {
+            keys[c] = n->key;
+            vals[c] = n->val;
+        }
+    }
+    return c;
+}
+
+/* n range searches: counts[i] = size of range i; the results of all ranges
+ * are concatenated in range order into keys/vals (at most cap pairs in
+ * total).  Returns the total. */
+uint64_t orc_range_batch(const orc_list *s, const uint64_t *lo, const uint64_t *hi, uint64_t n,
+                         uint64_t *counts, uint64_t *keys, uint64_t *vals, uint64_t cap)
+{
+    uint64_t total = 0;
+    for (uint64_t i = 0; i < n; i++) {
+        const uint64_t room = (keys && vals && total < cap) ? cap - total : 0;
+        const uint64_t c = orc_range(s, lo[i], hi[i], room ? keys + total : NULL, room ? vals + total : NULL, room);
+        counts[i] = c;
+        total += c;
+    }
+    return total;
+}
+
 /* Number of keys present on level l (1-based: level 1 is the storage level). */
 uint64_t orc_level_count(const orc_list *s, int32_t level)
 {

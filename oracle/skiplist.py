@@ -59,6 +59,8 @@ def _load():
     lib.orc_level_keys.argtypes = [vp, i32, vp, u64]
     lib.orc_interception.restype = i32
     lib.orc_interception.argtypes = [vp, u64, ctypes.POINTER(u64)]
+    lib.orc_range_batch.restype = u64
+    lib.orc_range_batch.argtypes = [vp, vp, vp, u64, vp, vp, vp, u64]
     lib.orc_check.restype = i32
     lib.orc_check.argtypes = [vp]
     _lib = lib
@@ -179,6 +181,21 @@ class SkipList:
         k = ctypes.c_uint64()
         hit = self._lib.orc_interception(self._h, q, ctypes.byref(k))
         return k.value if hit else None
+
+    def range_batch(self, lo, hi):
+        """Range searches [lo[i], hi[i]]: (counts, keys, values), the results
+        of all ranges concatenated in range order, each in key order."""
+        lo = np.ascontiguousarray(lo, dtype=np.uint64)
+        hi = np.ascontiguousarray(hi, dtype=np.uint64)
+        assert lo.shape == hi.shape
+        counts = np.zeros(lo.size, dtype=np.uint64)
+        total = self._lib.orc_range_batch(self._h, _ptr(lo), _ptr(hi), lo.size, _ptr(counts), None, None, 0)
+        keys = np.zeros(total, dtype=np.uint64)
+        vals = np.zeros(total, dtype=np.uint64)
+        got = self._lib.orc_range_batch(self._h, _ptr(lo), _ptr(hi), lo.size, _ptr(counts), _ptr(keys), _ptr(vals),
+                                      total)
+        assert got == total
+        return counts, keys, vals
 
     def check(self) -> int:
         return int(self._lib.orc_check(self._h))

@@ -327,3 +327,49 @@ def test_alg3_checker_catches_a_planted_split():
     icpt = [None, 10, 10, 10, 30]
     assert not redistribute.check_latch_free(icpt, [0, 0, 1, 1, 1])
     assert redistribute.check_latch_free(icpt, [0, 1, 1, 1, 1])
+
+
+# --------------------------------------------------------------- range search
+
+def _brute_range(pairs, lo, hi):
+    """Every pair with lo <= key <= hi, by a linear scan of the sorted pairs."""
+    return [(k, v) for k, v in pairs if lo <= k <= hi]
+
+
+def test_range_search_brute_force_and_special_cases():
+    """The range query of Section 4.3 (SEARCH only): the oracle and the numpy
+    reference against a linear scan, after inserts and deletes, with empty,
+    reversed, single-key, full-span and out-of-span ranges."""
+    rng = random.Random(31)
+    s = SkipList()
+    ref = SortedPairs()
+    for _ in range(3000):
+        k = rng.randrange(0, 5000)
+        if rng.random() < 0.7:
+            s.insert(k, k * 3 + 1)
+            ref.insert(k, k * 3 + 1)
+        else:
+            s.erase(k)
+            ref.erase(k)
+    pairs = list(zip(ref.keys, ref.vals))
+    lo = [rng.randrange(0, 5200) for _ in range(400)]
+    hi = [x + rng.randrange(0, 300) for x in lo]
+    present = ref.keys[len(ref.keys) // 2]
+    lo += [0, 0, 10, present, 4000, 7000, 0, 6000]
+    hi += [KMAX, 0, 9, present, 3999, 9000, (1 << 64) - 2, KMAX]
+    counts, keys, vals = s.range_batch(np.array(lo, dtype=np.uint64), np.array(hi, dtype=np.uint64))
+    ms = mapref.MapState(np.array(ref.keys, dtype=np.uint64), np.array(ref.vals, dtype=np.uint64))
+    mc, mk, mv = ms.range_batch(np.array(lo, dtype=np.uint64), np.array(hi, dtype=np.uint64))
+    off = 0
+    for i, (a, b) in enumerate(zip(lo, hi)):
+        want = _brute_range(pairs, a, b)
+        got = list(zip(keys[off:off + int(counts[i])].tolist(), vals[off:off + int(counts[i])].tolist()))
+        assert got == want, (i, a, b)
+        off += int(counts[i])
+    assert off == keys.size
+    assert np.array_equal(counts, mc) and np.array_equal(keys, mk) and np.array_equal(vals, mv)
+    # the special cases, spelled out
+    n_all = len(pairs)
+    assert counts[-8] == n_all and counts[-7] == (1 if ref.keys[0] == 0 else 0)
+    assert counts[-6] == 0 and counts[-5] == 1 and counts[-4] == 0 and counts[-3] == 0
+    assert counts[-2] == n_all and counts[-1] == 0
