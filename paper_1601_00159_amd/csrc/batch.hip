@@ -81,60 +81,77 @@ __device__ __forceinline__ uint32_t step_finish(KP K, DP D, const Step &s, uint6
     }
 }
 
-// Level step in global memory with an 8-entry window.  Keys are read as
-// 16-byte pairs starting at the even entry at or below pos+1 (levels start on
-// 128-byte lines), down pointers as 16-byte quads starting at the multiple of
-// 4 at or below pos: one round trip covers keys pos+1 .. pos+7 (at least) and
-// down pointers pos .. pos+8.  With p = 1/2 a run of 7 keys <= q on one level
-// is rare enough that a wave of queries almost never waits for a second trip.
 // Length of the run of keys <= q starting at keys[skip] (only the leading
 // run counts: entries after the first key > q may hold anything).
-__device__ __forceinline__ uint32_t leading_le(const uint64_t (&keys)[8], uint32_t skip, uint64_t q) {
+template <int N>
+__device__ __forceinline__ uint32_t leading_le(const uint64_t (&keys)[N], uint32_t skip, uint64_t q) {
     uint32_t m = 0;
 #pragma unroll
-    for (int i = 0; i < 8; i++) m |= (keys[i] <= q ? 1u : 0u) << i;
+    for (int i = 0; i < N; i++) m |= (keys[i] <= q ? 1u : 0u) << i;
     m >>= skip;
     return (uint32_t)__builtin_ctz(~m);
 }
 
+// Level step in global memory with a window of KP key pairs and DQ down
+// quads.  Keys are read as 16-byte pairs starting at the even entry at or
+// below pos+1 (levels start on 128-byte lines), down pointers as 16-byte quads
+// starting at the multiple of 4 at or below pos: with KP = 4, DQ = 3 one round
+// trip covers keys pos+1 .. pos+7 (at least) and down pointers pos .. pos+8.
+// With p = 1/2 a run of 7 keys <= q on one level is rare enough that a wave of
+// queries almost never waits for a second trip.
+template <int KP, int DQ>
 struct Wide {
-    ulonglong2 kp[4];
-    uint4 dq[3];
+    ulonglong2 kp[KP];
+    uint4 dq[DQ];
 };
 
-__device__ __forceinline__ Wide wide_load(const uint64_t *__restrict__ K, const uint32_t *__restrict__ D,
-                                          uint32_t pos) {
-    Wide w;
+template <int KP, int DQ>
+__device__ __forceinline__ Wide<KP, DQ> wide_load(const uint64_t *__restrict__ K, const uint32_t *__restrict__ D,
+                                                  uint32_t pos) {
+    Wide<KP, DQ> w;
     const ulonglong2 *K2 = reinterpret_cast<const ulonglong2 *>(K + ((pos + 1) & ~1u));
     const uint4 *D4 = reinterpret_cast<const uint4 *>(D + (pos & ~3u));
 #pragma unroll
-    for (int i = 0; i < 4; i++) w.kp[i] = K2[i];
+    for (int i = 0; i < KP; i++) w.kp[i] = K2[i];
 #pragma unroll
-    for (int i = 0; i < 3; i++) w.dq[i] = D4[i];
+    for (int i = 0; i < DQ; i++) w.dq[i] = D4[i];
     return w;
 }
 
+template <int KP, int DQ>
 __device__ __forceinline__ uint32_t wide_finish(const uint64_t *__restrict__ K, const uint32_t *__restrict__ D,
-                                                const Wide &w, uint64_t q, uint32_t pos, uint64_t &last) {
-    const uint64_t keys[8] = {w.kp[0].x, w.kp[0].y, w.kp[1].x, w.kp[1].y,
-                              w.kp[2].x, w.kp[2].y, w.kp[3].x, w.kp[3].y};
+                                                const Wide<KP, DQ> &w, uint64_t q, uint32_t pos, uint64_t &last) {
+    constexpr int NK = 2 * KP, ND = 4 * DQ;
+    uint64_t keys[NK];
+#pragma unroll
+    for (int i = 0; i < KP; i++) {
+        keys[2 * i] = w.kp[i].x;
+        keys[2 * i + 1] = w.kp[i].y;
+    }
     const uint32_t skip = (pos + 1) & 1u;  // entry pos+1 is keys[skip]
-    const uint32_t cnt = leading_le(keys, skip, q);
+    const uint32_t cnt = leading_le<NK>(keys, skip, q);
     uint32_t p = pos + cnt;
     if (cnt > 0) {
         const uint32_t li = skip + cnt - 1;
         uint64_t lk = keys[0];
 #pragma unroll
-        for (int i = 1; i < 8; i++) lk = ((uint32_t)i == li) ? keys[i] : lk;
+        for (int i = 1; i < NK; i++) lk = ((uint32_t)i == li) ? keys[i] : lk;
         last = lk;
     }
-    if (cnt < 8 - skip) {
-        const uint32_t downs[12] = {w.dq[0].x, w.dq[0].y, w.dq[0].z, w.dq[0].w, w.dq[1].x, w.dq[1].y,
-                                    w.dq[1].z, w.dq[1].w, w.dq[2].x, w.dq[2].y, w.dq[2].z, w.dq[2].w};
+    if (cnt < NK - skip) {
         const uint32_t di = p - (pos & ~3u);
+        if (di >= (uint32_t)ND) return D[p];  // run ended past the down window
+        uint32_t downs[ND];
+#pragma unroll
+        for (int i = 0; i < DQ; i++) {
+            downs[4 * i] = w.dq[i].x;
+            downs[4 * i + 1] = w.dq[i].y;
+            downs[4 * i + 2] = w.dq[i].z;
+            downs[4 * i + 3] = w.dq[i].w;
+        }
         uint32_t d = downs[0];
 #pragma unroll
-        for (int i = 1; i < 12; i++) d = ((uint32_t)i == di) ? downs[i] : d;
+        for (int i = 1; i < ND; i++) d = ((uint32_t)i == di) ? downs[i] : d;
         return d;
     }
     for (;;) {  // long run of keys <= q: one key at a time
@@ -144,6 +161,11 @@ __device__ __forceinline__ uint32_t wide_finish(const uint64_t *__restrict__ K, 
         p++;
     }
 }
+
+// Window of the global levels: 4 key pairs and 3 down quads.  Narrower
+// windows (2 pairs) cost a second round trip too often; wider ones buy nothing.
+constexpr int WIN_KP = 4;
+constexpr int WIN_DQ = 3;
 
 // Descends QPL independent queries together, level by level (the group
 // processing of Section 4.3.4): every query's loads for a level are issued
@@ -171,9 +193,9 @@ __device__ __forceinline__ void descend_index(const uint64_t (&q)[QPL], const In
         } else {
             const uint64_t *K = lkey + d.off[l];
             const uint32_t *D = ldown + d.off[l];
-            Wide wd[QPL];
+            Wide<WIN_KP, WIN_DQ> wd[QPL];
 #pragma unroll
-            for (int j = 0; j < QPL; j++) wd[j] = wide_load(K, D, pos[j]);
+            for (int j = 0; j < QPL; j++) wd[j] = wide_load<WIN_KP, WIN_DQ>(K, D, pos[j]);
 #pragma unroll
             for (int j = 0; j < QPL; j++) pos[j] = wide_finish(K, D, wd[j], q[j], pos[j], last[j]);
         }
@@ -221,7 +243,7 @@ __device__ __forceinline__ Found walk_storage(uint64_t q, uint32_t cur, uint64_t
         for (int i = 0; i < 4; i++) kp[i] = S2[i];
         const uint64_t keys[8] = {kp[0].x, kp[0].y, kp[1].x, kp[1].y, kp[2].x, kp[2].y, kp[3].x, kp[3].y};
         const uint32_t skip = (cur + 1) & 1u;
-        const uint32_t cnt = leading_le(keys, skip, q);  // stops at the tail's +infinity
+        const uint32_t cnt = leading_le<8>(keys, skip, q);  // stops at the tail's +infinity
         if (cnt > 0) {
             const uint32_t li = skip + cnt - 1;
             uint64_t lk = keys[0];

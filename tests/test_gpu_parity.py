@@ -289,6 +289,42 @@ def test_results_independent_of_lds_staging(lds_levels):
         assert_same(gv, gs, wv, ws, f"lds_levels={lds_levels}")
 
 
+@pytest.mark.parametrize("qpl,block", [(1, 1024), (2, 256), (4, 512), (1, 512), (2, 1024)])
+def test_descent_variants_agree(qpl, block):
+    """Every descent launch shape (queries per lane, block size) gives the
+    oracle's answers, on base nodes and on linked ones, and the oracle's
+    interceptions."""
+    rng = np.random.default_rng(100 + 10 * qpl + block)
+    lk = rng.integers(0, 1 << 63, size=60_000, dtype=np.uint64)
+    lv = rng.integers(0, 1 << 64, size=60_000, dtype=np.uint64, endpoint=False)
+    pool = np.concatenate([lk[:30_000], rng.integers(0, 1 << 63, size=30_000, dtype=np.uint64),
+                           np.array([0, (1 << 64) - 2], dtype=np.uint64)])
+    orc = SkipList()
+    orc.bulk_load(lk, lv)
+    with Index(rebuild_policy="never", queries_per_lane=qpl, descent_block=block, lds_budget=2000) as ix:
+        ix.bulk_load(lk, lv)
+        for b, n in enumerate([30_001, 1, 70_000]):
+            ops, keys, vals = _random_batch(rng, pool, n)
+            if b == 2:
+                ops[:] = 0  # read-only batch over base and linked nodes
+            wv, ws = orc.execute_batch(ops, keys, vals)
+            gv, gs = run_gpu(ix, ops, keys, vals)
+            assert_same(gv, gs, wv, ws, f"batch {b}")
+        q = np.concatenate([pool[rng.integers(0, pool.size, 5000)],
+                            np.array([0, lk.min(), lk.max(), KMAX - 1], dtype=np.uint64)])
+        ik, hd = ix.interceptions(q)
+        ik, hd = to_numpy_u64(ik), hd.cpu().numpy()
+        # with rebuilds off the index levels are those of the bulk load, so the
+        # interceptions are those of an oracle holding the loaded set
+        ref = SkipList()
+        uk, uv = mapref.dedupe_last(lk, lv)
+        ref.bulk_load_sorted(uk, uv)
+        for i in range(q.size):
+            w = ref.interception(int(q[i]))
+            assert (hd[i] == 1) if w is None else (hd[i] == 0 and int(ik[i]) == w), i
+        ref.close()
+
+
 # ------------------------------------------------ the named workloads
 
 def test_plain_pi_full_size():
