@@ -168,6 +168,27 @@ pi_status pi_repair(pi_index *idx, pi_stream stream);
 pi_status pi_export(pi_index *idx, uint64_t *d_keys, uint64_t *d_values, uint64_t cap,
                     uint64_t *n_out, pi_stream stream);
 
+/* Range search: the range query of Section 3.2.5, for SEARCH.  Range i
+ * holds every live (key, value) pair with d_lo[i] <= key <= d_hi[i]
+ * (none when d_lo[i] > d_hi[i]), in increasing key order.  Two calls on the
+ * same stream, with no batch or repair of this index in between:
+ *
+ *   pi_range_count   writes d_offsets u64[n + 1]: d_offsets[i] is the number
+ *                    of pairs in ranges 0 .. i-1, d_offsets[n] the total.
+ *   pi_range_collect writes range i's pairs to d_keys/d_values u64 at
+ *                    [d_offsets[i], d_offsets[i+1]).  It never writes past
+ *                    d_offsets[i+1]; if the index changed since the count,
+ *                    a range may fill fewer entries than reserved.
+ *
+ * Inputs d_lo, d_hi u64[n] and d_offsets are device memory owned by the
+ * caller; both calls are asynchronous on the stream and do not change the
+ * index.  n = 0 writes d_offsets[0] = 0.  Errors: PI_ERR_INVALID_ARG for
+ * NULL pointers or n above 2^31 - 1. */
+pi_status pi_range_count(pi_index *idx, const uint64_t *d_lo, const uint64_t *d_hi, uint64_t n,
+                         uint64_t *d_offsets, pi_stream stream);
+pi_status pi_range_collect(pi_index *idx, const uint64_t *d_lo, const uint64_t *d_hi, uint64_t n,
+                           const uint64_t *d_offsets, uint64_t *d_keys, uint64_t *d_values, pi_stream stream);
+
 /* Copies the counters into *out (host).  Synchronises the index's device. */
 pi_status pi_get_stats(pi_index *idx, pi_stats *out);
 

@@ -51,7 +51,7 @@ class pi_stats(ctypes.Structure):
 
 
 EXPORTED = ["pi_config_default", "pi_create", "pi_destroy", "pi_bulk_load", "pi_execute_batch",
-            "pi_repair", "pi_export", "pi_get_stats", "pi_get_profile", "pi_last_error", "pi_debug_interceptions",
+            "pi_repair", "pi_export", "pi_range_count", "pi_range_collect", "pi_get_stats", "pi_get_profile", "pi_last_error", "pi_debug_interceptions",
             "pi_debug_level", "pi_debug_sort"]
 
 
@@ -74,6 +74,8 @@ def load(path: str = LIB_PATH):
         "pi_execute_batch": ([vp, vp, vp, vp, u64, vp, vp, vp], i32),
         "pi_repair": ([vp, vp], i32),
         "pi_export": ([vp, vp, vp, u64, ctypes.POINTER(u64), vp], i32),
+        "pi_range_count": ([vp, vp, vp, u64, vp, vp], i32),
+        "pi_range_collect": ([vp, vp, vp, u64, vp, vp, vp, vp], i32),
         "pi_get_stats": ([vp, ctypes.POINTER(pi_stats)], i32),
         "pi_get_profile": ([vp, ctypes.POINTER(pi_profile), i32], i32),
         "pi_last_error": ([vp], ctypes.c_char_p),

@@ -93,6 +93,7 @@ void release_all(pi::Index &ix) {
     ix.scanws.release();
     ix.bws.release();
     for (auto &b : ix.tmp) b.release();
+    for (auto &b : ix.rng) b.release();
     if (ix.dstate) (void)hipFree(ix.dstate);
     if (ix.hstate) (void)hipHostFree(ix.hstate);
     if (ix.hcounts) (void)hipHostFree(ix.hcounts);
@@ -292,6 +293,27 @@ pi_status pi_export(pi_index *h, uint64_t *d_keys, uint64_t *d_values, uint64_t 
         *n_out = cur.n_live;
         if (cur.n_live > cap) return fail(ix, PI_ERR_CAPACITY, "export capacity too small");
         *n_out = pi::export_live(ix, d_keys, d_values, cap, (hipStream_t)stream);
+        return PI_OK;
+    });
+}
+
+pi_status pi_range_count(pi_index *h, const uint64_t *d_lo, const uint64_t *d_hi, uint64_t n, uint64_t *d_offsets,
+                         pi_stream stream) {
+    return guarded(h, [&](pi::Index &ix) -> pi_status {
+        if (n > MAX_BATCH) return fail(ix, PI_ERR_INVALID_ARG, "n too large");
+        if (!d_offsets || (n > 0 && (!d_lo || !d_hi))) return fail(ix, PI_ERR_INVALID_ARG, "NULL pointer");
+        pi::range_count(ix, d_lo, d_hi, n, d_offsets, (hipStream_t)stream);
+        return PI_OK;
+    });
+}
+
+pi_status pi_range_collect(pi_index *h, const uint64_t *d_lo, const uint64_t *d_hi, uint64_t n,
+                           const uint64_t *d_offsets, uint64_t *d_keys, uint64_t *d_values, pi_stream stream) {
+    return guarded(h, [&](pi::Index &ix) -> pi_status {
+        if (n > MAX_BATCH) return fail(ix, PI_ERR_INVALID_ARG, "n too large");
+        if (n > 0 && (!d_lo || !d_hi || !d_offsets || !d_keys || !d_values))
+            return fail(ix, PI_ERR_INVALID_ARG, "NULL pointer");
+        pi::range_collect(ix, d_lo, d_hi, n, d_offsets, d_keys, d_values, (hipStream_t)stream);
         return PI_OK;
     });
 }

@@ -69,6 +69,7 @@ struct Index {
     ScanWorkspace scanws;
     BatchWorkspace bws;
     DevBuf tmp[6];                 // rebuild / export scratch
+    DevBuf rng[4];                 // range search: first node, end slot, counts, scan tiles
     uint64_t *hcounts = nullptr;   // pinned: level totals etc.
     int num_cus = 256;
     Profiler prof;
@@ -88,5 +89,10 @@ void execute_batch(Index &ix, const uint8_t *ops, const uint64_t *keys, const ui
 void debug_interceptions(Index &ix, const uint64_t *keys, uint64_t n, uint64_t *icpt_keys, uint8_t *is_head,
                          hipStream_t s);
 uint64_t count_inserts(Index &ix, const uint8_t *ops, const uint64_t *keys, uint64_t n, hipStream_t s);
+
+// range.hip
+void range_count(Index &ix, const uint64_t *lo, const uint64_t *hi, uint64_t n, uint64_t *offsets, hipStream_t s);
+void range_collect(Index &ix, const uint64_t *lo, const uint64_t *hi, uint64_t n, const uint64_t *offsets,
+                   uint64_t *keys, uint64_t *vals, hipStream_t s);
 
 }  // namespace pi

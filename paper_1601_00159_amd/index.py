@@ -128,6 +128,33 @@ class Index:
         self._check(self._L.pi_export(self._h, _ptr(k), _ptr(v), n, ctypes.byref(got), _stream(stream)))
         return k[:got.value], v[:got.value]
 
+    def range_count(self, lo, hi, stream=None):
+        """Output offsets u64[n+1] (int64 tensor) of range searches [lo, hi]."""
+        lo = to_device_u64(lo, self.device)
+        hi = to_device_u64(hi, self.device)
+        assert lo.numel() == hi.numel()
+        off = torch.empty(lo.numel() + 1, dtype=torch.int64, device=self.device)
+        self._check(self._L.pi_range_count(self._h, _ptr(lo), _ptr(hi), lo.numel(), _ptr(off), _stream(stream)))
+        return off
+
+    def range_collect(self, lo, hi, offsets, total, stream=None):
+        """Pairs of range searches [lo, hi] at the given offsets (total pairs)."""
+        lo = to_device_u64(lo, self.device)
+        hi = to_device_u64(hi, self.device)
+        k = torch.empty(max(total, 1), dtype=torch.int64, device=self.device)
+        v = torch.empty(max(total, 1), dtype=torch.int64, device=self.device)
+        self._check(self._L.pi_range_collect(self._h, _ptr(lo), _ptr(hi), lo.numel(), _ptr(offsets), _ptr(k),
+                                             _ptr(v), _stream(stream)))
+        return k[:total], v[:total]
+
+    def range_search(self, lo, hi, stream=None):
+        """(counts, keys, values): every live pair of each range [lo[i], hi[i]],
+        concatenated in range order.  Synchronises to size the output."""
+        off = self.range_count(lo, hi, stream)
+        total = int(off[-1].item())
+        k, v = self.range_collect(lo, hi, off, total, stream)
+        return off[1:] - off[:-1], k, v
+
     def stats(self):
         s = _lib.pi_stats()
         self._check(self._L.pi_get_stats(self._h, ctypes.byref(s)))

@@ -382,3 +382,67 @@ def test_headline_full_size_search():
         gv, gs = run_gpu(ix, b.ops, b.keys, b.vals)
         assert_same(gv, gs, wv, ws, w.name)
         assert (gs == 1).all()
+
+
+# ------------------------------------------------------------ range search
+
+def _ranges(rng, keys, n):
+    gap = (1 << 63) // max(keys.size, 1)
+    lo = np.where(rng.random(n) < 0.5, keys[rng.integers(0, keys.size, n)],
+                  rng.integers(0, 1 << 63, size=n, dtype=np.uint64)).astype(np.uint64)
+    gran = rng.choice(np.array([0, 1, 10, 100, 1000]), size=n)
+    width = (rng.random(n) * gran * gap).astype(np.uint64)
+    hi = lo + width
+    edge_lo = np.array([0, 0, KMAX, 10, keys[0], keys[-1], KMAX - 1, 0, keys[5]], dtype=np.uint64)
+    edge_hi = np.array([KMAX, 0, KMAX, 9, keys[0], KMAX, KMAX, KMAX - 1, keys[5] - 1], dtype=np.uint64)
+    return np.concatenate([lo, edge_lo]), np.concatenate([hi, edge_hi])
+
+
+@pytest.mark.parametrize("state", ["base", "dead", "linked", "rebuilt"])
+def test_range_search_vs_oracle(state):
+    """Range search (Section 3.2.5) against the oracle on every storage state:
+    base nodes only, base nodes with delete flags, linked new nodes, and after
+    a rebuild; granularity 0 to ~1000 keys per range plus edge ranges."""
+    rng = np.random.default_rng({"base": 1, "dead": 2, "linked": 3, "rebuilt": 4}[state])
+    lk = rng.integers(0, 1 << 63, size=200_000, dtype=np.uint64)
+    lv = rng.integers(0, 1 << 64, size=200_000, dtype=np.uint64, endpoint=False)
+    orc = SkipList()
+    orc.bulk_load(lk, lv)
+    with Index(rebuild_policy="never") as ix:
+        ix.bulk_load(lk, lv)
+        if state != "base":
+            n = 40_000
+            ops = np.full(n, 2, dtype=np.uint8)
+            keys = lk[rng.integers(0, lk.size, n)]
+            if state in ("linked", "rebuilt"):
+                ops[: n // 2] = 1
+                keys[: n // 2] = rng.integers(0, 1 << 63, size=n // 2, dtype=np.uint64)
+            vals = rng.integers(0, 1 << 64, size=n, dtype=np.uint64, endpoint=False)
+            orc.execute_batch(ops, keys, vals)
+            run_gpu(ix, ops, keys, vals)
+            st = ix.stats()
+            assert (st["overflow_nodes"] > 0) == (state == "linked" or state == "rebuilt")
+            if state == "rebuilt":
+                ix.repair()
+        ok, _ = orc.export()
+        lo, hi = _ranges(rng, ok, 20_000)
+        wc, wk, wv = orc.range_batch(lo, hi)
+        say(f"{lo.size} ranges, {int(wc.sum())} results, max {int(wc.max())}")
+        gc, gk, gv = ix.range_search(lo, hi)
+        torch.cuda.synchronize()
+        assert np.array_equal(gc.cpu().numpy().astype(np.uint64), wc)
+        assert np.array_equal(to_numpy_u64(gk), wk) and np.array_equal(to_numpy_u64(gv), wv)
+
+
+def test_range_search_edges():
+    with Index() as ix:
+        off = ix.range_count(np.zeros(0, dtype=np.uint64), np.zeros(0, dtype=np.uint64))
+        assert off.cpu().tolist() == [0]
+        c, k, v = ix.range_search(np.array([0, 5], dtype=np.uint64), np.array([KMAX, 1], dtype=np.uint64))
+        assert c.cpu().tolist() == [0, 0] and k.numel() == 0          # empty index
+        ix.bulk_load(np.array([3, 7, 11], dtype=np.uint64), np.array([30, 70, 110], dtype=np.uint64))
+        c, k, v = ix.range_search(np.array([0, 7, 8, 12, 0], dtype=np.uint64),
+                                  np.array([KMAX, 11, 10, KMAX, 3], dtype=np.uint64))
+        assert c.cpu().tolist() == [3, 2, 0, 0, 1]
+        assert to_numpy_u64(k).tolist() == [3, 7, 11, 7, 11, 3]
+        assert to_numpy_u64(v).tolist() == [30, 70, 110, 70, 110, 30]
