@@ -30,7 +30,7 @@ def log(*a):
 
 def kernel_source_hash():
     h = hashlib.sha256()
-    for f in ("batch.hip", "pi_internal.h"):
+    for f in ("batch.hip", "descent.h", "pi_internal.h"):
         with open(os.path.join(ROOT, "paper_1601_00159_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
@@ -80,6 +80,117 @@ def cpu_baseline(w, sample_queries, budget_s=12.0):
                       f"{os.cpu_count()} logical CPUs)"}
 
 
+def run_range(args):
+    """Range searches (--workload range): batches of --ranges range queries at
+    each granularity of --granularity over the loaded keys; each batch is
+    count -> read the total -> collect.  One JSON line per granularity."""
+    import numpy as np
+    import torch
+
+    from paper_1601_00159_amd import workloads as W
+    from paper_1601_00159_amd.index import Index, to_device_u64, to_numpy_u64
+
+    dev = torch.device("cuda", 0)
+    K, WU = args.steps, args.warmup
+    for g in [int(x) for x in args.granularity.split(",")]:
+        w = W.range_scan(args.load_log2, args.ranges, g, n_batches=K + WU)
+        ix = Index(device=0)
+        ix.bulk_load(w.load_keys, w.load_vals)
+        lo = [to_device_u64(a, dev) for a, _ in w.batches]
+        hi = [to_device_u64(b, dev) for _, b in w.batches]
+        results = 0
+        lat = []
+        torch.cuda.synchronize()
+        for i in range(K + WU):
+            t0 = time.perf_counter()
+            off = ix.range_count(lo[i], hi[i])
+            total = int(off[-1].item())
+            k, v = ix.range_collect(lo[i], hi[i], off, total)
+            torch.cuda.synchronize()
+            dt = time.perf_counter() - t0
+            if i >= WU:
+                lat.append(dt)
+                results += total
+        # the last batch against sorted arrays (cheap check)
+        order = np.argsort(w.load_keys, kind="stable")
+        sk, sv = w.load_keys[order], w.load_vals[order]
+        a = np.searchsorted(sk, w.batches[-1][0], side="left")
+        b = np.searchsorted(sk, w.batches[-1][1], side="right")
+        idx = np.concatenate([np.arange(x, y) for x, y in zip(a.tolist(), b.tolist())])
+        ok = bool(np.array_equal(to_numpy_u64(k), sk[idx]) and np.array_equal(to_numpy_u64(v), sv[idx]))
+        ix.close()
+        tot = sum(lat)
+        print(json.dumps({
+            "metric": "Mranges/s (range search, count + collect)", "value": round(K * args.ranges / tot / 1e6, 3),
+            "unit": "Mranges/s", "n_gpus": 1, "steps": K, "warmup": WU, "ms_per_step": round(tot / K * 1e3, 4),
+            "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "u64", "data": "synthetic",
+            "config": {"workload": w.name, "loaded_keys": int(w.load_keys.size), "ranges_per_batch": args.ranges,
+                       "granularity": g, "parallelism": "single GPU"},
+            "results_per_s_M": round(results / tot / 1e6, 2), "mean_results_per_range": round(results / K / args.ranges, 1),
+            "latency_ms": {"p50": round(float(np.percentile(lat, 50)) * 1e3, 4),
+                           "p99": round(float(np.percentile(lat, 99)) * 1e3, 4)},
+            "correct_last_batch": ok, "roofline": None, "cpu_baseline": None}), flush=True)
+
+
+def run_write(args):
+    """Write-heavy skew (--workload write): 2^26 loaded keys, batches of 2^22
+    queries 40/50/10 SEARCH/INSERT/DELETE, SEARCH and DELETE keys Zipf 0.99
+    over the loaded keys, INSERT keys fresh; threshold rebuilds run inside the
+    timed batches."""
+    import numpy as np
+    import torch
+
+    from paper_1601_00159_amd import workloads as W
+    from paper_1601_00159_amd.index import Index, to_device_u64, to_device_u8
+
+    dev = torch.device("cuda", 0)
+    K, WU = args.steps, args.warmup
+    t0 = time.perf_counter()
+    w = W.write_skew(args.load_log2, args.batch_log2, n_batches=K + WU)
+    log(f"workload {w.name}: {w.note}; generated in {time.perf_counter() - t0:.1f}s")
+    Q = 1 << args.batch_log2
+    d = [(to_device_u8(b.ops, dev), to_device_u64(b.keys, dev), to_device_u64(b.vals, dev)) for b in w.batches]
+    out_v = torch.empty(Q, dtype=torch.int64, device=dev)
+    out_s = torch.empty(Q, dtype=torch.uint8, device=dev)
+    ix = Index(device=0, profile=1)
+    ix.bulk_load(w.load_keys, w.load_vals)
+    for i in range(WU):
+        ix.execute_raw(*d[i], out_v, out_s)
+    torch.cuda.synchronize()
+    ix.profile(reset=True)
+    r0 = ix.stats()["repairs"]
+    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(K)]
+    start, end = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    start.record()
+    for i in range(K):
+        evs[i][0].record()
+        ix.execute_raw(*d[WU + i], out_v, out_s)
+        evs[i][1].record()
+    end.record()
+    torch.cuda.synchronize()
+    total_ms = start.elapsed_time(end)
+    lat = np.array([a.elapsed_time(b) for a, b in evs])
+    prof = ix.profile(reset=True)
+    st = ix.stats()
+    ix.close()
+    nb = max(prof["batches"], 1)
+    print(json.dumps({
+        "metric": "Mqueries/s, write-heavy Zipf batches", "value": round(K * Q / (total_ms / 1e3) / 1e6, 2),
+        "unit": "Mqueries/s", "n_gpus": 1, "steps": K, "warmup": WU, "ms_per_step": round(total_ms / K, 4),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "u64", "data": "synthetic",
+        "config": {"workload": w.name, "loaded_keys": int(w.load_keys.size), "batch_queries": Q,
+                   "op_mix": "40/50/10 S/I/D", "key_distribution": "zipf 0.99 (inserts fresh uniform)",
+                   "parallelism": "single GPU"},
+        "latency_ms": {"p50": round(float(np.percentile(lat, 50)), 4), "p99": round(float(np.percentile(lat, 99)), 4),
+                       "max": round(float(lat.max()), 4)},
+        "stages_ms_per_batch": {k: round(prof[k] / nb, 4) for k in ("sort_ms", "descend_ms", "own_ms", "link_ms")},
+        "rebuilds_in_timed_region": st["repairs"] - r0,
+        "rebuild_ms_total": round(prof["rebuild_ms"], 3),
+        "live_nodes_after": st["live_nodes"], "correct_last_batch": None, "roofline": None,
+        "cpu_baseline": None}), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -96,11 +207,20 @@ def main():
     ap.add_argument("--blocks-per-cu", type=int, default=0)
     ap.add_argument("--lds-budget", type=int, default=0)
     ap.add_argument("--descent-block", type=int, default=0)
+    ap.add_argument("--workload", choices=["search", "range", "write"], default="search",
+                    help="search: the 64M-key SEARCH batches (default); range: range searches; "
+                         "write: write-heavy Zipf batches")
+    ap.add_argument("--ranges", type=int, default=8192, help="range queries per batch (--workload range)")
+    ap.add_argument("--granularity", default="1,10,100,1000", help="mean keys per range (--workload range)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the index shards by key range "
               "across GPUs, which this build does not run.", file=sys.stderr)
         sys.exit(2)
+    if args.workload != "search":
+        import torch
+        assert torch.cuda.is_available(), "bench needs a GPU"
+        return run_range(args) if args.workload == "range" else run_write(args)
 
     import numpy as np
     import torch

@@ -97,24 +97,55 @@ void release_all(pi::Index &ix) {
     if (ix.dstate) (void)hipFree(ix.dstate);
     if (ix.hstate) (void)hipHostFree(ix.hstate);
     if (ix.hcounts) (void)hipHostFree(ix.hcounts);
-    if (ix.ev_state) (void)hipEventDestroy(ix.ev_state);
+    if (ix.hring) (void)hipHostFree(ix.hring);
+    for (auto &e : ix.ev_ring)
+        if (e) (void)hipEventDestroy(e);
     ix.prof.release();
     ix.dstate = nullptr;
     ix.hstate = nullptr;
     ix.hcounts = nullptr;
-    ix.ev_state = nullptr;
+    ix.hring = nullptr;
+    for (auto &e : ix.ev_ring) e = nullptr;
 }
 
-// Rebuild decision from the last counters the host has (never waits).
+// Threshold rebuild (Section 4.3.5, 15 % by default) decided from the newest
+// counters that have reached the host.  A copy that has not landed is waited
+// for only when STATE_RING batches are queued behind it, so the decision
+// lags the device by at most that many batches and the GPU queue never runs
+// dry because of it.
 void maybe_rebuild(pi::Index &ix, hipStream_t s) {
-    if (ix.cfg.rebuild_policy != PI_REBUILD_THRESHOLD || !ix.state_enqueued) return;
-    if (hipEventQuery(ix.ev_state) != hipSuccess) {
-        (void)hipGetLastError();
+    if (ix.cfg.rebuild_policy != PI_REBUILD_THRESHOLD) {
+        ix.ring_seen = ix.ring_head;
         return;
     }
-    const pi::DevState &h = *ix.hstate;
+    bool have = false;
+    pi::DevState latest{};
+    while (ix.ring_seen < ix.ring_head) {
+        const int slot = (int)(ix.ring_seen % pi::Index::STATE_RING);
+        if (ix.ring_head - ix.ring_seen >= (uint64_t)pi::Index::STATE_RING) {
+            PI_HIP(hipEventSynchronize(ix.ev_ring[slot]));
+        } else if (hipEventQuery(ix.ev_ring[slot]) != hipSuccess) {
+            (void)hipGetLastError();
+            break;
+        }
+        latest = ix.hring[slot];
+        have = true;
+        ix.ring_seen++;
+    }
+    if (!have) return;
     const double thr = std::max(1.0, (double)ix.cfg.rebuild_fraction * (double)std::max<uint64_t>(ix.live_at_rebuild, 1));
-    if ((double)h.changes >= thr) pi::rebuild(ix, s);
+    if ((double)latest.changes >= thr) {
+        pi::rebuild(ix, s);
+        ix.ring_seen = ix.ring_head;  // copies taken before the rebuild are stale
+    }
+}
+
+// Queues the copy of the counters after a batch.
+void push_state(pi::Index &ix, hipStream_t s) {
+    const int slot = (int)(ix.ring_head % pi::Index::STATE_RING);
+    PI_HIP(hipMemcpyAsync(ix.hring + slot, ix.dstate, sizeof(pi::DevState), hipMemcpyDeviceToHost, s));
+    PI_HIP(hipEventRecord(ix.ev_ring[slot], s));
+    ix.ring_head++;
 }
 
 void ensure_capacity(pi::Index &ix, const uint8_t *ops, const uint64_t *keys, uint64_t n, hipStream_t s) {
@@ -206,8 +237,10 @@ pi_status pi_create(const pi_config *cfg_in, pi_index **out) {
         PI_HIP(hipMalloc(&ix.dstate, sizeof(pi::DevState)));
         PI_HIP(hipHostMalloc(&ix.hstate, sizeof(pi::DevState), hipHostMallocDefault));
         PI_HIP(hipHostMalloc(&ix.hcounts, 64 * sizeof(uint64_t), hipHostMallocDefault));
-        PI_HIP(hipEventCreateWithFlags(&ix.ev_state, hipEventDisableTiming));
+        PI_HIP(hipHostMalloc(&ix.hring, pi::Index::STATE_RING * sizeof(pi::DevState), hipHostMallocDefault));
+        for (auto &e : ix.ev_ring) PI_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
         std::memset(ix.hstate, 0, sizeof(pi::DevState));
+        std::memset(ix.hring, 0, pi::Index::STATE_RING * sizeof(pi::DevState));
         const uint64_t cap = std::max<uint64_t>(cfg.capacity_hint ? cfg.capacity_hint : (1u << 16), 4);
         ix.st.alloc(cap);
         pi::init_empty(ix, nullptr);
@@ -246,7 +279,7 @@ pi_status pi_bulk_load(pi_index *h, const uint64_t *d_keys, const uint64_t *d_va
         if (cur.n_live != 0 || cur.nused != ix.nbase + 2 || ix.nbase != 0)
             return fail(ix, PI_ERR_STATE, "bulk load needs an empty index");
         pi::bulk_load(ix, d_keys, d_values, n, s);
-        ix.state_enqueued = false;
+        ix.ring_seen = ix.ring_head;
         return PI_OK;
     });
 }
@@ -263,9 +296,7 @@ pi_status pi_execute_batch(pi_index *h, const uint8_t *d_ops, const uint64_t *d_
         ensure_capacity(ix, d_ops, d_keys, n, s);
         pi::execute_batch(ix, d_ops, d_keys, d_values, n, d_out_values, d_out_status, s);
         ix.used_upper = std::min<uint64_t>(ix.used_upper + n, ~0ull);
-        PI_HIP(hipMemcpyAsync(ix.hstate, ix.dstate, sizeof(pi::DevState), hipMemcpyDeviceToHost, s));
-        PI_HIP(hipEventRecord(ix.ev_state, s));
-        ix.state_enqueued = true;
+        push_state(ix, s);
         if (ix.cfg.rebuild_policy == PI_REBUILD_ALWAYS) {
             pi::DevState cur;
             pi::read_state(ix, s, &cur);
@@ -278,7 +309,7 @@ pi_status pi_execute_batch(pi_index *h, const uint8_t *d_ops, const uint64_t *d_
 pi_status pi_repair(pi_index *h, pi_stream stream) {
     return guarded(h, [&](pi::Index &ix) -> pi_status {
         pi::rebuild(ix, (hipStream_t)stream);
-        ix.state_enqueued = false;
+        ix.ring_seen = ix.ring_head;
         return PI_OK;
     });
 }

@@ -60,9 +60,16 @@ struct Index {
     IndexDesc desc{};
 
     DevState *dstate = nullptr;    // device
-    DevState *hstate = nullptr;    // pinned host copy
-    hipEvent_t ev_state = nullptr;
-    bool state_enqueued = false;
+    DevState *hstate = nullptr;    // pinned host copy (blocking reads)
+    // Counters after each of the last STATE_RING batches, copied to pinned
+    // host memory behind an event: the threshold rebuild is decided from the
+    // newest copy that has landed, and the host never runs more than
+    // STATE_RING batches ahead of that decision.
+    static constexpr int STATE_RING = 4;
+    DevState *hring = nullptr;
+    hipEvent_t ev_ring[STATE_RING] = {};
+    uint64_t ring_head = 0;        // copies enqueued
+    uint64_t ring_seen = 0;        // copies consumed (or dropped)
 
     SortWorkspace sortws;
     MsdWorkspace msdws;

@@ -186,3 +186,34 @@ def headline(theta: Optional[float] = None, load_log2: int = 26, query_log2: int
     """64M-key search workload: 2^26 loaded keys, batches of 2^22 SEARCH."""
     return search_only(6, 1 << load_log2, 1 << query_log2, n_batches, theta,
                        name=f"search-2^{load_log2}-{'zipf' + str(theta) if theta else 'uniform'}")
+
+
+@dataclass
+class RangeWorkload:
+    name: str
+    load_keys: np.ndarray
+    load_vals: np.ndarray
+    batches: List[tuple] = field(default_factory=list)  # (lo, hi) arrays
+    note: str = ""
+
+
+def range_scan(load_log2: int = 26, n_ranges: int = 8192, granularity: int = 100,
+               n_batches: int = 8) -> RangeWorkload:
+    """Range searches over 2^load_log2 uniform keys (the paper's range-query
+    experiment, Section 6: batches of 8192 range queries, granularity = mean
+    number of keys per range).  lo is a uniformly chosen loaded key and
+    hi = lo + U(0, 2) * granularity * (mean gap between loaded keys)."""
+    base = workload_base(7)
+    n_load = 1 << load_log2
+    lk = unique_uniform_keys(n_load, rng_for(base, ST_LOAD))
+    lv = uniform_values(n_load, rng_for(base, ST_VALS, 1 << 20))
+    gap = KEY_SPACE / n_load
+    batches = []
+    for b in range(n_batches):
+        rq = rng_for(base, ST_QKEYS, (granularity << 8) + b)
+        lo = lk[rq.integers(0, n_load, size=n_ranges)]
+        width = (rq.random(n_ranges) * 2.0 * granularity * gap).astype(np.uint64)
+        batches.append((lo, lo + width))
+    return RangeWorkload(f"range-2^{load_log2}-g{granularity}", lk, lv, batches,
+                         note=f"load {n_load} uniform keys; {n_batches} x {n_ranges} ranges, "
+                              f"about {granularity} keys per range")
