@@ -86,6 +86,7 @@ pi_status fail(pi::Index &ix, pi_status code, const char *msg) {
 
 void release_all(pi::Index &ix) {
     ix.st.release();
+    ix.spare.release();
     ix.arena_key.release();
     ix.arena_down.release();
     ix.sortws.release();

@@ -178,23 +178,10 @@ __global__ void k_reset_region(uint64_t *__restrict__ skey, uint64_t *__restrict
 
 // ---- merge of the base region with the overflow nodes -----------------------
 
-__global__ void k_base_live(const uint8_t *__restrict__ smeta, uint64_t nbase, uint32_t *__restrict__ flag) {
-    const uint64_t b = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (b > nbase) return;
-    flag[b] = (b < nbase && !(smeta[1 + b] & META_DEL)) ? 1u : 0u;  // flag[nbase] = 0 (sentinel)
-}
-
-__global__ void k_ovf_gather(const uint64_t *__restrict__ skey, uint64_t first, uint64_t novf,
-                             uint64_t *__restrict__ okey, uint32_t *__restrict__ oslot) {
-    const uint64_t o = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (o >= novf) return;
-    okey[o] = skey[first + o];
-    oslot[o] = (uint32_t)(first + o);
-}
-
 // For each sorted overflow node: live flag, and p = number of base keys
 // smaller than its key (binary search; keys are unique across the list).
-__global__ void k_ovf_place(const uint64_t *__restrict__ osk, const uint32_t *__restrict__ oslot, uint64_t novf,
+__global__ void k_ovf_place(const uint64_t *__restrict__ osk, const uint32_t *__restrict__ orel, uint32_t first,
+                            uint64_t novf,
                             const uint64_t *__restrict__ skey, const uint8_t *__restrict__ smeta, uint64_t nbase,
                             uint32_t *__restrict__ olive, uint32_t *__restrict__ opos,
                             uint32_t *__restrict__ hist) {
@@ -209,7 +196,7 @@ __global__ void k_ovf_place(const uint64_t *__restrict__ osk, const uint32_t *__
         else
             hi = mid;
     }
-    const uint32_t live = (smeta[oslot[o]] & META_DEL) ? 0u : 1u;
+    const uint32_t live = (smeta[first + orel[o]] & META_DEL) ? 0u : 1u;
     olive[o] = live;
     opos[o] = (uint32_t)lo;
     if (live) atomicAdd(&hist[lo], 1u);
@@ -237,7 +224,8 @@ __global__ void k_merge_base(const uint64_t *__restrict__ skey, const uint64_t *
     if (ometa) ometa[o] = 0;
 }
 
-__global__ void k_merge_ovf(const uint64_t *__restrict__ osk, const uint32_t *__restrict__ oslot, uint64_t novf,
+__global__ void k_merge_ovf(const uint64_t *__restrict__ osk, const uint32_t *__restrict__ orel, uint32_t first,
+                            uint64_t novf,
                             const uint64_t *__restrict__ sval, const uint32_t *__restrict__ olive,
                             const uint32_t *__restrict__ C, const uint32_t *__restrict__ opos,
                             const uint32_t *__restrict__ A, uint64_t *__restrict__ okey,
@@ -246,7 +234,7 @@ __global__ void k_merge_ovf(const uint64_t *__restrict__ osk, const uint32_t *__
     if (o >= novf || !olive[o]) return;
     const uint64_t d = slot_off + A[opos[o]] + C[o];
     okey[d] = osk[o];
-    oval[d] = sval[oslot[o]];
+    oval[d] = sval[first + orel[o]];
     if (ometa) ometa[d] = 0;
 }
 
@@ -311,8 +299,10 @@ static void build_levels(Index &ix, hipStream_t s) {
             total += ((uint64_t)d.n[l] + 1 + LEVEL_PAD + 15) & ~15ull;  // 128-byte aligned levels
         }
         if (d.top >= 2) {
-            ix.arena_key.ensure(total * sizeof(uint64_t));
-            ix.arena_down.ensure(total * sizeof(uint32_t));
+            // a quarter of headroom: levels grow with the inserts between
+            // rebuilds, and reallocating costs more than the spare bytes
+            if (ix.arena_key.bytes < total * sizeof(uint64_t)) ix.arena_key.ensure(total * sizeof(uint64_t) * 5 / 4);
+            if (ix.arena_down.bytes < total * sizeof(uint32_t)) ix.arena_down.ensure(total * sizeof(uint32_t) * 5 / 4);
             hipLaunchKernelGGL(k_level_scatter, dim3(ntiles), dim3(BT), 0, s, ix.st.key.as<uint64_t>(),
                                (uint32_t)nb, ix.cfg.height_seed, ix.cfg.log2_inv_p, maxh, cnt.as<uint32_t>(),
                                ntiles, d, ix.arena_key.as<uint64_t>(), ix.arena_down.as<uint32_t>());
@@ -423,7 +413,7 @@ static uint64_t merge_live(Index &ix, uint64_t *okey, uint64_t *oval, uint8_t *o
     const uint64_t novf = cur.nused > first ? cur.nused - first : 0;
     *too_small = cur.n_live > cap;
     if (*too_small) return cur.n_live;
-    DevBuf &A = ix.tmp[0];    // base live flags -> exclusive prefix (nb+1)
+    DevBuf &A = ix.tmp[0];    // exclusive prefix of the base live flags (nb+1)
     DevBuf &H = ix.tmp[1];    // live overflow nodes placed at each base position (nb+1)
     DevBuf &B = ix.tmp[2];    // exclusive prefix of H
     DevBuf &C = ix.tmp[3];    // overflow live flags -> exclusive prefix
@@ -435,33 +425,24 @@ static uint64_t merge_live(Index &ix, uint64_t *okey, uint64_t *oval, uint8_t *o
     C.ensure((novf + 1) * 4);
     P.ensure((novf + 1) * 4);
     T.ensure(16);
-    DevBuf flagA;
-    flagA.ensure((nb + 1) * 4);
-    hipLaunchKernelGGL(k_base_live, dim3(blocks_for(nb + 1, 256)), dim3(256), 0, s, ix.st.meta.as<uint8_t>(), nb,
-                       flagA.as<uint32_t>());
     hipLaunchKernelGGL(k_fill_u32, dim3(blocks_for(nb + 1, 256)), dim3(256), 0, s, H.as<uint32_t>(), nb + 1, 0u);
     PI_LAUNCH_CHECK();
-    exclusive_scan_u32(ix.scanws, flagA.as<uint32_t>(), A.as<uint32_t>(), nb + 1, T.as<uint32_t>(), nullptr, s);
+    exclusive_scan_live(ix.scanws, ix.st.meta.as<uint8_t>() + 1, nb, A.as<uint32_t>(), T.as<uint32_t>(), s);
     const uint64_t *osk = nullptr;
-    const uint32_t *oslot = nullptr;
-    DevBuf olive;
+    const uint32_t *opos_in = nullptr;
+    DevBuf &olive = ix.tmp[7];
     if (novf > 0) {
-        DevBuf okey, oslot0;
-        okey.ensure(novf * 8);
-        oslot0.ensure(novf * 4);
         olive.ensure(novf * 4);
-        hipLaunchKernelGGL(k_ovf_gather, dim3(blocks_for(novf, 256)), dim3(256), 0, s, ix.st.key.as<uint64_t>(),
-                           first, novf, okey.as<uint64_t>(), oslot0.as<uint32_t>());
-        PI_LAUNCH_CHECK();
-        sort_pairs(ix.sortws, okey.as<uint64_t>(), oslot0.as<uint32_t>(), novf, s, &osk, &oslot);
-        hipLaunchKernelGGL(k_ovf_place, dim3(blocks_for(novf, 256)), dim3(256), 0, s, osk, oslot, novf,
-                           ix.st.key.as<uint64_t>(), ix.st.meta.as<uint8_t>(), nb, olive.as<uint32_t>(),
+        // the overflow region holds distinct keys: the batch ordering (range
+        // groups + in-group fix-up) sorts them fully; the payload is the
+        // position in the region, so the slot is first + payload
+        sort_batch_by_range(ix.sortws, ix.msdws, ix.st.key.as<uint64_t>() + first, nullptr, novf, nullptr, s, &osk,
+                            &opos_in);
+        hipLaunchKernelGGL(k_ovf_place, dim3(blocks_for(novf, 256)), dim3(256), 0, s, osk, opos_in, (uint32_t)first,
+                           novf, ix.st.key.as<uint64_t>(), ix.st.meta.as<uint8_t>(), nb, olive.as<uint32_t>(),
                            P.as<uint32_t>(), H.as<uint32_t>());
         PI_LAUNCH_CHECK();
         exclusive_scan_u32(ix.scanws, olive.as<uint32_t>(), C.as<uint32_t>(), novf, T.as<uint32_t>() + 1, nullptr, s);
-        PI_HIP(hipStreamSynchronize(s));
-        okey.release();
-        oslot0.release();
     }
     exclusive_scan_u32(ix.scanws, H.as<uint32_t>(), B.as<uint32_t>(), nb + 1, T.as<uint32_t>() + 2, nullptr, s);
     {
@@ -478,13 +459,11 @@ static uint64_t merge_live(Index &ix, uint64_t *okey, uint64_t *oval, uint8_t *o
                            ix.st.val.as<uint64_t>(), ix.st.meta.as<uint8_t>(), nb, A.as<uint32_t>(),
                            B.as<uint32_t>(), H.as<uint32_t>(), okey, oval, ometa, slot_off);
     if (novf > 0)
-        hipLaunchKernelGGL(k_merge_ovf, dim3(blocks_for(novf, 256)), dim3(256), 0, s, osk, oslot, novf,
+        hipLaunchKernelGGL(k_merge_ovf, dim3(blocks_for(novf, 256)), dim3(256), 0, s, osk, opos_in, (uint32_t)first, novf,
                            ix.st.val.as<uint64_t>(), olive.as<uint32_t>(), C.as<uint32_t>(), P.as<uint32_t>(),
                            A.as<uint32_t>(), okey, oval, ometa, slot_off);
     PI_LAUNCH_CHECK();
     PI_HIP(hipStreamSynchronize(s));
-    flagA.release();
-    olive.release();
     return cur.n_live;
 }
 
@@ -507,11 +486,23 @@ void rebuild(Index &ix, hipStream_t s) {
     const uint64_t live = cur.n_live;
     uint64_t ncap = ix.cfg.capacity_hint ? ix.cfg.capacity_hint
                                          : std::max<uint64_t>(ix.st.cap, live + 2 + std::max<uint64_t>(live / 4, 1 << 16));
-    Storage ns;
-    ns.alloc(ncap);
+    // the new base region goes to the spare storage (the one replaced by the
+    // previous rebuild) when it is large enough; the current one becomes the
+    // spare
+    Storage ns = ix.spare;
+    ix.spare = Storage{};
+    if (ns.cap < ncap || (ix.cfg.capacity_hint && ns.cap != ncap)) {
+        ns.release();
+        ns.alloc(ncap);
+    }
     bool small = false;
-    merge_live(ix, ns.key.as<uint64_t>(), ns.val.as<uint64_t>(), ns.meta.as<uint8_t>(), 1, ~0ull, s, &small);
-    ix.st.release();
+    try {
+        merge_live(ix, ns.key.as<uint64_t>(), ns.val.as<uint64_t>(), ns.meta.as<uint8_t>(), 1, ~0ull, s, &small);
+    } catch (...) {
+        ix.spare = ns;
+        throw;
+    }
+    ix.spare = ix.st;
     ix.st = ns;
     ix.nbase = live;
     hipLaunchKernelGGL(k_reset_region, dim3(1), dim3(64), 0, s, ix.st.key.as<uint64_t>(), ix.st.val.as<uint64_t>(),

@@ -51,6 +51,7 @@ struct Index {
     std::string err;
 
     Storage st;
+    Storage spare;                 // the previous storage, reused by the next rebuild
     uint64_t nbase = 0;        // base-region nodes
     uint64_t used_upper = 2;   // host upper bound of DevState::nused
     uint64_t live_at_rebuild = 0;
@@ -75,7 +76,7 @@ struct Index {
     MsdWorkspace msdws;
     ScanWorkspace scanws;
     BatchWorkspace bws;
-    DevBuf tmp[6];                 // rebuild / export scratch
+    DevBuf tmp[10];                // rebuild / export scratch
     DevBuf rng[4];                 // range search: first node, end slot, counts, scan tiles
     uint64_t *hcounts = nullptr;   // pinned: level totals etc.
     int num_cus = 256;

@@ -223,5 +223,10 @@ struct ScanWorkspace {
 // d_enable is not null and *d_enable == 0 the kernels do nothing.
 void exclusive_scan_u32(ScanWorkspace &ws, const uint32_t *in, uint32_t *out, uint64_t n,
                         uint32_t *d_total, const unsigned int *d_enable, hipStream_t s);
+// Same over the live flags of the base region: out[i] (i = 0 .. nbase) =
+// number of slots 1 .. i that are not flagged deleted, from the node flags of
+// slot 1 onwards; *d_total = the live count.
+void exclusive_scan_live(ScanWorkspace &ws, const uint8_t *meta_slot1, uint64_t nbase, uint32_t *out,
+                         uint32_t *d_total, hipStream_t s);
 
 }  // namespace pi

@@ -12,8 +12,46 @@ constexpr int CI = 16;
 constexpr int CTILE = CT * CI;
 constexpr int NW = CT / 64;
 
-__global__ __launch_bounds__(CT) void k_scan_reduce(const uint32_t *__restrict__ in, uint64_t n,
-                                                    uint32_t *__restrict__ tiles, const unsigned int *en) {
+// Sources of the scanned values: a u32 array, or the live flags of the base
+// region read straight from the node flags (flag i = slot 1 + i is not
+// deleted, for i < nbase; 0 at i = nbase).
+struct SrcU32 {
+    const uint32_t *p;
+    __device__ __forceinline__ uint32_t at(uint64_t i) const { return p[i]; }
+    // CI consecutive values from i0 (16-byte loads when aligned and in range)
+    __device__ __forceinline__ void block(uint64_t i0, uint64_t n, uint32_t (&v)[CI]) const {
+        const uint32_t *q = p + i0;
+        if (i0 + CI <= n && (reinterpret_cast<uintptr_t>(q) & 15u) == 0) {
+#pragma unroll
+            for (int j = 0; j < CI / 4; j++) {
+                const uint4 x = reinterpret_cast<const uint4 *>(q)[j];
+                v[4 * j] = x.x;
+                v[4 * j + 1] = x.y;
+                v[4 * j + 2] = x.z;
+                v[4 * j + 3] = x.w;
+            }
+        } else {
+#pragma unroll
+            for (int j = 0; j < CI; j++) v[j] = i0 + j < n ? q[j] : 0u;
+        }
+    }
+};
+
+struct SrcLive {
+    const uint8_t *meta;  // flags of slot 1 onwards
+    uint64_t nbase;
+    __device__ __forceinline__ uint32_t at(uint64_t i) const {
+        return (i < nbase && !(meta[i] & META_DEL)) ? 1u : 0u;
+    }
+    __device__ __forceinline__ void block(uint64_t i0, uint64_t n, uint32_t (&v)[CI]) const {
+#pragma unroll
+        for (int j = 0; j < CI; j++) v[j] = i0 + j < n ? at(i0 + j) : 0u;
+    }
+};
+
+template <class Src>
+__global__ __launch_bounds__(CT) void k_scan_reduce(Src src, uint64_t n, uint32_t *__restrict__ tiles,
+                                                    const unsigned int *en) {
     if (en && *en == 0) return;
     __shared__ uint32_t s_w[NW];
     const uint64_t base = (uint64_t)blockIdx.x * CTILE;
@@ -21,7 +59,7 @@ __global__ __launch_bounds__(CT) void k_scan_reduce(const uint32_t *__restrict__
 #pragma unroll 4
     for (int j = 0; j < CI; j++) {
         const uint64_t i = base + (uint64_t)j * CT + threadIdx.x;
-        if (i < n) sum += in[i];
+        if (i < n) sum += src.at(i);
     }
     sum = wave_sum_u32(sum);
     if (lane_id() == 0) s_w[threadIdx.x >> 6] = sum;
@@ -63,28 +101,52 @@ __global__ __launch_bounds__(CT) void k_scan_tiles(uint32_t *__restrict__ tiles,
     if (threadIdx.x == 0 && total) *total = carry;
 }
 
-__global__ __launch_bounds__(CT) void k_scan_down(const uint32_t *__restrict__ in, uint32_t *__restrict__ out,
-                                                  uint64_t n, const uint32_t *__restrict__ tiles,
-                                                  const unsigned int *en) {
+template <class Src>
+__global__ __launch_bounds__(CT) void k_scan_down(Src src, uint32_t *__restrict__ out, uint64_t n,
+                                                  const uint32_t *__restrict__ tiles, const unsigned int *en) {
     if (en && *en == 0) return;
     __shared__ uint32_t s_tmp[NW + 1];
     const uint64_t base = (uint64_t)blockIdx.x * CTILE + (uint64_t)threadIdx.x * CI;
     uint32_t v[CI];
+    src.block(base, n, v);
     uint32_t sum = 0;
 #pragma unroll
-    for (int j = 0; j < CI; j++) {
-        const uint64_t i = base + j;
-        v[j] = i < n ? in[i] : 0u;
-        sum += v[j];
-    }
+    for (int j = 0; j < CI; j++) sum += v[j];
     uint32_t tot;
     uint32_t run = tiles[blockIdx.x] + block_excl_scan_u32<CT>(sum, s_tmp, &tot);
+    uint32_t r[CI];
 #pragma unroll
     for (int j = 0; j < CI; j++) {
-        const uint64_t i = base + j;
-        if (i < n) out[i] = run;
+        r[j] = run;
         run += v[j];
     }
+    uint32_t *o = out + base;
+    if (base + CI <= n && (reinterpret_cast<uintptr_t>(o) & 15u) == 0) {
+#pragma unroll
+        for (int j = 0; j < CI / 4; j++)
+            reinterpret_cast<uint4 *>(o)[j] = make_uint4(r[4 * j], r[4 * j + 1], r[4 * j + 2], r[4 * j + 3]);
+    } else {
+#pragma unroll
+        for (int j = 0; j < CI; j++)
+            if (base + j < n) o[j] = r[j];
+    }
+}
+
+template <class Src>
+void scan_impl(ScanWorkspace &ws, Src src, uint32_t *out, uint64_t n, uint32_t *d_total,
+               const unsigned int *d_enable, hipStream_t s) {
+    ws.ensure(n);
+    const uint32_t ntiles = (uint32_t)((n + CTILE - 1) / CTILE);
+    uint32_t *tiles = ws.tiles.as<uint32_t>();
+    if (n == 0) {
+        hipLaunchKernelGGL(k_scan_tiles, dim3(1), dim3(CT), 0, s, tiles, 0u, d_total, d_enable);
+        PI_LAUNCH_CHECK();
+        return;
+    }
+    hipLaunchKernelGGL(k_scan_reduce<Src>, dim3(ntiles), dim3(CT), 0, s, src, n, tiles, d_enable);
+    hipLaunchKernelGGL(k_scan_tiles, dim3(1), dim3(CT), 0, s, tiles, ntiles, d_total, d_enable);
+    hipLaunchKernelGGL(k_scan_down<Src>, dim3(ntiles), dim3(CT), 0, s, src, out, n, tiles, d_enable);
+    PI_LAUNCH_CHECK();
 }
 
 }  // namespace
@@ -98,18 +160,12 @@ void ScanWorkspace::release() { tiles.release(); }
 
 void exclusive_scan_u32(ScanWorkspace &ws, const uint32_t *in, uint32_t *out, uint64_t n, uint32_t *d_total,
                         const unsigned int *d_enable, hipStream_t s) {
-    ws.ensure(n);
-    const uint32_t ntiles = (uint32_t)((n + CTILE - 1) / CTILE);
-    uint32_t *tiles = ws.tiles.as<uint32_t>();
-    if (n == 0) {
-        hipLaunchKernelGGL(k_scan_tiles, dim3(1), dim3(CT), 0, s, tiles, 0u, d_total, d_enable);
-        PI_LAUNCH_CHECK();
-        return;
-    }
-    hipLaunchKernelGGL(k_scan_reduce, dim3(ntiles), dim3(CT), 0, s, in, n, tiles, d_enable);
-    hipLaunchKernelGGL(k_scan_tiles, dim3(1), dim3(CT), 0, s, tiles, ntiles, d_total, d_enable);
-    hipLaunchKernelGGL(k_scan_down, dim3(ntiles), dim3(CT), 0, s, in, out, n, tiles, d_enable);
-    PI_LAUNCH_CHECK();
+    scan_impl(ws, SrcU32{in}, out, n, d_total, d_enable, s);
+}
+
+void exclusive_scan_live(ScanWorkspace &ws, const uint8_t *meta_slot1, uint64_t nbase, uint32_t *out,
+                         uint32_t *d_total, hipStream_t s) {
+    scan_impl(ws, SrcLive{meta_slot1, nbase}, out, nbase + 1, d_total, nullptr, s);
 }
 
 }  // namespace pi
