@@ -191,6 +191,52 @@ def run_write(args):
         "cpu_baseline": None}), flush=True)
 
 
+def run_serve(args):
+    """Serving loop (--workload serve): 2^25 loaded keys, open-loop Poisson
+    arrivals at each rate of --rates for --serve-ms of arrivals, 90/5/5
+    S/I/D with Zipf 0.8 keys.  Continuous batching (100 us deadline, 4
+    micro-batches in flight) beside launch-and-wait batching (1 in flight,
+    no deadline).  One JSON line per rate and mode."""
+    import numpy as np
+    import torch
+
+    from paper_1601_00159_amd import workloads as W
+    from paper_1601_00159_amd.index import Index
+
+    for rate in [float(x) for x in args.rates.split(",")]:
+        n = int(rate * args.serve_ms / 1e3)
+        t0 = time.perf_counter()
+        w = W.serving(args.load_log2 if args.load_log2 != 26 else 25, rate, n)
+        log(f"workload {w.name}: {w.note}; generated in {time.perf_counter() - t0:.1f}s")
+        for mode, deadline, inflight in (("continuous", 100.0, 4), ("launch-and-wait", 0.0, 1)):
+            with Index(device=0) as ix:
+                ix.bulk_load(w.load_keys, w.load_vals)
+                torch.cuda.synchronize()
+                gv, gs, done, ends = ix.serve(w.arrival_us, w.ops, w.keys, w.vals, deadline_us=deadline,
+                                              max_inflight=inflight)
+                torch.cuda.synchronize()
+                st = ix.stats()
+            lat = done - w.arrival_us
+            starts = np.concatenate([[0], ends[:-1]])
+            blat = done[ends - 1] - w.arrival_us[starts]
+            span_s = (done.max() - w.arrival_us[0]) / 1e6
+            print(json.dumps({
+                "metric": "Mqueries/s served (open-loop arrivals) at p99 latency", "value": round(n / span_s / 1e6, 2),
+                "unit": "Mqueries/s", "n_gpus": 1, "steps": int(ends.size), "warmup": 0,
+                "ms_per_step": round(span_s * 1e3 / max(ends.size, 1), 4), "higher_is_better": True,
+                "scaling": "weak", "vs_baseline": None, "dtype": "u64", "data": "synthetic",
+                "config": {"workload": w.name, "loaded_keys": int(w.load_keys.size), "queries": n,
+                           "offered_Mqps": rate / 1e6, "op_mix": "90/5/5 S/I/D", "key_distribution": "zipf 0.8",
+                           "mode": mode, "deadline_us": deadline, "max_inflight": inflight,
+                           "parallelism": "single GPU"},
+                "latency_us": {"query_p50": round(float(np.percentile(lat, 50)), 1),
+                               "query_p99": round(float(np.percentile(lat, 99)), 1),
+                               "batch_p50": round(float(np.percentile(blat, 50)), 1),
+                               "batch_p99": round(float(np.percentile(blat, 99)), 1)},
+                "micro_batches": int(ends.size), "mean_batch": round(n / max(ends.size, 1), 1),
+                "rebuilds": st["repairs"], "roofline": None, "cpu_baseline": None}), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -207,9 +253,11 @@ def main():
     ap.add_argument("--blocks-per-cu", type=int, default=0)
     ap.add_argument("--lds-budget", type=int, default=0)
     ap.add_argument("--descent-block", type=int, default=0)
-    ap.add_argument("--workload", choices=["search", "range", "write"], default="search",
+    ap.add_argument("--workload", choices=["search", "range", "write", "serve"], default="search",
                     help="search: the 64M-key SEARCH batches (default); range: range searches; "
-                         "write: write-heavy Zipf batches")
+                         "write: write-heavy Zipf batches; serve: continuous batching of Poisson arrivals")
+    ap.add_argument("--rates", default="50e6,200e6,500e6", help="offered queries/s (--workload serve)")
+    ap.add_argument("--serve-ms", type=float, default=20.0, help="ms of arrivals per rate (--workload serve)")
     ap.add_argument("--ranges", type=int, default=8192, help="range queries per batch (--workload range)")
     ap.add_argument("--granularity", default="1,10,100,1000", help="mean keys per range (--workload range)")
     args = ap.parse_args()
@@ -220,7 +268,7 @@ def main():
     if args.workload != "search":
         import torch
         assert torch.cuda.is_available(), "bench needs a GPU"
-        return run_range(args) if args.workload == "range" else run_write(args)
+        return {"range": run_range, "write": run_write, "serve": run_serve}[args.workload](args)
 
     import numpy as np
     import torch

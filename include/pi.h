@@ -189,6 +189,40 @@ pi_status pi_range_count(pi_index *idx, const uint64_t *d_lo, const uint64_t *d_
 pi_status pi_range_collect(pi_index *idx, const uint64_t *d_lo, const uint64_t *d_hi, uint64_t n,
                            const uint64_t *d_offsets, uint64_t *d_keys, uint64_t *d_values, pi_stream stream);
 
+/* Serving loop: continuous batching of an open-loop arrival schedule.
+ *
+ * Query i (arrays in arrival order, device memory as for pi_execute_batch)
+ * arrives h_arrival_us[i] microseconds after the call starts (host array,
+ * non-decreasing).  The loop admits arrived queries into a micro-batch that
+ * closes deadline_us after its first query arrived, or as soon as it holds
+ * max_batch queries; a closed micro-batch is enqueued as one pi_execute_batch
+ * on the stream when fewer than max_inflight micro-batches are still running
+ * on the device, and keeps admitting arrivals (up to max_batch) while it
+ * waits for a slot.  Micro-batches are contiguous runs of the arrival order
+ * applied in that order, so every answer equals that of applying all n
+ * queries one by one in arrival order (the serial semantics of
+ * pi_execute_batch); the batching changes only when answers are ready.
+ *
+ * Outputs: d_out_values/d_out_status as for pi_execute_batch; h_done_us[i]
+ * (host) = device completion time of query i's micro-batch, microseconds
+ * since the call started; h_batch_end (host, capacity n) = end index of each
+ * micro-batch, *n_batches of them.  Returns when every query is answered
+ * (synchronises the stream).  Errors: PI_ERR_INVALID_ARG for NULL pointers,
+ * a wrong struct_size, max_batch above 2^31 - 1, max_inflight above 64 or
+ * decreasing arrival times. */
+typedef struct {
+    uint32_t struct_size;   /* sizeof(pi_serve_config) */
+    uint32_t max_inflight;  /* micro-batches on the device at once (0 = 4) */
+    double deadline_us;     /* micro-batch deadline after its first arrival (default 100) */
+    uint64_t max_batch;     /* queries per micro-batch (0 = as many as free device memory allows, <= 2^22) */
+} pi_serve_config;
+
+pi_status pi_serve_config_default(pi_serve_config *cfg);
+pi_status pi_serve(pi_index *idx, const pi_serve_config *cfg, const double *h_arrival_us, const uint8_t *d_ops,
+                   const uint64_t *d_keys, const uint64_t *d_values, uint64_t n, uint64_t *d_out_values,
+                   uint8_t *d_out_status, double *h_done_us, uint64_t *h_batch_end, uint64_t *n_batches,
+                   pi_stream stream);
+
 /* Copies the counters into *out (host).  Synchronises the index's device. */
 pi_status pi_get_stats(pi_index *idx, pi_stats *out);
 

@@ -51,8 +51,13 @@ class pi_stats(ctypes.Structure):
 
 
 EXPORTED = ["pi_config_default", "pi_create", "pi_destroy", "pi_bulk_load", "pi_execute_batch",
-            "pi_repair", "pi_export", "pi_range_count", "pi_range_collect", "pi_get_stats", "pi_get_profile", "pi_last_error", "pi_debug_interceptions",
+            "pi_repair", "pi_export", "pi_range_count", "pi_range_collect", "pi_serve_config_default", "pi_serve", "pi_get_stats", "pi_get_profile", "pi_last_error", "pi_debug_interceptions",
             "pi_debug_level", "pi_debug_sort"]
+
+
+class pi_serve_config(ctypes.Structure):
+    _fields_ = [("struct_size", ctypes.c_uint32), ("max_inflight", ctypes.c_uint32),
+                ("deadline_us", ctypes.c_double), ("max_batch", ctypes.c_uint64)]
 
 
 class PiError(RuntimeError):
@@ -76,6 +81,9 @@ def load(path: str = LIB_PATH):
         "pi_export": ([vp, vp, vp, u64, ctypes.POINTER(u64), vp], i32),
         "pi_range_count": ([vp, vp, vp, u64, vp, vp], i32),
         "pi_range_collect": ([vp, vp, vp, u64, vp, vp, vp, vp], i32),
+        "pi_serve_config_default": ([ctypes.POINTER(pi_serve_config)], i32),
+        "pi_serve": ([vp, ctypes.POINTER(pi_serve_config), vp, vp, vp, vp, u64, vp, vp, vp, vp,
+                      ctypes.POINTER(u64), vp], i32),
         "pi_get_stats": ([vp, ctypes.POINTER(pi_stats)], i32),
         "pi_get_profile": ([vp, ctypes.POINTER(pi_profile), i32], i32),
         "pi_last_error": ([vp], ctypes.c_char_p),

@@ -168,6 +168,16 @@ void ensure_capacity(pi::Index &ix, const uint8_t *ops, const uint64_t *keys, ui
 
 extern "C" {
 
+pi_status pi_serve_config_default(pi_serve_config *cfg) {
+    if (!cfg) return PI_ERR_INVALID_ARG;
+    std::memset(cfg, 0, sizeof(*cfg));
+    cfg->struct_size = sizeof(pi_serve_config);
+    cfg->max_inflight = 4;
+    cfg->deadline_us = 100.0;
+    cfg->max_batch = 0;
+    return PI_OK;
+}
+
 pi_status pi_config_default(pi_config *cfg) {
     if (!cfg) return PI_ERR_INVALID_ARG;
     std::memset(cfg, 0, sizeof(*cfg));
@@ -285,6 +295,22 @@ pi_status pi_bulk_load(pi_index *h, const uint64_t *d_keys, const uint64_t *d_va
     });
 }
 
+// One batch: the rebuild decision, room for the batch's new nodes, the hot
+// path, the queued counter copy.
+void batch_step(pi::Index &ix, const uint8_t *d_ops, const uint64_t *d_keys, const uint64_t *d_values, uint64_t n,
+                uint64_t *d_out_values, uint8_t *d_out_status, hipStream_t s) {
+    maybe_rebuild(ix, s);
+    ensure_capacity(ix, d_ops, d_keys, n, s);
+    pi::execute_batch(ix, d_ops, d_keys, d_values, n, d_out_values, d_out_status, s);
+    ix.used_upper = std::min<uint64_t>(ix.used_upper + n, ~0ull);
+    push_state(ix, s);
+    if (ix.cfg.rebuild_policy == PI_REBUILD_ALWAYS) {
+        pi::DevState cur;
+        pi::read_state(ix, s, &cur);
+        if (cur.changes > 0) pi::rebuild(ix, s);
+    }
+}
+
 pi_status pi_execute_batch(pi_index *h, const uint8_t *d_ops, const uint64_t *d_keys, const uint64_t *d_values,
                            uint64_t n, uint64_t *d_out_values, uint8_t *d_out_status, pi_stream stream) {
     return guarded(h, [&](pi::Index &ix) -> pi_status {
@@ -292,17 +318,39 @@ pi_status pi_execute_batch(pi_index *h, const uint8_t *d_ops, const uint64_t *d_
         if (n > MAX_BATCH) return fail(ix, PI_ERR_INVALID_ARG, "n too large");
         if (!d_ops || !d_keys || !d_values || !d_out_values || !d_out_status)
             return fail(ix, PI_ERR_INVALID_ARG, "NULL pointer");
+        batch_step(ix, d_ops, d_keys, d_values, n, d_out_values, d_out_status, (hipStream_t)stream);
+        return PI_OK;
+    });
+}
+
+pi_status pi_serve(pi_index *h, const pi_serve_config *cfg, const double *h_arrival_us, const uint8_t *d_ops,
+                   const uint64_t *d_keys, const uint64_t *d_values, uint64_t n, uint64_t *d_out_values,
+                   uint8_t *d_out_status, double *h_done_us, uint64_t *h_batch_end, uint64_t *n_batches,
+                   pi_stream stream) {
+    return guarded(h, [&](pi::Index &ix) -> pi_status {
+        if (!cfg || cfg->struct_size != sizeof(pi_serve_config)) return fail(ix, PI_ERR_INVALID_ARG, "bad config");
+        if (!n_batches) return fail(ix, PI_ERR_INVALID_ARG, "n_batches is NULL");
+        *n_batches = 0;
+        if (n == 0) return PI_OK;
+        if (!h_arrival_us || !d_ops || !d_keys || !d_values || !d_out_values || !d_out_status || !h_done_us ||
+            !h_batch_end)
+            return fail(ix, PI_ERR_INVALID_ARG, "NULL pointer");
+        if (!(cfg->deadline_us >= 0.0) || cfg->max_batch > MAX_BATCH || cfg->max_inflight > 64)
+            return fail(ix, PI_ERR_INVALID_ARG, "bad config");
+        for (uint64_t i = 1; i < n; i++)
+            if (!(h_arrival_us[i] >= h_arrival_us[i - 1]))
+                return fail(ix, PI_ERR_INVALID_ARG, "arrival times must be non-decreasing");
         hipStream_t s = (hipStream_t)stream;
-        maybe_rebuild(ix, s);
-        ensure_capacity(ix, d_ops, d_keys, n, s);
-        pi::execute_batch(ix, d_ops, d_keys, d_values, n, d_out_values, d_out_status, s);
-        ix.used_upper = std::min<uint64_t>(ix.used_upper + n, ~0ull);
-        push_state(ix, s);
-        if (ix.cfg.rebuild_policy == PI_REBUILD_ALWAYS) {
-            pi::DevState cur;
-            pi::read_state(ix, s, &cur);
-            if (cur.changes > 0) pi::rebuild(ix, s);
-        }
+        pi::ServePlan plan;
+        plan.deadline_us = cfg->deadline_us;
+        plan.max_inflight = cfg->max_inflight ? cfg->max_inflight : 4;
+        plan.max_batch = cfg->max_batch ? cfg->max_batch : pi::serve_batch_limit(ix, plan.max_inflight);
+        *n_batches = pi::serve_loop(
+            h_arrival_us, n, plan, s,
+            [&](uint64_t b, uint64_t e) {
+                batch_step(ix, d_ops + b, d_keys + b, d_values + b, e - b, d_out_values + b, d_out_status + b, s);
+            },
+            h_done_us, h_batch_end);
         return PI_OK;
     });
 }

@@ -1,6 +1,7 @@
 // Host-side state of one index and the operations of the library.
 #pragma once
 
+#include <functional>
 #include <vector>
 
 #include "pi_internal.h"
@@ -97,6 +98,19 @@ void execute_batch(Index &ix, const uint8_t *ops, const uint64_t *keys, const ui
 void debug_interceptions(Index &ix, const uint64_t *keys, uint64_t n, uint64_t *icpt_keys, uint8_t *is_head,
                          hipStream_t s);
 uint64_t count_inserts(Index &ix, const uint8_t *ops, const uint64_t *keys, uint64_t n, hipStream_t s);
+
+// serve.hip
+struct ServePlan {
+    double deadline_us = 100.0;
+    uint64_t max_batch = 1u << 22;
+    uint32_t max_inflight = 4;
+};
+// Largest micro-batch that free device memory allows (at most 2^22).
+uint64_t serve_batch_limit(Index &ix, uint32_t inflight);
+// Replays the arrival schedule; launch(b, e) enqueues queries [b, e) on s.
+// Returns the number of micro-batches (their end indices in batch_end).
+uint64_t serve_loop(const double *arrival_us, uint64_t n, const ServePlan &plan, hipStream_t s,
+                    const std::function<void(uint64_t, uint64_t)> &launch, double *done_us, uint64_t *batch_end);
 
 // range.hip
 void range_count(Index &ix, const uint64_t *lo, const uint64_t *hi, uint64_t n, uint64_t *offsets, hipStream_t s);

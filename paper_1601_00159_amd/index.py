@@ -128,6 +128,31 @@ class Index:
         self._check(self._L.pi_export(self._h, _ptr(k), _ptr(v), n, ctypes.byref(got), _stream(stream)))
         return k[:got.value], v[:got.value]
 
+    def serve(self, arrival_us, ops, keys, values, deadline_us=100.0, max_batch=0, max_inflight=4, stream=None):
+        """Continuous batching of an arrival schedule (pi_serve).  Returns
+        (values, status, done_us, batch_ends): device answers, host
+        completion time per query and the end index of every micro-batch."""
+        arr = np.ascontiguousarray(arrival_us, dtype=np.float64)
+        o = to_device_u8(ops, self.device)
+        k = to_device_u64(keys, self.device)
+        v = to_device_u64(values, self.device)
+        n = k.numel()
+        assert arr.size == n and o.numel() == n and v.numel() == n
+        out_v = torch.empty(n, dtype=torch.int64, device=self.device)
+        out_s = torch.empty(n, dtype=torch.uint8, device=self.device)
+        done = np.zeros(n, dtype=np.float64)
+        ends = np.zeros(max(n, 1), dtype=np.uint64)
+        nb = ctypes.c_uint64()
+        cfg = _lib.pi_serve_config()
+        check(self._L.pi_serve_config_default(ctypes.byref(cfg)))
+        cfg.deadline_us = deadline_us
+        cfg.max_batch = max_batch
+        cfg.max_inflight = max_inflight
+        self._check(self._L.pi_serve(self._h, ctypes.byref(cfg), ctypes.c_void_p(arr.ctypes.data), _ptr(o), _ptr(k),
+                                     _ptr(v), n, _ptr(out_v), _ptr(out_s), ctypes.c_void_p(done.ctypes.data),
+                                     ctypes.c_void_p(ends.ctypes.data), ctypes.byref(nb), _stream(stream)))
+        return out_v, out_s, done, ends[:nb.value].astype(np.int64)
+
     def range_count(self, lo, hi, stream=None):
         """Output offsets u64[n+1] (int64 tensor) of range searches [lo, hi]."""
         lo = to_device_u64(lo, self.device)

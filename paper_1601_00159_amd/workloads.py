@@ -217,3 +217,38 @@ def range_scan(load_log2: int = 26, n_ranges: int = 8192, granularity: int = 100
     return RangeWorkload(f"range-2^{load_log2}-g{granularity}", lk, lv, batches,
                          note=f"load {n_load} uniform keys; {n_batches} x {n_ranges} ranges, "
                               f"about {granularity} keys per range")
+
+
+@dataclass
+class ServingWorkload:
+    name: str
+    load_keys: np.ndarray
+    load_vals: np.ndarray
+    arrival_us: np.ndarray   # float64, non-decreasing
+    ops: np.ndarray
+    keys: np.ndarray
+    vals: np.ndarray
+    note: str = ""
+
+
+def serving(load_log2: int = 25, rate_qps: float = 200e6, n_queries: int = 1 << 22, theta: float = 0.8,
+            mix=(0.9, 0.05, 0.05)) -> ServingWorkload:
+    """Open-loop Poisson arrivals at rate_qps (seeded exponential gaps) of
+    queries with the given S/I/D mix; SEARCH and DELETE keys Zipf(theta) over
+    the loaded keys, INSERT keys fresh uniform."""
+    base = workload_base(8)
+    n_load = 1 << load_log2
+    lk = unique_uniform_keys(n_load, rng_for(base, ST_LOAD))
+    lv = uniform_values(n_load, rng_for(base, ST_VALS, 1 << 20))
+    ra = rng_for(base, ST_ARRIVAL, int(rate_qps // 1000))
+    gaps = ra.exponential(1e6 / rate_qps, size=n_queries)
+    arrival = np.cumsum(gaps)
+    ops = draw_ops(n_queries, mix, rng_for(base, ST_OPS))
+    rq = rng_for(base, ST_QKEYS)
+    fresh = rq.integers(0, KEY_SPACE, size=n_queries, dtype=np.uint64)
+    hot = lk[Zipf(n_load, theta).sample(n_queries, rq)]
+    keys = np.where(ops == INSERT, fresh, hot).astype(np.uint64)
+    vals = uniform_values(n_queries, rng_for(base, ST_VALS))
+    return ServingWorkload(f"serve-2^{load_log2}-{rate_qps / 1e6:g}Mqps", lk, lv, arrival, ops, keys, vals,
+                           note=f"load {n_load} keys; {n_queries} Poisson arrivals at {rate_qps / 1e6:g} M/s, "
+                                f"mix {mix}, Zipf theta={theta}")

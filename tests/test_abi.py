@@ -37,8 +37,9 @@ def test_library_exports_every_declared_symbol():
 def test_struct_layout_matches_header(tmp_path):
     src = tmp_path / "sz.c"
     src.write_text('#include <stdio.h>\n#include <stddef.h>\n#include "pi.h"\n'
-                   'int main(void){printf("%zu %zu %zu %zu\\n", sizeof(pi_config), sizeof(pi_stats),'
-                   ' offsetof(pi_config, capacity_hint), offsetof(pi_stats, level_size));return 0;}\n')
+                   'int main(void){printf("%zu %zu %zu %zu %zu %zu\\n", sizeof(pi_config), sizeof(pi_stats),'
+                   ' offsetof(pi_config, capacity_hint), offsetof(pi_stats, level_size),'
+                   ' sizeof(pi_serve_config), offsetof(pi_serve_config, max_batch));return 0;}\n')
     exe = tmp_path / "sz"
     subprocess.run(["gcc", "-std=c11", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)], check=True)
     out = subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout.split()
@@ -46,6 +47,8 @@ def test_struct_layout_matches_header(tmp_path):
     assert int(out[1]) == ctypes.sizeof(_lib.pi_stats)
     assert int(out[2]) == _lib.pi_config.capacity_hint.offset
     assert int(out[3]) == _lib.pi_stats.level_size.offset
+    assert int(out[4]) == ctypes.sizeof(_lib.pi_serve_config)
+    assert int(out[5]) == _lib.pi_serve_config.max_batch.offset
 
 
 def test_config_default_without_gpu():
@@ -62,3 +65,7 @@ def test_config_default_without_gpu():
     # NULL handles are rejected before any device work
     assert L.pi_execute_batch(None, None, None, None, 0, None, None, None) == _lib.PI_ERR_INVALID_ARG
     assert L.pi_destroy(None) == _lib.PI_OK
+    scfg = _lib.pi_serve_config()
+    assert L.pi_serve_config_default(ctypes.byref(scfg)) == _lib.PI_OK
+    assert scfg.struct_size == ctypes.sizeof(_lib.pi_serve_config)
+    assert scfg.deadline_us == 100.0 and scfg.max_inflight == 4 and scfg.max_batch == 0

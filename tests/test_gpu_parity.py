@@ -446,3 +446,36 @@ def test_range_search_edges():
         assert c.cpu().tolist() == [3, 2, 0, 0, 1]
         assert to_numpy_u64(k).tolist() == [3, 7, 11, 7, 11, 3]
         assert to_numpy_u64(v).tolist() == [30, 70, 110, 70, 110, 30]
+
+
+# ------------------------------------------------------------ serving loop
+
+def test_serving_loop_matches_serial_replay():
+    """Continuous batching (pi_serve): every answer and the final set equal
+    the serial replay of the whole arrival stream, whatever the batching --
+    the same stream served with different deadlines, batch caps and slot
+    counts gives identical answers."""
+    w = W.serving(load_log2=16, rate_qps=100e6, n_queries=300_000)
+    ms = mapref.MapState(w.load_keys, w.load_vals)
+    wv, ws = ms.apply_batch(w.ops, w.keys, w.vals)
+    runs = []
+    for deadline, cap, inflight in [(100.0, 0, 4), (0.0, 0, 1), (20.0, 1000, 2)]:
+        with Index() as ix:
+            ix.bulk_load(w.load_keys, w.load_vals)
+            torch.cuda.synchronize()
+            gv, gs, done, ends = ix.serve(w.arrival_us, w.ops, w.keys, w.vals, deadline_us=deadline,
+                                          max_batch=cap, max_inflight=inflight)
+            torch.cuda.synchronize()
+            gv, gs = to_numpy_u64(gv), gs.cpu().numpy()
+            say(f"deadline {deadline} cap {cap} inflight {inflight}: {ends.size} micro-batches, "
+                f"p99 latency {np.percentile(done - w.arrival_us, 99):.1f} us")
+            assert_same(gv, gs, wv, ws, f"serve deadline={deadline}")
+            assert ends[-1] == w.ops.size and np.all(np.diff(ends) > 0) and ends[0] > 0
+            if cap:
+                assert np.max(np.diff(np.concatenate([[0], ends]))) <= cap
+            # a micro-batch is launched only once its queries have arrived
+            assert np.all(done >= w.arrival_us - 50.0)
+            ek, ev = export_np(ix)
+            assert np.array_equal(ek, ms.keys) and np.array_equal(ev, ms.vals)
+            runs.append(ends.size)
+    assert len(set(runs)) > 1  # the batchings differed
