@@ -88,7 +88,9 @@ typedef struct {
     uint32_t blocks_per_cu;   /* descent: cap on resident blocks per CU (0 = occupancy limit) */
     uint32_t lds_budget;      /* descent: index entries staged in LDS per block, <= 13000 (0 = 12000) */
     uint32_t descent_block;   /* descent: threads per block, 256, 512 or 1024 (0 = 1024) */
-    uint32_t reserved[2];
+    uint32_t graph_max_log2;  /* batches of up to 2^graph_max_log2 queries replay a captured HIP graph of the
+                                 hot path instead of ~26 launches; 12..22, 0 = never (default) */
+    uint32_t reserved[1];
 } pi_config;
 
 /* Accumulated device time per stage of pi_execute_batch (profile = 1). */

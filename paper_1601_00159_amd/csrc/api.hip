@@ -95,6 +95,7 @@ void release_all(pi::Index &ix) {
     ix.bws.release();
     for (auto &b : ix.tmp) b.release();
     for (auto &b : ix.rng) b.release();
+    pi::release_graphs(ix);
     if (ix.dstate) (void)hipFree(ix.dstate);
     if (ix.hstate) (void)hipHostFree(ix.hstate);
     if (ix.hcounts) (void)hipHostFree(ix.hcounts);
@@ -195,6 +196,7 @@ pi_status pi_config_default(pi_config *cfg) {
     cfg->blocks_per_cu = 0;
     cfg->lds_budget = 0;
     cfg->descent_block = 0;
+    cfg->graph_max_log2 = 0;
     return PI_OK;
 }
 
@@ -224,7 +226,8 @@ pi_status pi_create(const pi_config *cfg_in, pi_index **out) {
          cfg.queries_per_lane != 4) ||
         cfg.lds_budget > 13000 ||
         (cfg.descent_block != 0 && cfg.descent_block != 256 && cfg.descent_block != 512 &&
-         cfg.descent_block != 1024)) {
+         cfg.descent_block != 1024) ||
+        (cfg.graph_max_log2 != 0 && (cfg.graph_max_log2 < 12 || cfg.graph_max_log2 > 22))) {
         set_err("invalid pi_config field");
         return PI_ERR_INVALID_ARG;
     }
@@ -301,7 +304,11 @@ void batch_step(pi::Index &ix, const uint8_t *d_ops, const uint64_t *d_keys, con
                 uint64_t *d_out_values, uint8_t *d_out_status, hipStream_t s) {
     maybe_rebuild(ix, s);
     ensure_capacity(ix, d_ops, d_keys, n, s);
-    pi::execute_batch(ix, d_ops, d_keys, d_values, n, d_out_values, d_out_status, s);
+    const uint32_t glog = ix.cfg.graph_max_log2;
+    if (glog != 0 && !ix.prof.on && n <= (1ull << glog))
+        pi::execute_batch_graph(ix, d_ops, d_keys, d_values, n, d_out_values, d_out_status, s);
+    else
+        pi::execute_batch(ix, d_ops, d_keys, d_values, n, d_out_values, d_out_status, s);
     ix.used_upper = std::min<uint64_t>(ix.used_upper + n, ~0ull);
     push_state(ix, s);
     if (ix.cfg.rebuild_policy == PI_REBUILD_ALWAYS) {

@@ -365,9 +365,10 @@ __global__ void k_batch_end(DevState *st) {
     if (nn) st->has_links = 1;
     if (st->b_deletes) st->has_dead = 1;
     st->batches += 1;
-    st->queries += st->b_n;
+    st->queries += st->b_n - st->b_pad;
     st->hits += st->b_hits;
-    st->invalid += st->b_invalid;
+    st->invalid += st->b_invalid - st->b_pad;
+    st->b_pad = 0;
     st->new_nodes += nn;
     st->deletes += st->b_deletes;
     st->revives += st->b_revives;
@@ -573,6 +574,125 @@ void Profiler::release() {
     pending.clear();
     for (hipEvent_t e : pool) (void)hipEventDestroy(e);
     pool.clear();
+}
+
+namespace {
+
+// Copies a batch into the staging buffers of a graph of capacity cap; the
+// tail [n, cap) becomes invalid queries (op 255, key +infinity), which sort
+// last, change nothing and are subtracted from the counters.
+__global__ void k_stage_in(const uint8_t *__restrict__ ops, const uint64_t *__restrict__ keys,
+                           const uint64_t *__restrict__ vals, uint64_t n, uint64_t cap, uint8_t *__restrict__ sops,
+                           uint64_t *__restrict__ skeys, uint64_t *__restrict__ svals, DevState *st) {
+    const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i == 0) st->b_pad = (unsigned int)(cap - n);
+    if (i >= cap) return;
+    if (i < n) {
+        sops[i] = ops[i];
+        skeys[i] = keys[i];
+        svals[i] = vals[i];
+    } else {
+        sops[i] = 255;
+        skeys[i] = KEY_MAX;
+        svals[i] = 0;
+    }
+}
+
+__global__ void k_stage_out(const uint64_t *__restrict__ sv, const uint8_t *__restrict__ ss, uint64_t n,
+                            uint64_t *__restrict__ ov, uint8_t *__restrict__ os) {
+    const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    ov[i] = sv[i];
+    os[i] = ss[i];
+}
+
+// Everything a captured graph bakes in: buffer addresses and launch shape.
+std::vector<uint64_t> fingerprint(const Index &ix) {
+    std::vector<uint64_t> f;
+    auto add = [&](const DevBuf &b) {
+        f.push_back((uint64_t)(uintptr_t)b.p);
+        f.push_back(b.bytes);
+    };
+    add(ix.st.key), add(ix.st.val), add(ix.st.next), add(ix.st.meta);
+    add(ix.arena_key), add(ix.arena_down);
+    for (const DevBuf &b : ix.sortws.keys) add(b);
+    for (const DevBuf &b : ix.sortws.idx) add(b);
+    add(ix.sortws.tile_hist), add(ix.sortws.digit_tot);
+    add(ix.msdws.partials), add(ix.msdws.map), add(ix.msdws.big), add(ix.msdws.nbig), add(ix.msdws.dirty);
+    add(ix.scanws.tiles);
+    const BatchWorkspace &w = ix.bws;
+    add(w.res_val), add(w.res_flags), add(w.loc), add(w.locnext), add(w.newflag), add(w.newpos), add(w.gw);
+    add(w.agg), add(w.carry), add(w.nk), add(w.nv), add(w.npred), add(w.npnext);
+    for (const DevBuf &b : ix.stage) add(b);
+    f.push_back((uint64_t)(uintptr_t)ix.dstate);
+    const uint64_t *d = reinterpret_cast<const uint64_t *>(&ix.desc);
+    for (size_t i = 0; i < sizeof(IndexDesc) / 8; i++) f.push_back(d[i]);
+    f.push_back(ix.cfg.descent_block), f.push_back(ix.cfg.queries_per_lane), f.push_back(ix.cfg.blocks_per_cu);
+    f.push_back((uint64_t)ix.num_cus);
+    return f;
+}
+
+}  // namespace
+
+void release_graphs(Index &ix) {
+    for (auto &g : ix.graphs) {
+        if (g.exec) (void)hipGraphExecDestroy(g.exec);
+        g.exec = nullptr;
+        g.fp.clear();
+    }
+    for (auto &b : ix.stage) b.release();
+    if (ix.cap_stream) (void)hipStreamDestroy(ix.cap_stream);
+    ix.cap_stream = nullptr;
+}
+
+void execute_batch_graph(Index &ix, const uint8_t *ops, const uint64_t *keys, const uint64_t *vals, uint64_t n,
+                         uint64_t *out_vals, uint8_t *out_status, hipStream_t s) {
+    int lg = 12;
+    while ((1ull << lg) < n) lg++;
+    const uint64_t cap = 1ull << lg;
+    // every buffer the hot path touches, at the class size, before capture
+    ix.stage[0].ensure(cap);
+    ix.stage[1].ensure(cap * 8);
+    ix.stage[2].ensure(cap * 8);
+    ix.stage[3].ensure(cap * 8);
+    ix.stage[4].ensure(cap);
+    ix.bws.ensure(cap);
+    ix.sortws.ensure(cap);
+    ix.msdws.ensure(cap);
+    ix.scanws.ensure(cap);
+    uint8_t *sops = ix.stage[0].as<uint8_t>();
+    uint64_t *skeys = ix.stage[1].as<uint64_t>(), *svals = ix.stage[2].as<uint64_t>();
+    uint64_t *sov = ix.stage[3].as<uint64_t>();
+    uint8_t *sos = ix.stage[4].as<uint8_t>();
+    Index::Graph &g = ix.graphs[lg];
+    std::vector<uint64_t> fp = fingerprint(ix);
+    if (!g.exec || g.fp != fp) {
+        if (g.exec) PI_HIP(hipGraphExecDestroy(g.exec));
+        g.exec = nullptr;
+        if (!ix.cap_stream) PI_HIP(hipStreamCreateWithFlags(&ix.cap_stream, hipStreamNonBlocking));
+        PI_HIP(hipStreamBeginCapture(ix.cap_stream, hipStreamCaptureModeThreadLocal));
+        hipGraph_t graph = nullptr;
+        try {
+            execute_batch(ix, sops, skeys, svals, cap, sov, sos, ix.cap_stream);
+        } catch (...) {
+            (void)hipStreamEndCapture(ix.cap_stream, &graph);
+            if (graph) (void)hipGraphDestroy(graph);
+            throw;
+        }
+        PI_HIP(hipStreamEndCapture(ix.cap_stream, &graph));
+        const hipError_t e = hipGraphInstantiate(&g.exec, graph, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(graph);
+        PI_HIP(e);
+        // capture must not have moved any buffer
+        if (fingerprint(ix) != fp) throw Error{PI_ERR_DEVICE, "internal error: buffers moved during graph capture"};
+        g.fp = fp;
+    }
+    hipLaunchKernelGGL(k_stage_in, dim3(blocks_for(cap, 256)), dim3(256), 0, s, ops, keys, vals, n, cap, sops, skeys,
+                       svals, ix.dstate);
+    PI_LAUNCH_CHECK();
+    PI_HIP(hipGraphLaunch(g.exec, s));
+    hipLaunchKernelGGL(k_stage_out, dim3(blocks_for(n, 256)), dim3(256), 0, s, sov, sos, n, out_vals, out_status);
+    PI_LAUNCH_CHECK();
 }
 
 void debug_interceptions(Index &ix, const uint64_t *keys, uint64_t n, uint64_t *icpt_keys, uint8_t *is_head,

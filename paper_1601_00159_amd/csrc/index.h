@@ -79,6 +79,16 @@ struct Index {
     BatchWorkspace bws;
     DevBuf tmp[10];                // rebuild / export scratch
     DevBuf rng[4];                 // range search: first node, end slot, counts, scan tiles
+    // captured hot path per batch-size class 2^c (queries padded with invalid
+    // ones), valid while the buffers and launch parameters it was captured
+    // with are unchanged
+    struct Graph {
+        hipGraphExec_t exec = nullptr;
+        std::vector<uint64_t> fp;
+    };
+    Graph graphs[23];
+    DevBuf stage[5];               // graph inputs/outputs: ops, keys, values, answer values, answer status
+    hipStream_t cap_stream = nullptr;
     uint64_t *hcounts = nullptr;   // pinned: level totals etc.
     int num_cus = 256;
     Profiler prof;
@@ -95,6 +105,11 @@ void grow_storage(Index &ix, uint64_t need_slots, hipStream_t s);
 // batch.hip
 void execute_batch(Index &ix, const uint8_t *ops, const uint64_t *keys, const uint64_t *vals, uint64_t n,
                    uint64_t *out_vals, uint8_t *out_status, hipStream_t s);
+// Same result through a captured graph of the hot path for the smallest
+// power-of-two class >= n (padding with invalid queries).
+void execute_batch_graph(Index &ix, const uint8_t *ops, const uint64_t *keys, const uint64_t *vals, uint64_t n,
+                         uint64_t *out_vals, uint8_t *out_status, hipStream_t s);
+void release_graphs(Index &ix);
 void debug_interceptions(Index &ix, const uint64_t *keys, uint64_t n, uint64_t *icpt_keys, uint8_t *is_head,
                          hipStream_t s);
 uint64_t count_inserts(Index &ix, const uint8_t *ops, const uint64_t *keys, uint64_t n, hipStream_t s);

@@ -48,6 +48,7 @@ struct DevState {
     // current batch
     unsigned int b_writers, b_new, b_deletes, b_revives, b_hits, b_invalid;
     unsigned int b_n;
+    unsigned int b_pad;          // padding queries of a graph replay (not counted)
     unsigned int errors;         // internal consistency failures (must stay 0)
 };
 

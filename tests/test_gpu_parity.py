@@ -479,3 +479,33 @@ def test_serving_loop_matches_serial_replay():
             assert np.array_equal(ek, ms.keys) and np.array_equal(ev, ms.vals)
             runs.append(ends.size)
     assert len(set(runs)) > 1  # the batchings differed
+
+
+def test_graph_replays_match_eager_batches():
+    """Small batches replay a captured graph (padded to a power of two with
+    invalid queries).  The same sequence of batches -- sizes across several
+    classes, repeats of one class, a rebuild in between that forces a new
+    capture -- gives the eager path's answers and counters, replay after
+    replay, with host synchronisation between them."""
+    rng = np.random.default_rng(77)
+    lk = rng.integers(0, 1 << 63, size=100_000, dtype=np.uint64)
+    lv = rng.integers(0, 1 << 64, size=100_000, dtype=np.uint64, endpoint=False)
+    pool = np.concatenate([lk[:50_000], rng.integers(0, 1 << 63, size=50_000, dtype=np.uint64)])
+    sizes = [1, 100, 4096, 4097, 5000, 5000, 5000, 70_000, 3000, 262_144, 9]
+    batches = [_random_batch(rng, pool, n) for n in sizes]
+    res = {}
+    for mode, glog in (("eager", 0), ("graph", 18)):
+        with Index(rebuild_policy="never", graph_max_log2=glog) as ix:
+            ix.bulk_load(lk, lv)
+            out = []
+            for b, (ops, keys, vals) in enumerate(batches):
+                if b == 8:
+                    ix.repair()  # new levels and storage: the graphs must be captured again
+                out.append(run_gpu(ix, ops, keys, vals))
+            res[mode] = (out, export_np(ix), ix.stats())
+    for b in range(len(sizes)):
+        assert_same(*res["graph"][0][b], *res["eager"][0][b], f"batch {b} (n={sizes[b]})")
+    assert np.array_equal(res["graph"][1][0], res["eager"][1][0])
+    assert np.array_equal(res["graph"][1][1], res["eager"][1][1])
+    for k in ("queries", "hits", "invalid", "new_nodes", "deletes", "revives", "live_nodes"):
+        assert res["graph"][2][k] == res["eager"][2][k], k
