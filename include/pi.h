@@ -90,7 +90,8 @@ typedef struct {
     uint32_t descent_block;   /* descent: threads per block, 256, 512 or 1024 (0 = 1024) */
     uint32_t graph_max_log2;  /* batches of up to 2^graph_max_log2 queries replay a captured HIP graph of the
                                  hot path instead of ~26 launches; 12..22, 0 = never (default) */
-    uint32_t reserved[1];
+    uint32_t small_batch_log2; /* batches of at most 2^small_batch_log2 queries run in one workgroup, one
+                                 launch (0 = 10, i.e. 1024; 1..12; 255 = never) */
 } pi_config;
 
 /* Accumulated device time per stage of pi_execute_batch (profile = 1). */

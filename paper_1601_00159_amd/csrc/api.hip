@@ -197,6 +197,7 @@ pi_status pi_config_default(pi_config *cfg) {
     cfg->lds_budget = 0;
     cfg->descent_block = 0;
     cfg->graph_max_log2 = 0;
+    cfg->small_batch_log2 = 0;
     return PI_OK;
 }
 
@@ -227,7 +228,8 @@ pi_status pi_create(const pi_config *cfg_in, pi_index **out) {
         cfg.lds_budget > 13000 ||
         (cfg.descent_block != 0 && cfg.descent_block != 256 && cfg.descent_block != 512 &&
          cfg.descent_block != 1024) ||
-        (cfg.graph_max_log2 != 0 && (cfg.graph_max_log2 < 12 || cfg.graph_max_log2 > 22))) {
+        (cfg.graph_max_log2 != 0 && (cfg.graph_max_log2 < 12 || cfg.graph_max_log2 > 22)) ||
+        (cfg.small_batch_log2 > 12 && cfg.small_batch_log2 != 255)) {
         set_err("invalid pi_config field");
         return PI_ERR_INVALID_ARG;
     }
@@ -304,8 +306,11 @@ void batch_step(pi::Index &ix, const uint8_t *d_ops, const uint64_t *d_keys, con
                 uint64_t *d_out_values, uint8_t *d_out_status, hipStream_t s) {
     maybe_rebuild(ix, s);
     ensure_capacity(ix, d_ops, d_keys, n, s);
+    const uint32_t slog = ix.cfg.small_batch_log2 ? ix.cfg.small_batch_log2 : 10;
     const uint32_t glog = ix.cfg.graph_max_log2;
-    if (glog != 0 && !ix.prof.on && n <= (1ull << glog))
+    if (slog != 255 && n <= (1ull << slog))
+        pi::execute_batch_small(ix, d_ops, d_keys, d_values, n, d_out_values, d_out_status, s);
+    else if (glog != 0 && !ix.prof.on && n <= (1ull << glog))
         pi::execute_batch_graph(ix, d_ops, d_keys, d_values, n, d_out_values, d_out_status, s);
     else
         pi::execute_batch(ix, d_ops, d_keys, d_values, n, d_out_values, d_out_status, s);

@@ -110,6 +110,11 @@ void execute_batch(Index &ix, const uint8_t *ops, const uint64_t *keys, const ui
 void execute_batch_graph(Index &ix, const uint8_t *ops, const uint64_t *keys, const uint64_t *vals, uint64_t n,
                          uint64_t *out_vals, uint8_t *out_status, hipStream_t s);
 void release_graphs(Index &ix);
+
+// small.hip: the whole batch (n <= 4096) in one workgroup, one launch
+void execute_batch_small(Index &ix, const uint8_t *ops, const uint64_t *keys, const uint64_t *vals, uint64_t n,
+                         uint64_t *out_vals, uint8_t *out_status, hipStream_t s);
+uint32_t small_batch_lds_bytes();
 void debug_interceptions(Index &ix, const uint64_t *keys, uint64_t n, uint64_t *icpt_keys, uint8_t *is_head,
                          hipStream_t s);
 uint64_t count_inserts(Index &ix, const uint8_t *ops, const uint64_t *keys, uint64_t n, hipStream_t s);

@@ -509,3 +509,40 @@ def test_graph_replays_match_eager_batches():
     assert np.array_equal(res["graph"][1][1], res["eager"][1][1])
     for k in ("queries", "hits", "invalid", "new_nodes", "deletes", "revives", "live_nodes"):
         assert res["graph"][2][k] == res["eager"][2][k], k
+
+
+@pytest.mark.parametrize("policy", ["never", "always"])
+def test_small_batches_in_one_workgroup(policy):
+    """Batches of at most 4096 queries run as one workgroup (sort, descent,
+    ownership, apply and linking in one launch).  Against the oracle: hot
+    keys, chains of new nodes behind one predecessor, deletes, revives,
+    invalid queries, batch sizes across the power-of-two edges, over linked
+    and rebuilt storage."""
+    rng = np.random.default_rng({"never": 5, "always": 6}[policy])
+    lk = (rng.integers(0, 1 << 40, size=20_000, dtype=np.uint64) << np.uint64(8))  # room for keys in between
+    lv = rng.integers(0, 1 << 64, size=20_000, dtype=np.uint64, endpoint=False)
+    pool = np.concatenate([lk[:5000], lk[:200] + np.uint64(1), lk[:200] + np.uint64(2), lk[:200] + np.uint64(3),
+                           rng.integers(0, 1 << 48, size=3000, dtype=np.uint64), np.array([0], dtype=np.uint64)])
+    orc = SkipList()
+    orc.bulk_load(lk, lv)
+    with Index(rebuild_policy=policy, small_batch_log2=12) as ix:
+        ix.bulk_load(lk, lv)
+        for b, n in enumerate([1, 2, 63, 64, 65, 1000, 4095, 4096, 4096, 3000, 4096, 17, 4096]):
+            ops, keys, vals = _random_batch(rng, pool, n, p_invalid=0.02)
+            if b % 4 == 1:
+                keys[: n // 2] = pool[3]  # a hot key
+            wv, ws = orc.execute_batch(ops, keys, vals)
+            gv, gs = run_gpu(ix, ops, keys, vals)
+            assert_same(gv, gs, wv, ws, f"batch {b} (n={n})")
+        ek, ev = export_np(ix)
+        ok, ov = orc.export()
+        assert np.array_equal(ek, ok) and np.array_equal(ev, ov)
+        st = ix.stats()
+        assert st["live_nodes"] == len(orc)
+        if policy == "never":
+            assert st["overflow_nodes"] > 0
+        # small and large paths agree on one state: a large batch after small ones
+        ops, keys, vals = _random_batch(rng, pool, 50_000)
+        wv, ws = orc.execute_batch(ops, keys, vals)
+        gv, gs = run_gpu(ix, ops, keys, vals)
+        assert_same(gv, gs, wv, ws, "large batch after small ones")
