@@ -226,6 +226,58 @@ pi_status pi_serve(pi_index *idx, const pi_serve_config *cfg, const double *h_ar
                    uint8_t *d_out_status, double *h_done_us, uint64_t *h_batch_end, uint64_t *n_batches,
                    pi_stream stream);
 
+/* ---- many indices, one launch (batching form) ---------------------------
+ *
+ * A group runs one batch on each of several independent indices of one
+ * device.  Batches of at most fused_max queries run in one persistent fused
+ * launch: each workgroup takes the next (index, batch) from a work queue,
+ * largest first, and runs the whole hot path for it (ordering, descent,
+ * ownership, apply) in chunks of 4096 queries; larger batches take the
+ * multi-kernel path of pi_execute_batch.  Every index's answers and final
+ * state equal those of pi_execute_batch on that index alone.
+ *
+ * The counters of all indices are copied back once per call; threshold
+ * rebuilds and storage growth are decided from that copy at the next call
+ * (the host waits for the previous call's copy, so a group lags the device
+ * by at most one call). */
+typedef struct {
+    const uint8_t *d_ops;       /* as for pi_execute_batch; n = 0 skips the index */
+    const uint64_t *d_keys;
+    const uint64_t *d_values;
+    uint64_t n;
+    uint64_t *d_out_values;
+    uint8_t *d_out_status;
+} pi_batch;
+
+typedef struct pi_group pi_group; /* opaque: scratch and tuning of the fused launch */
+
+typedef struct {
+    uint32_t struct_size;  /* sizeof(pi_group_config) */
+    uint32_t max_indices;  /* most indices per call (0 = 4096) */
+    uint64_t fused_max;    /* largest batch run in the fused launch (0 = 4096) */
+} pi_group_config;
+
+pi_status pi_group_config_default(pi_group_config *cfg);
+pi_status pi_group_create(const pi_group_config *cfg, pi_group **out);
+/* Waits for the group's last call, then frees it (NULL ok). */
+pi_status pi_group_destroy(pi_group *g);
+/* Runs batches[i] on indices[i] for i < count, asynchronously on the stream.
+ * The indices must be distinct, live on one device and not be used by other
+ * calls until this one completes.  Errors: PI_ERR_INVALID_ARG (NULL pointers,
+ * count above max_indices, a repeated index, mixed devices, n above 2^31 - 1),
+ * PI_ERR_CAPACITY (an index with a fixed capacity has no room; nothing is
+ * enqueued). */
+pi_status pi_group_execute(pi_group *g, pi_index *const *indices, const pi_batch *batches, uint32_t count,
+                           pi_stream stream);
+/* Autotuner: replays the given batches as SEARCH-only (the indices' contents
+ * do not change; their query counters do) under several fused_max
+ * thresholds, keeps the fastest in the group and returns it in *fused_max
+ * (host).  Synchronises the stream. */
+pi_status pi_group_autotune(pi_group *g, pi_index *const *indices, const pi_batch *batches, uint32_t count,
+                            pi_stream stream, uint64_t *fused_max);
+/* Message of the last error of the group. */
+const char *pi_group_last_error(const pi_group *g);
+
 /* Copies the counters into *out (host).  Synchronises the index's device. */
 pi_status pi_get_stats(pi_index *idx, pi_stats *out);
 

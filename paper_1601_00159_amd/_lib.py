@@ -51,13 +51,23 @@ class pi_stats(ctypes.Structure):
 
 
 EXPORTED = ["pi_config_default", "pi_create", "pi_destroy", "pi_bulk_load", "pi_execute_batch",
-            "pi_repair", "pi_export", "pi_range_count", "pi_range_collect", "pi_serve_config_default", "pi_serve", "pi_get_stats", "pi_get_profile", "pi_last_error", "pi_debug_interceptions",
+            "pi_repair", "pi_export", "pi_range_count", "pi_range_collect", "pi_serve_config_default", "pi_serve", "pi_group_config_default", "pi_group_create",
+            "pi_group_destroy", "pi_group_execute", "pi_group_autotune", "pi_group_last_error", "pi_get_stats", "pi_get_profile", "pi_last_error", "pi_debug_interceptions",
             "pi_debug_level", "pi_debug_sort"]
 
 
 class pi_serve_config(ctypes.Structure):
     _fields_ = [("struct_size", ctypes.c_uint32), ("max_inflight", ctypes.c_uint32),
                 ("deadline_us", ctypes.c_double), ("max_batch", ctypes.c_uint64)]
+
+
+class pi_batch(ctypes.Structure):
+    _fields_ = [("d_ops", ctypes.c_void_p), ("d_keys", ctypes.c_void_p), ("d_values", ctypes.c_void_p),
+                ("n", ctypes.c_uint64), ("d_out_values", ctypes.c_void_p), ("d_out_status", ctypes.c_void_p)]
+
+
+class pi_group_config(ctypes.Structure):
+    _fields_ = [("struct_size", ctypes.c_uint32), ("max_indices", ctypes.c_uint32), ("fused_max", ctypes.c_uint64)]
 
 
 class PiError(RuntimeError):
@@ -84,6 +94,12 @@ def load(path: str = LIB_PATH):
         "pi_serve_config_default": ([ctypes.POINTER(pi_serve_config)], i32),
         "pi_serve": ([vp, ctypes.POINTER(pi_serve_config), vp, vp, vp, vp, u64, vp, vp, vp, vp,
                       ctypes.POINTER(u64), vp], i32),
+        "pi_group_config_default": ([ctypes.POINTER(pi_group_config)], i32),
+        "pi_group_create": ([ctypes.POINTER(pi_group_config), ctypes.POINTER(vp)], i32),
+        "pi_group_destroy": ([vp], i32),
+        "pi_group_execute": ([vp, vp, ctypes.POINTER(pi_batch), u32, vp], i32),
+        "pi_group_autotune": ([vp, vp, ctypes.POINTER(pi_batch), u32, vp, ctypes.POINTER(u64)], i32),
+        "pi_group_last_error": ([vp], ctypes.c_char_p),
         "pi_get_stats": ([vp, ctypes.POINTER(pi_stats)], i32),
         "pi_get_profile": ([vp, ctypes.POINTER(pi_profile), i32], i32),
         "pi_last_error": ([vp], ctypes.c_char_p),

@@ -7,9 +7,6 @@
 
 #include "index.h"
 
-struct pi_index {
-    pi::Index ix;
-};
 
 namespace pi {
 

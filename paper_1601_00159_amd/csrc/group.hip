@@ -1,0 +1,368 @@
+// Many independent indices, one launch: the batching form of the hot path.
+//
+// The paper splits one index into per-NUMA-node sub-indices that process
+// their own queries independently (Section 4.2); here many independent
+// indices of very different sizes share one GPU.  Batches that are small
+// enough run in one persistent fused launch: each workgroup pulls the next
+// (index, batch) item from a work queue -- items sorted largest first -- and
+// runs the whole hot path for it in LDS-sized chunks (the workgroup batch of
+// small.h), so one launch serves hundreds of indices and the host cost per
+// index is a few bytes of descriptor instead of ~26 launches.  Larger
+// batches use the GPU-wide multi-kernel path.  A workgroup is the only
+// writer of its index while it runs, which is why an index may appear once
+// per call.
+//
+// The threshold between the two paths is picked by an autotuner that times
+// SEARCH-only replays of the caller's batches.
+#include <algorithm>
+#include <chrono>
+#include <cstring>
+#include <string>
+#include <unordered_set>
+#include <vector>
+
+#include "small.h"
+
+namespace pi {
+namespace {
+
+struct GroupItem {
+    IndexView v;
+    BatchView b;
+};
+
+__global__ __launch_bounds__(SBT) void k_group_batches(const GroupItem *__restrict__ items, uint32_t nitems,
+                                                       unsigned int *next) {
+    extern __shared__ uint64_t s_raw[];
+    __shared__ uint32_t s_item;
+    for (;;) {
+        if (threadIdx.x == 0) s_item = atomicAdd(next, 1u);
+        __syncthreads();
+        const uint32_t it = s_item;
+        __syncthreads();
+        if (it >= nitems) break;
+        const GroupItem &g = items[it];
+        const uint32_t n = g.b.n;
+        for (uint32_t c = 0; c < n; c += SB_MAX) {
+            BatchView b = g.b;
+            b.ops += c;
+            b.keys += c;
+            b.vals += c;
+            b.out_vals += c;
+            b.out_status += c;
+            b.n = n - c < SB_MAX ? n - c : SB_MAX;
+            block_batch(g.v, b, s_raw);
+        }
+    }
+}
+
+__global__ void k_gather_states(DevState *const *__restrict__ src, uint32_t n, DevState *__restrict__ dst) {
+    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) dst[i] = *src[i];
+}
+
+__global__ void k_zero_counter(unsigned int *p) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) *p = 0;
+}
+
+}  // namespace
+}  // namespace pi
+
+struct pi_group {
+    pi_group_config cfg{};
+    int device = -1;
+    pi::DevBuf d_items, d_ptrs, d_states, d_counter, d_zero_ops;
+    pi::GroupItem *h_items = nullptr;
+    pi::DevState **h_ptrs = nullptr;
+    pi::DevState *h_states = nullptr;
+    uint32_t cap_items = 0;
+    std::vector<pi_index *> last;  // indices whose counters h_states holds
+    hipEvent_t ev = nullptr;
+    bool pending = false;
+    bool lds_attr = false;
+    std::string err;
+};
+
+namespace pi {
+namespace {
+
+struct GroupError {
+    pi_status code;
+    std::string msg;
+};
+
+void ensure_host(pi_group *g, uint32_t count) {
+    if (count <= g->cap_items) return;
+    if (g->h_items) (void)hipHostFree(g->h_items);
+    if (g->h_ptrs) (void)hipHostFree(g->h_ptrs);
+    if (g->h_states) (void)hipHostFree(g->h_states);
+    g->h_items = nullptr;
+    g->h_ptrs = nullptr;
+    g->h_states = nullptr;
+    PI_HIP(hipHostMalloc(&g->h_items, count * sizeof(GroupItem), hipHostMallocDefault));
+    PI_HIP(hipHostMalloc(&g->h_ptrs, count * sizeof(DevState *), hipHostMallocDefault));
+    PI_HIP(hipHostMalloc(&g->h_states, count * sizeof(DevState), hipHostMallocDefault));
+    g->cap_items = count;
+}
+
+// Counters of the previous call: storage use and the threshold rebuild.
+void settle_previous(pi_group *g, hipStream_t s) {
+    if (!g->pending) return;
+    PI_HIP(hipEventSynchronize(g->ev));
+    g->pending = false;
+    for (size_t k = 0; k < g->last.size(); k++) {
+        Index &ix = g->last[k]->ix;
+        const DevState &st = g->h_states[k];
+        if (st.errors) throw Error{PI_ERR_DEVICE, "internal error: storage walk exceeded its bound"};
+        ix.used_upper = st.nused;
+        if (ix.cfg.rebuild_policy == PI_REBUILD_NEVER) continue;
+        const double thr = std::max(1.0, (double)ix.cfg.rebuild_fraction *
+                                             (double)std::max<uint64_t>(ix.live_at_rebuild, 1));
+        if ((ix.cfg.rebuild_policy == PI_REBUILD_ALWAYS && st.changes > 0) || (double)st.changes >= thr) {
+            rebuild(ix, s);
+            ix.ring_seen = ix.ring_head;
+        }
+    }
+    g->last.clear();
+}
+
+// Room for the batch's new nodes (the host bound first, the device count
+// when the bound does not fit).
+void group_capacity(Index &ix, const pi_batch &b, hipStream_t s) {
+    if (ix.used_upper + b.n <= ix.st.cap) return;
+    DevState cur;
+    read_state(ix, s, &cur);
+    if (cur.nused + b.n <= ix.st.cap) return;
+    if (ix.cfg.capacity_hint) {
+        const uint64_t ins = count_inserts(ix, b.d_ops, b.d_keys, b.n, s);
+        if (cur.nused + ins > ix.st.cap) throw GroupError{PI_ERR_CAPACITY, "an index of the group has no room"};
+        return;
+    }
+    grow_storage(ix, std::max<uint64_t>(cur.nused + b.n, ix.st.cap * 2), s);
+}
+
+void run_group(pi_group *g, pi_index *const *indices, const pi_batch *batches, uint32_t count, hipStream_t s,
+               uint64_t fused_max, const uint8_t *ops_override) {
+    settle_previous(g, s);
+    for (uint32_t i = 0; i < count; i++)
+        if (batches[i].n) group_capacity(indices[i]->ix, batches[i], s);
+    ensure_host(g, count);
+    // large batches: the GPU-wide path
+    std::vector<uint32_t> fused;
+    for (uint32_t i = 0; i < count; i++) {
+        const pi_batch &b = batches[i];
+        if (!b.n) continue;
+        Index &ix = indices[i]->ix;
+        const uint8_t *ops = ops_override ? ops_override : b.d_ops;
+        if (b.n > fused_max) {
+            execute_batch(ix, ops, b.d_keys, b.d_values, b.n, b.d_out_values, b.d_out_status, s);
+        } else {
+            fused.push_back(i);
+        }
+        ix.used_upper = std::min<uint64_t>(ix.used_upper + b.n, ~0ull);
+    }
+    // small ones: one persistent launch, largest first
+    if (!fused.empty()) {
+        std::sort(fused.begin(), fused.end(), [&](uint32_t a, uint32_t b) { return batches[a].n > batches[b].n; });
+        const uint32_t nf = (uint32_t)fused.size();
+        for (uint32_t k = 0; k < nf; k++) {
+            const pi_batch &b = batches[fused[k]];
+            GroupItem &it = g->h_items[k];
+            it.v = index_view(indices[fused[k]]->ix);
+            it.b = BatchView{ops_override ? ops_override : b.d_ops, b.d_keys, b.d_values, (uint32_t)b.n,
+                             b.d_out_values, b.d_out_status};
+        }
+        g->d_items.ensure((size_t)g->cap_items * sizeof(GroupItem));
+        g->d_counter.ensure(64);
+        PI_HIP(hipMemcpyAsync(g->d_items.p, g->h_items, nf * sizeof(GroupItem), hipMemcpyHostToDevice, s));
+        hipLaunchKernelGGL(k_zero_counter, dim3(1), dim3(64), 0, s, g->d_counter.as<unsigned int>());
+        const uint32_t lds = SmallLds::bytes();
+        if (!g->lds_attr) {
+            PI_HIP(hipFuncSetAttribute((const void *)k_group_batches, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                       (int)lds));
+            g->lds_attr = true;
+        }
+        const uint32_t grid = std::min<uint32_t>(nf, (uint32_t)indices[fused[0]]->ix.num_cus);
+        hipLaunchKernelGGL(k_group_batches, dim3(grid), dim3(SBT), lds, s, g->d_items.as<GroupItem>(), nf,
+                           g->d_counter.as<unsigned int>());
+        PI_LAUNCH_CHECK();
+    }
+    // one copy of every index's counters
+    uint32_t ns = 0;
+    g->last.clear();
+    for (uint32_t i = 0; i < count; i++) {
+        if (!batches[i].n) continue;
+        g->h_ptrs[ns++] = indices[i]->ix.dstate;
+        g->last.push_back(indices[i]);
+    }
+    if (ns) {
+        g->d_ptrs.ensure((size_t)g->cap_items * sizeof(DevState *));
+        g->d_states.ensure((size_t)g->cap_items * sizeof(DevState));
+        PI_HIP(hipMemcpyAsync(g->d_ptrs.p, g->h_ptrs, ns * sizeof(DevState *), hipMemcpyHostToDevice, s));
+        hipLaunchKernelGGL(k_gather_states, dim3((ns + 255) / 256), dim3(256), 0, s,
+                           g->d_ptrs.as<DevState *>(), ns, g->d_states.as<DevState>());
+        PI_LAUNCH_CHECK();
+        PI_HIP(hipMemcpyAsync(g->h_states, g->d_states.p, ns * sizeof(DevState), hipMemcpyDeviceToHost, s));
+    }
+    PI_HIP(hipEventRecord(g->ev, s));
+    g->pending = true;
+}
+
+pi_status validate(pi_group *g, pi_index *const *indices, const pi_batch *batches, uint32_t count) {
+    if (count == 0) return PI_OK;
+    if (!indices || !batches) return PI_ERR_INVALID_ARG;
+    if (count > g->cfg.max_indices) return PI_ERR_INVALID_ARG;
+    std::unordered_set<const pi_index *> seen;
+    int dev = -1;
+    for (uint32_t i = 0; i < count; i++) {
+        const pi_index *h = indices[i];
+        const pi_batch &b = batches[i];
+        if (!h || h->ix.failed) return PI_ERR_INVALID_ARG;
+        if (!seen.insert(h).second) return PI_ERR_INVALID_ARG;
+        if (dev < 0) dev = h->ix.device;
+        if (h->ix.device != dev) return PI_ERR_INVALID_ARG;
+        if (b.n > (1ull << 31) - 1) return PI_ERR_INVALID_ARG;
+        if (b.n && (!b.d_ops || !b.d_keys || !b.d_values || !b.d_out_values || !b.d_out_status))
+            return PI_ERR_INVALID_ARG;
+    }
+    if (g->device >= 0 && g->device != dev) return PI_ERR_INVALID_ARG;
+    g->device = dev;
+    return PI_OK;
+}
+
+template <class F>
+pi_status group_guarded(pi_group *g, F &&f) {
+    if (!g) return PI_ERR_INVALID_ARG;
+    int prev = -1;
+    (void)hipGetDevice(&prev);
+    pi_status r = PI_OK;
+    try {
+        r = f();
+        if (r == PI_OK) g->err.clear();
+    } catch (const GroupError &e) {
+        g->err = e.msg;
+        r = e.code;
+    } catch (const Error &e) {
+        g->err = e.msg;
+        r = e.code;
+    } catch (const std::exception &e) {
+        g->err = e.what();
+        r = PI_ERR_DEVICE;
+    }
+    if (prev >= 0) (void)hipSetDevice(prev);
+    return r;
+}
+
+}  // namespace
+}  // namespace pi
+
+extern "C" {
+
+pi_status pi_group_config_default(pi_group_config *cfg) {
+    if (!cfg) return PI_ERR_INVALID_ARG;
+    std::memset(cfg, 0, sizeof(*cfg));
+    cfg->struct_size = sizeof(pi_group_config);
+    cfg->max_indices = 4096;
+    cfg->fused_max = 4096;
+    return PI_OK;
+}
+
+pi_status pi_group_create(const pi_group_config *cfg, pi_group **out) {
+    if (!out) return PI_ERR_INVALID_ARG;
+    *out = nullptr;
+    pi_group_config c;
+    pi_group_config_default(&c);
+    if (cfg) {
+        if (cfg->struct_size != sizeof(pi_group_config)) return PI_ERR_INVALID_ARG;
+        c = *cfg;
+        if (!c.max_indices) c.max_indices = 4096;
+        if (!c.fused_max) c.fused_max = 4096;
+    }
+    if (c.fused_max > (1ull << 31) - 1) return PI_ERR_INVALID_ARG;
+    pi_group *g = new pi_group;
+    g->cfg = c;
+    if (hipEventCreateWithFlags(&g->ev, hipEventDisableTiming) != hipSuccess) {
+        (void)hipGetLastError();
+        delete g;
+        return PI_ERR_DEVICE;
+    }
+    *out = g;
+    return PI_OK;
+}
+
+pi_status pi_group_destroy(pi_group *g) {
+    if (!g) return PI_OK;
+    if (g->pending) (void)hipEventSynchronize(g->ev);
+    if (g->device >= 0) (void)hipSetDevice(g->device);
+    g->d_items.release();
+    g->d_ptrs.release();
+    g->d_states.release();
+    g->d_counter.release();
+    g->d_zero_ops.release();
+    if (g->h_items) (void)hipHostFree(g->h_items);
+    if (g->h_ptrs) (void)hipHostFree(g->h_ptrs);
+    if (g->h_states) (void)hipHostFree(g->h_states);
+    if (g->ev) (void)hipEventDestroy(g->ev);
+    delete g;
+    return PI_OK;
+}
+
+pi_status pi_group_execute(pi_group *g, pi_index *const *indices, const pi_batch *batches, uint32_t count,
+                           pi_stream stream) {
+    return pi::group_guarded(g, [&]() -> pi_status {
+        const pi_status v = pi::validate(g, indices, batches, count);
+        if (v != PI_OK) {
+            g->err = "invalid group call";
+            return v;
+        }
+        if (count == 0) return PI_OK;
+        PI_HIP(hipSetDevice(g->device));
+        pi::run_group(g, indices, batches, count, (hipStream_t)stream, g->cfg.fused_max, nullptr);
+        return PI_OK;
+    });
+}
+
+pi_status pi_group_autotune(pi_group *g, pi_index *const *indices, const pi_batch *batches, uint32_t count,
+                            pi_stream stream, uint64_t *fused_max) {
+    return pi::group_guarded(g, [&]() -> pi_status {
+        const pi_status v = pi::validate(g, indices, batches, count);
+        if (v != PI_OK || !fused_max) {
+            g->err = "invalid group call";
+            return v != PI_OK ? v : PI_ERR_INVALID_ARG;
+        }
+        *fused_max = g->cfg.fused_max;
+        if (count == 0) return PI_OK;
+        PI_HIP(hipSetDevice(g->device));
+        hipStream_t s = (hipStream_t)stream;
+        uint64_t nmax = 0;
+        for (uint32_t i = 0; i < count; i++) nmax = std::max<uint64_t>(nmax, batches[i].n);
+        // all-SEARCH replays: a zero op array as long as the longest batch
+        g->d_zero_ops.ensure(std::max<uint64_t>(nmax, 1));
+        PI_HIP(hipMemsetAsync(g->d_zero_ops.p, 0, std::max<uint64_t>(nmax, 1), s));
+        const uint64_t candidates[] = {0, 1024, 4096, 16384, 65536};
+        double best = 1e30;
+        uint64_t pick = g->cfg.fused_max;
+        for (uint64_t t : candidates) {
+            double tmin = 1e30;
+            for (int rep = 0; rep < 2; rep++) {
+                PI_HIP(hipStreamSynchronize(s));
+                const auto t0 = std::chrono::steady_clock::now();
+                pi::run_group(g, indices, batches, count, s, t, g->d_zero_ops.as<uint8_t>());
+                PI_HIP(hipStreamSynchronize(s));
+                const double dt = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+                tmin = std::min(tmin, dt);
+            }
+            if (tmin < best) {
+                best = tmin;
+                pick = t;
+            }
+        }
+        g->cfg.fused_max = pick;
+        *fused_max = pick;
+        return PI_OK;
+    });
+}
+
+const char *pi_group_last_error(const pi_group *g) { return g ? g->err.c_str() : ""; }
+
+}  // extern "C"

@@ -94,6 +94,15 @@ struct Index {
     Profiler prof;
 };
 
+}  // namespace pi
+
+// The opaque handle of the C ABI.
+struct pi_index {
+    pi::Index ix;
+};
+
+namespace pi {
+
 // build.hip
 void init_empty(Index &ix, hipStream_t s);
 void bulk_load(Index &ix, const uint64_t *keys, const uint64_t *vals, uint64_t n, hipStream_t s);

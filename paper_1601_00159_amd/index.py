@@ -219,3 +219,70 @@ class Index:
         perm = torch.empty(n, dtype=torch.int32, device=self.device)
         self._check(self._L.pi_debug_sort(self._h, _ptr(k), n, _ptr(sk), _ptr(perm), _stream(stream)))
         return sk, perm
+
+
+class Group:
+    """Many indices, one launch (pi_group_*): runs one batch on each of
+    several distinct indices of one device."""
+
+    def __init__(self, fused_max: int = 0, max_indices: int = 0):
+        self._L = _lib.lib()
+        cfg = _lib.pi_group_config()
+        check(self._L.pi_group_config_default(ctypes.byref(cfg)))
+        if fused_max:
+            cfg.fused_max = fused_max
+        if max_indices:
+            cfg.max_indices = max_indices
+        h = ctypes.c_void_p()
+        check(self._L.pi_group_create(ctypes.byref(cfg), ctypes.byref(h)))
+        self._h = h
+
+    def close(self):
+        if getattr(self, "_h", None):
+            self._L.pi_group_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+    def _args(self, indices, batches):
+        """batches: per index (ops, keys, values, out_values, out_status)
+        device tensors (already converted), or None to skip the index."""
+        n = len(indices)
+        hs = (ctypes.c_void_p * n)(*[ix._h.value for ix in indices])
+        bs = (_lib.pi_batch * n)()
+        keep = []
+        for i, b in enumerate(batches):
+            if b is None:
+                bs[i].n = 0
+                continue
+            o, k, v, ov, os_ = b
+            keep.append(b)
+            bs[i].d_ops, bs[i].d_keys, bs[i].d_values = o.data_ptr(), k.data_ptr(), v.data_ptr()
+            bs[i].n = k.numel()
+            bs[i].d_out_values, bs[i].d_out_status = ov.data_ptr(), os_.data_ptr()
+        return hs, bs, keep
+
+    def _check(self, st):
+        if st != _lib.PI_OK:
+            msg = self._L.pi_group_last_error(self._h)
+            raise _lib.PiError(st, msg.decode() if msg else "")
+
+    def execute(self, indices, batches, stream=None):
+        hs, bs, _keep = self._args(indices, batches)
+        self._check(self._L.pi_group_execute(self._h, hs, bs, len(indices), _stream(stream)))
+
+    def autotune(self, indices, batches, stream=None) -> int:
+        hs, bs, _keep = self._args(indices, batches)
+        out = ctypes.c_uint64()
+        self._check(self._L.pi_group_autotune(self._h, hs, bs, len(indices), _stream(stream), ctypes.byref(out)))
+        return out.value

@@ -252,3 +252,47 @@ def serving(load_log2: int = 25, rate_qps: float = 200e6, n_queries: int = 1 << 
     return ServingWorkload(f"serve-2^{load_log2}-{rate_qps / 1e6:g}Mqps", lk, lv, arrival, ops, keys, vals,
                            note=f"load {n_load} keys; {n_queries} Poisson arrivals at {rate_qps / 1e6:g} M/s, "
                                 f"mix {mix}, Zipf theta={theta}")
+
+
+@dataclass
+class ManyIndexWorkload:
+    name: str
+    loads: List[tuple]            # per index (keys, values)
+    rounds: List[List[Batch]]     # per round, per index
+    note: str = ""
+
+
+def many_indices(n_indices: int = 512, size_log2=(10, 22), batch_log2=(8, 18), n_rounds: int = 2,
+                 mix=(0.9, 0.05, 0.05), seed_id: int = 9) -> ManyIndexWorkload:
+    """Independent indices with sizes log-uniform in 2^size_log2 and per-index
+    batches log-uniform in 2^batch_log2; SEARCH and DELETE keys uniform over
+    that index's loaded keys, INSERT keys fresh uniform."""
+    base = workload_base(seed_id)
+    rs = rng_for(base, ST_SOURCE)
+    sizes = np.round(2.0 ** rs.uniform(size_log2[0], size_log2[1], size=n_indices)).astype(np.int64)
+    loads = []
+    for i in range(n_indices):
+        lk = unique_uniform_keys(int(sizes[i]), rng_for(base, ST_LOAD, i))
+        lv = uniform_values(int(sizes[i]), rng_for(base, ST_VALS, (1 << 20) + i))
+        loads.append((lk, lv))
+    rounds = []
+    for r in range(n_rounds):
+        rb = rng_for(base, ST_SOURCE, 1 + r)
+        nq = np.round(2.0 ** rb.uniform(batch_log2[0], batch_log2[1], size=n_indices)).astype(np.int64)
+        batches = []
+        for i in range(n_indices):
+            n = int(nq[i])
+            seq = (r << 16) + i
+            ops = draw_ops(n, mix, rng_for(base, ST_OPS, seq))
+            rq = rng_for(base, ST_QKEYS, seq)
+            fresh = rq.integers(0, KEY_SPACE, size=n, dtype=np.uint64)
+            lk = loads[i][0]
+            pick = lk[rq.integers(0, lk.size, size=n)]
+            keys = np.where(ops == INSERT, fresh, pick).astype(np.uint64)
+            vals = uniform_values(n, rng_for(base, ST_VALS, seq))
+            batches.append(Batch(ops, keys, vals))
+        rounds.append(batches)
+    return ManyIndexWorkload(f"many-{n_indices}-indices", loads, rounds,
+                             note=f"{n_indices} indices, sizes 2^{size_log2[0]}..2^{size_log2[1]} "
+                                  f"(total {int(sizes.sum())} keys), batches 2^{batch_log2[0]}..2^{batch_log2[1]}, "
+                                  f"mix {mix}")

@@ -546,3 +546,72 @@ def test_small_batches_in_one_workgroup(policy):
         wv, ws = orc.execute_batch(ops, keys, vals)
         gv, gs = run_gpu(ix, ops, keys, vals)
         assert_same(gv, gs, wv, ws, "large batch after small ones")
+
+
+# ------------------------------------------------------- many indices
+
+@pytest.mark.parametrize("fused_max", [4096, 0, 16384])
+def test_group_matches_each_index_alone(fused_max):
+    """One batch on each of many indices per call (pi_group_execute): each
+    index's answers and final set equal the serial replay of its own
+    batches, whichever batches take the fused launch (fused_max 0: none;
+    16384: chunks of 4096 in one workgroup)."""
+    from paper_1601_00159_amd.index import Group
+    from paper_1601_00159_amd.index import to_device_u64 as d64, to_device_u8 as d8
+    w = W.many_indices(n_indices=24, size_log2=(8, 15), batch_log2=(5, 14), n_rounds=3, seed_id=10 + fused_max % 7)
+    dev = torch.device("cuda", 0)
+    refs = [mapref.MapState(k, v) for k, v in w.loads]
+    ixs = [Index(rebuild_policy="threshold", rebuild_fraction=0.05) for _ in w.loads]
+    try:
+        for ix, (k, v) in zip(ixs, w.loads):
+            ix.bulk_load(k, v)
+        with Group(fused_max=fused_max if fused_max else 1) as g:
+            for r, batches in enumerate(w.rounds):
+                dev_b = [(d8(b.ops, dev), d64(b.keys, dev), d64(b.vals, dev),
+                          torch.empty(len(b), dtype=torch.int64, device=dev),
+                          torch.empty(len(b), dtype=torch.uint8, device=dev)) for b in batches]
+                if r == 0:
+                    dev_b[3] = None  # an index may sit out a call
+                g.execute(ixs, dev_b)
+                torch.cuda.synchronize()
+                for i, b in enumerate(batches):
+                    if dev_b[i] is None:
+                        continue
+                    wv, ws = refs[i].apply_batch(b.ops, b.keys, b.vals)
+                    assert_same(to_numpy_u64(dev_b[i][3]), dev_b[i][4].cpu().numpy(), wv, ws,
+                                f"round {r} index {i} (n={len(b)})")
+        for i, ix in enumerate(ixs):
+            ek, ev = export_np(ix)
+            assert np.array_equal(ek, refs[i].keys) and np.array_equal(ev, refs[i].vals), i
+    finally:
+        for ix in ixs:
+            ix.close()
+
+
+def test_group_autotune_and_errors():
+    from paper_1601_00159_amd._lib import PI_ERR_INVALID_ARG
+    from paper_1601_00159_amd.index import Group
+    from paper_1601_00159_amd.index import to_device_u64 as d64, to_device_u8 as d8
+    w = W.many_indices(n_indices=8, size_log2=(10, 14), batch_log2=(6, 13), n_rounds=1, seed_id=20)
+    dev = torch.device("cuda", 0)
+    ixs = [Index() for _ in w.loads]
+    try:
+        for ix, (k, v) in zip(ixs, w.loads):
+            ix.bulk_load(k, v)
+        before = [export_np(ix) for ix in ixs]
+        b = w.rounds[0]
+        dev_b = [(d8(x.ops, dev), d64(x.keys, dev), d64(x.vals, dev), torch.empty(len(x), dtype=torch.int64, device=dev),
+                  torch.empty(len(x), dtype=torch.uint8, device=dev)) for x in b]
+        with Group() as g:
+            t = g.autotune(ixs, dev_b)
+            assert t in (0, 1024, 4096, 16384, 65536)
+            # the SEARCH-only replays left every index as it was
+            for ix, (k0, v0) in zip(ixs, before):
+                k1, v1 = export_np(ix)
+                assert np.array_equal(k0, k1) and np.array_equal(v0, v1)
+            with pytest.raises(PiError) as e:
+                g.execute([ixs[0], ixs[0]], [dev_b[0], dev_b[0]])  # one index twice
+            assert e.value.status == PI_ERR_INVALID_ARG
+    finally:
+        for ix in ixs:
+            ix.close()
