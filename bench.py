@@ -237,6 +237,79 @@ def run_serve(args):
                 "rebuilds": st["repairs"], "roofline": None, "cpu_baseline": None}), flush=True)
 
 
+def run_many(args):
+    """Many indices (--workload many): --indices independent indices, sizes
+    log-uniform in [2^10, 2^22] keys, per-index batches log-uniform in
+    [2^8, 2^18] queries, 90/5/5 S/I/D.  One round = one batch on every index.
+    Per-index launches (pi_execute_batch one index after another) beside the
+    group launch (autotuned fused threshold).  One JSON line per mode."""
+    import numpy as np
+    import torch
+
+    from paper_1601_00159_amd import workloads as W
+    from paper_1601_00159_amd.index import Group, Index, to_device_u64, to_device_u8
+
+    dev = torch.device("cuda", 0)
+    rounds = args.steps + args.warmup + 1  # one more round feeds the autotuner
+    t0 = time.perf_counter()
+    w = W.many_indices(n_indices=args.indices, n_rounds=rounds)
+    log(f"workload {w.name}: {w.note}; generated in {time.perf_counter() - t0:.1f}s")
+    total_keys = sum(k.size for k, _ in w.loads)
+    dev_rounds = []
+    for batches in w.rounds:
+        dev_rounds.append([(to_device_u8(b.ops, dev), to_device_u64(b.keys, dev), to_device_u64(b.vals, dev),
+                            torch.empty(len(b), dtype=torch.int64, device=dev),
+                            torch.empty(len(b), dtype=torch.uint8, device=dev)) for b in batches])
+    q_per_round = [sum(len(b) for b in batches) for batches in w.rounds]
+    for mode in ("per-index", "group"):
+        ixs = [Index(device=0) for _ in w.loads]
+        for ix, (k, v) in zip(ixs, w.loads):
+            ix.bulk_load(k, v)
+        torch.cuda.synchronize()
+        g = Group() if mode == "group" else None
+        fused = None
+        if g is not None:
+            fused = g.autotune(ixs, dev_rounds[-1])
+            log(f"autotuner picked fused_max={fused}")
+
+        def one_round(r):
+            if g is not None:
+                g.execute(ixs, dev_rounds[r])
+            else:
+                for ix, b in zip(ixs, dev_rounds[r]):
+                    ix.execute_raw(*b)
+
+        for r in range(args.warmup):
+            one_round(r)
+        torch.cuda.synchronize()
+        lat = []
+        t_all = time.perf_counter()
+        for r in range(args.warmup, args.warmup + args.steps):
+            t1 = time.perf_counter()
+            m0 = time.monotonic_ns()
+            one_round(r)
+            torch.cuda.synchronize()
+            lat.append(time.perf_counter() - t1)
+            log(f"{mode} round {r}: monotonic_ns {m0} {time.monotonic_ns()}")
+        tot = time.perf_counter() - t_all
+        nq = sum(q_per_round[args.warmup:args.warmup + args.steps])
+        if g is not None:
+            g.close()
+        for ix in ixs:
+            ix.close()
+        print(json.dumps({
+            "metric": "Mqueries/s over many indices (one batch per index per round)",
+            "value": round(nq / tot / 1e6, 2), "unit": "Mqueries/s", "n_gpus": 1, "steps": args.steps,
+            "warmup": args.warmup, "ms_per_step": round(tot / args.steps * 1e3, 3), "higher_is_better": True,
+            "scaling": "weak", "vs_baseline": None, "dtype": "u64", "data": "synthetic",
+            "config": {"workload": w.name, "indices": args.indices, "total_keys": int(total_keys),
+                       "queries_per_round": int(np.mean(q_per_round)), "op_mix": "90/5/5 S/I/D", "mode": mode,
+                       "fused_max": fused, "parallelism": "single GPU"},
+            "latency_ms": {"round_p50": round(float(np.percentile(lat, 50)) * 1e3, 3),
+                           "round_p99": round(float(np.percentile(lat, 99)) * 1e3, 3)},
+            "roofline": None, "cpu_baseline": None}), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -253,9 +326,11 @@ def main():
     ap.add_argument("--blocks-per-cu", type=int, default=0)
     ap.add_argument("--lds-budget", type=int, default=0)
     ap.add_argument("--descent-block", type=int, default=0)
-    ap.add_argument("--workload", choices=["search", "range", "write", "serve"], default="search",
+    ap.add_argument("--workload", choices=["search", "range", "write", "serve", "many"], default="search",
                     help="search: the 64M-key SEARCH batches (default); range: range searches; "
-                         "write: write-heavy Zipf batches; serve: continuous batching of Poisson arrivals")
+                         "write: write-heavy Zipf batches; serve: continuous batching of Poisson arrivals; "
+                         "many: one batch on each of many indices per round")
+    ap.add_argument("--indices", type=int, default=512, help="indices (--workload many)")
     ap.add_argument("--rates", default="50e6,200e6,500e6", help="offered queries/s (--workload serve)")
     ap.add_argument("--serve-ms", type=float, default=20.0, help="ms of arrivals per rate (--workload serve)")
     ap.add_argument("--ranges", type=int, default=8192, help="range queries per batch (--workload range)")
@@ -268,7 +343,7 @@ def main():
     if args.workload != "search":
         import torch
         assert torch.cuda.is_available(), "bench needs a GPU"
-        return {"range": run_range, "write": run_write, "serve": run_serve}[args.workload](args)
+        return {"range": run_range, "write": run_write, "serve": run_serve, "many": run_many}[args.workload](args)
 
     import numpy as np
     import torch

@@ -92,6 +92,9 @@ typedef struct {
                                  hot path instead of ~26 launches; 12..22, 0 = never (default) */
     uint32_t small_batch_log2; /* batches of at most 2^small_batch_log2 queries run in one workgroup, one
                                  launch (0 = 10, i.e. 1024; 1..12; 255 = never) */
+    uint32_t reserved;
+    uint64_t rebuild_min;     /* a threshold rebuild also needs at least this many changes (default 4096):
+                                 an index of a few thousand keys is cheaper to walk than to rebuild */
 } pi_config;
 
 /* Accumulated device time per stage of pi_execute_batch (profile = 1). */

@@ -32,7 +32,8 @@ class pi_config(ctypes.Structure):
                 ("lds_levels", ctypes.c_uint32), ("profile", ctypes.c_uint32),
                 ("queries_per_lane", ctypes.c_uint32), ("blocks_per_cu", ctypes.c_uint32),
                 ("lds_budget", ctypes.c_uint32), ("descent_block", ctypes.c_uint32),
-                ("graph_max_log2", ctypes.c_uint32), ("small_batch_log2", ctypes.c_uint32)]
+                ("graph_max_log2", ctypes.c_uint32), ("small_batch_log2", ctypes.c_uint32),
+                ("reserved", ctypes.c_uint32), ("rebuild_min", ctypes.c_uint64)]
 
 
 class pi_profile(ctypes.Structure):

@@ -12,12 +12,15 @@ namespace pi {
 
 void DevBuf::ensure(size_t need) {
     if (need <= bytes && p) return;
+    // a buffer that has to grow again gets half as much again as asked:
+    // batch sizes that vary from call to call settle after a few reallocations
+    const bool regrow = p != nullptr;
     if (p) {
         PI_HIP(hipFree(p));
         p = nullptr;
         bytes = 0;
     }
-    const size_t b = std::max<size_t>(need, 256);
+    const size_t b = std::max<size_t>(regrow ? need + need / 2 : need, 256);
     void *q = nullptr;
     hipError_t e = hipMalloc(&q, b);
     if (e != hipSuccess) {
@@ -132,7 +135,7 @@ void maybe_rebuild(pi::Index &ix, hipStream_t s) {
         ix.ring_seen++;
     }
     if (!have) return;
-    const double thr = std::max(1.0, (double)ix.cfg.rebuild_fraction * (double)std::max<uint64_t>(ix.live_at_rebuild, 1));
+    const double thr = pi::rebuild_threshold(ix);
     if ((double)latest.changes >= thr) {
         pi::rebuild(ix, s);
         ix.ring_seen = ix.ring_head;  // copies taken before the rebuild are stale
@@ -185,6 +188,7 @@ pi_status pi_config_default(pi_config *cfg) {
     cfg->log2_inv_p = 1;
     cfg->height_seed = 0x9E3779B97F4A7C15ull;
     cfg->rebuild_fraction = 0.15f;
+    cfg->rebuild_min = 4096;
     cfg->rebuild_policy = PI_REBUILD_THRESHOLD;
     cfg->capacity_hint = 0;
     cfg->lds_levels = 0;

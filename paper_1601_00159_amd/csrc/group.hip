@@ -78,6 +78,8 @@ struct pi_group {
     uint32_t cap_items = 0;
     std::vector<pi_index *> last;  // indices whose counters h_states holds
     hipEvent_t ev = nullptr;
+    hipEvent_t ev_start = nullptr, ev_fused = nullptr;  // fork/join of the fused launch
+    hipStream_t fstream = nullptr;                      // the fused launch runs beside the large batches
     bool pending = false;
     bool lds_attr = false;
     std::string err;
@@ -116,8 +118,7 @@ void settle_previous(pi_group *g, hipStream_t s) {
         if (st.errors) throw Error{PI_ERR_DEVICE, "internal error: storage walk exceeded its bound"};
         ix.used_upper = st.nused;
         if (ix.cfg.rebuild_policy == PI_REBUILD_NEVER) continue;
-        const double thr = std::max(1.0, (double)ix.cfg.rebuild_fraction *
-                                             (double)std::max<uint64_t>(ix.live_at_rebuild, 1));
+        const double thr = rebuild_threshold(ix);
         if ((ix.cfg.rebuild_policy == PI_REBUILD_ALWAYS && st.changes > 0) || (double)st.changes >= thr) {
             rebuild(ix, s);
             ix.ring_seen = ix.ring_head;
@@ -147,22 +148,23 @@ void run_group(pi_group *g, pi_index *const *indices, const pi_batch *batches, u
     for (uint32_t i = 0; i < count; i++)
         if (batches[i].n) group_capacity(indices[i]->ix, batches[i], s);
     ensure_host(g, count);
-    // large batches: the GPU-wide path
     std::vector<uint32_t> fused;
     for (uint32_t i = 0; i < count; i++) {
         const pi_batch &b = batches[i];
         if (!b.n) continue;
-        Index &ix = indices[i]->ix;
-        const uint8_t *ops = ops_override ? ops_override : b.d_ops;
-        if (b.n > fused_max) {
-            execute_batch(ix, ops, b.d_keys, b.d_values, b.n, b.d_out_values, b.d_out_status, s);
-        } else {
-            fused.push_back(i);
-        }
-        ix.used_upper = std::min<uint64_t>(ix.used_upper + b.n, ~0ull);
+        if (b.n <= fused_max) fused.push_back(i);
+        indices[i]->ix.used_upper = std::min<uint64_t>(indices[i]->ix.used_upper + b.n, ~0ull);
     }
-    // small ones: one persistent launch, largest first
+    // small batches: one persistent launch, largest first, on the group's
+    // own stream so that it overlaps the large batches below
     if (!fused.empty()) {
+        if (!g->fstream) {
+            PI_HIP(hipStreamCreateWithFlags(&g->fstream, hipStreamNonBlocking));
+            PI_HIP(hipEventCreateWithFlags(&g->ev_start, hipEventDisableTiming));
+            PI_HIP(hipEventCreateWithFlags(&g->ev_fused, hipEventDisableTiming));
+        }
+        PI_HIP(hipEventRecord(g->ev_start, s));
+        PI_HIP(hipStreamWaitEvent(g->fstream, g->ev_start, 0));
         std::sort(fused.begin(), fused.end(), [&](uint32_t a, uint32_t b) { return batches[a].n > batches[b].n; });
         const uint32_t nf = (uint32_t)fused.size();
         for (uint32_t k = 0; k < nf; k++) {
@@ -174,8 +176,9 @@ void run_group(pi_group *g, pi_index *const *indices, const pi_batch *batches, u
         }
         g->d_items.ensure((size_t)g->cap_items * sizeof(GroupItem));
         g->d_counter.ensure(64);
-        PI_HIP(hipMemcpyAsync(g->d_items.p, g->h_items, nf * sizeof(GroupItem), hipMemcpyHostToDevice, s));
-        hipLaunchKernelGGL(k_zero_counter, dim3(1), dim3(64), 0, s, g->d_counter.as<unsigned int>());
+        hipStream_t fs = g->fstream;
+        PI_HIP(hipMemcpyAsync(g->d_items.p, g->h_items, nf * sizeof(GroupItem), hipMemcpyHostToDevice, fs));
+        hipLaunchKernelGGL(k_zero_counter, dim3(1), dim3(64), 0, fs, g->d_counter.as<unsigned int>());
         const uint32_t lds = SmallLds::bytes();
         if (!g->lds_attr) {
             PI_HIP(hipFuncSetAttribute((const void *)k_group_batches, hipFuncAttributeMaxDynamicSharedMemorySize,
@@ -183,10 +186,19 @@ void run_group(pi_group *g, pi_index *const *indices, const pi_batch *batches, u
             g->lds_attr = true;
         }
         const uint32_t grid = std::min<uint32_t>(nf, (uint32_t)indices[fused[0]]->ix.num_cus);
-        hipLaunchKernelGGL(k_group_batches, dim3(grid), dim3(SBT), lds, s, g->d_items.as<GroupItem>(), nf,
+        hipLaunchKernelGGL(k_group_batches, dim3(grid), dim3(SBT), lds, fs, g->d_items.as<GroupItem>(), nf,
                            g->d_counter.as<unsigned int>());
         PI_LAUNCH_CHECK();
+        PI_HIP(hipEventRecord(g->ev_fused, fs));
     }
+    // large batches: the GPU-wide path on the caller's stream
+    for (uint32_t i = 0; i < count; i++) {
+        const pi_batch &b = batches[i];
+        if (!b.n || b.n <= fused_max) continue;
+        execute_batch(indices[i]->ix, ops_override ? ops_override : b.d_ops, b.d_keys, b.d_values, b.n,
+                      b.d_out_values, b.d_out_status, s);
+    }
+    if (!fused.empty()) PI_HIP(hipStreamWaitEvent(s, g->ev_fused, 0));
     // one copy of every index's counters
     uint32_t ns = 0;
     g->last.clear();
@@ -303,6 +315,12 @@ pi_status pi_group_destroy(pi_group *g) {
     if (g->h_ptrs) (void)hipHostFree(g->h_ptrs);
     if (g->h_states) (void)hipHostFree(g->h_states);
     if (g->ev) (void)hipEventDestroy(g->ev);
+    if (g->ev_start) (void)hipEventDestroy(g->ev_start);
+    if (g->ev_fused) (void)hipEventDestroy(g->ev_fused);
+    if (g->fstream) {
+        (void)hipStreamSynchronize(g->fstream);
+        (void)hipStreamDestroy(g->fstream);
+    }
     delete g;
     return PI_OK;
 }

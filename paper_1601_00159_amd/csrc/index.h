@@ -1,6 +1,7 @@
 // Host-side state of one index and the operations of the library.
 #pragma once
 
+#include <algorithm>
 #include <functional>
 #include <vector>
 
@@ -102,6 +103,13 @@ struct pi_index {
 };
 
 namespace pi {
+
+// Changes since the last rebuild that trigger the next one: the fraction of
+// the live keys at the last rebuild (Section 4.3.5), at least rebuild_min.
+inline double rebuild_threshold(const Index &ix) {
+    const double frac = (double)ix.cfg.rebuild_fraction * (double)ix.live_at_rebuild;
+    return std::max(std::max(1.0, frac), (double)ix.cfg.rebuild_min);
+}
 
 // build.hip
 void init_empty(Index &ix, hipStream_t s);

@@ -46,7 +46,8 @@ class Index:
                  height_seed: int = 0x9E3779B97F4A7C15, rebuild_fraction: float = 0.15,
                  rebuild_policy: str = "threshold", capacity_hint: int = 0, lds_levels: int = 0,
                  profile: int = 0, queries_per_lane: int = 0, blocks_per_cu: int = 0, lds_budget: int = 0,
-                 descent_block: int = 0, graph_max_log2: int = 0, small_batch_log2: int = 0):
+                 descent_block: int = 0, graph_max_log2: int = 0, small_batch_log2: int = 0,
+                 rebuild_min: int = 4096):
         self._L = _lib.lib()
         cfg = _lib.pi_config()
         check(self._L.pi_config_default(ctypes.byref(cfg)))
@@ -65,6 +66,7 @@ class Index:
         cfg.descent_block = descent_block
         cfg.graph_max_log2 = graph_max_log2
         cfg.small_batch_log2 = small_batch_log2
+        cfg.rebuild_min = rebuild_min
         h = ctypes.c_void_p()
         check(self._L.pi_create(ctypes.byref(cfg), ctypes.byref(h)))
         self._h = h

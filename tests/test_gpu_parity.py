@@ -187,7 +187,7 @@ def test_mixed_batches_vs_oracle(policy):
                            np.array([0, (1 << 64) - 2], dtype=np.uint64)])
     orc = SkipList()
     orc.bulk_load(lk, lv)
-    with Index(rebuild_policy=policy, rebuild_fraction=0.05) as ix:
+    with Index(rebuild_policy=policy, rebuild_fraction=0.05, rebuild_min=1) as ix:
         ix.bulk_load(lk, lv)
         for b in range(6):
             n = [40_000, 1, 4097, 65_536, 12_345, 40_000][b]
@@ -561,7 +561,7 @@ def test_group_matches_each_index_alone(fused_max):
     w = W.many_indices(n_indices=24, size_log2=(8, 15), batch_log2=(5, 14), n_rounds=3, seed_id=10 + fused_max % 7)
     dev = torch.device("cuda", 0)
     refs = [mapref.MapState(k, v) for k, v in w.loads]
-    ixs = [Index(rebuild_policy="threshold", rebuild_fraction=0.05) for _ in w.loads]
+    ixs = [Index(rebuild_policy="threshold", rebuild_fraction=0.05, rebuild_min=1) for _ in w.loads]
     try:
         for ix, (k, v) in zip(ixs, w.loads):
             ix.bulk_load(k, v)
