@@ -278,8 +278,8 @@ static void build_levels(Index &ix, hipStream_t s) {
     const uint32_t maxh = ix.cfg.max_height;
     if (nb > 0) {
         const uint32_t ntiles = blocks_for(nb, BTILE);
-        DevBuf &cnt = ix.tmp[0];
-        DevBuf &tot = ix.tmp[1];
+        DevBuf &cnt = ix.tmp[8];  // not the merge's buffers: the merge may still be running
+        DevBuf &tot = ix.tmp[9];
         cnt.ensure((size_t)MAX_LEVELS * ntiles * sizeof(uint32_t));
         tot.ensure(MAX_LEVELS * sizeof(uint32_t));
         hipLaunchKernelGGL(k_height_count, dim3(ntiles), dim3(BT), 0, s, ix.st.key.as<uint64_t>(), (uint32_t)nb,
@@ -326,7 +326,6 @@ static void build_levels(Index &ix, hipStream_t s) {
         d.lds_from = from;
         d.lds_entries = used;
     }
-    PI_HIP(hipStreamSynchronize(s));
     ix.desc = d;
 }
 
@@ -405,9 +404,13 @@ void bulk_load(Index &ix, const uint64_t *keys, const uint64_t *vals, uint64_t n
 // Writes the live pairs in key order to okey/oval (+ slot_off), and, when
 // ometa is given, clears their flags.  Returns the live count.  Synchronises.
 static uint64_t merge_live(Index &ix, uint64_t *okey, uint64_t *oval, uint8_t *ometa, uint64_t slot_off,
-                           uint64_t cap, hipStream_t s, bool *too_small) {
+                           uint64_t cap, hipStream_t s, bool *too_small, const DevState *known = nullptr,
+                           bool sync_end = true) {
     DevState cur;
-    read_state(ix, s, &cur);
+    if (known)
+        cur = *known;
+    else
+        read_state(ix, s, &cur);
     const uint64_t nb = ix.nbase;
     const uint64_t first = nb + 2;
     const uint64_t novf = cur.nused > first ? cur.nused - first : 0;
@@ -463,7 +466,7 @@ static uint64_t merge_live(Index &ix, uint64_t *okey, uint64_t *oval, uint8_t *o
                            ix.st.val.as<uint64_t>(), olive.as<uint32_t>(), C.as<uint32_t>(), P.as<uint32_t>(),
                            A.as<uint32_t>(), okey, oval, ometa, slot_off);
     PI_LAUNCH_CHECK();
-    PI_HIP(hipStreamSynchronize(s));
+    if (sync_end) PI_HIP(hipStreamSynchronize(s));
     return cur.n_live;
 }
 
@@ -497,7 +500,10 @@ void rebuild(Index &ix, hipStream_t s) {
     }
     bool small = false;
     try {
-        merge_live(ix, ns.key.as<uint64_t>(), ns.val.as<uint64_t>(), ns.meta.as<uint8_t>(), 1, ~0ull, s, &small);
+        // the counters were read above; the merge is ordered before the
+        // level build on the stream, so nothing waits for it here
+        merge_live(ix, ns.key.as<uint64_t>(), ns.val.as<uint64_t>(), ns.meta.as<uint8_t>(), 1, ~0ull, s, &small,
+                   &cur, false);
     } catch (...) {
         ix.spare = ns;
         throw;
