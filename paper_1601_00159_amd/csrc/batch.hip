@@ -50,7 +50,9 @@ __global__ __launch_bounds__(DT) void k_descend(IndexDesc desc, const uint64_t *
                                                 const uint32_t *__restrict__ sidx, uint32_t n, DevState *st,
                                                 uint64_t *__restrict__ out_vals, uint8_t *__restrict__ out_status,
                                                 uint64_t *__restrict__ res_val, uint8_t *__restrict__ res_flags,
-                                                uint32_t *__restrict__ loc, uint32_t *__restrict__ locnext) {
+                                                uint32_t *__restrict__ loc, uint32_t *__restrict__ locnext,
+                                                const uint8_t *__restrict__ ops, const uint64_t *__restrict__ vals,
+                                                uint8_t *__restrict__ sop, uint64_t *__restrict__ svin) {
     extern __shared__ uint64_t s_dyn[];
     uint64_t *s_k = s_dyn;
     uint32_t *s_d = reinterpret_cast<uint32_t *>(s_dyn + desc.lds_entries);
@@ -96,6 +98,7 @@ __global__ __launch_bounds__(DT) void k_descend(IndexDesc desc, const uint64_t *
                 out_vals[id] = 0;
                 out_status[id] = PI_R_INVALID;
                 invalid++;
+                if (mixed) sop[i] = 255;
                 continue;
             }
             const Found f = walk_storage(q[j], pos[j], ik[j], links, dead, skey, sval, snext, smeta, &st->errors);
@@ -108,6 +111,11 @@ __global__ __launch_bounds__(DT) void k_descend(IndexDesc desc, const uint64_t *
                 res_flags[i] = (uint8_t)((f.exists ? 1 : 0) | (f.live ? 2 : 0));
                 loc[i] = f.node;
                 locnext[i] = f.next;
+                // the op and the inserted value in sorted order, for the
+                // ownership kernels (one gather here instead of several there)
+                const uint8_t o = ops[id];
+                sop[i] = o;
+                svin[i] = o == PI_OP_INSERT ? vals[id] : 0;
             }
         }
     }
@@ -172,25 +180,24 @@ __device__ __forceinline__ Seg block_excl_scan_seg(Seg x, Seg *s_w, Seg *total) 
     return seg_op(pre, ex);
 }
 
-__device__ __forceinline__ Seg element(const uint64_t *__restrict__ sk, const uint32_t *__restrict__ sidx,
-                                       const uint8_t *__restrict__ ops, uint32_t i, uint64_t q) {
+__device__ __forceinline__ Seg element(const uint64_t *__restrict__ sk, const uint8_t *__restrict__ sop, uint32_t i,
+                                       uint64_t q) {
     Seg e;
     e.f = (i == 0 || sk[i - 1] != q) ? 1u : 0u;
-    const uint8_t op = ops[sidx[i]];
+    const uint8_t op = sop[i];
     e.v = (q != KEY_MAX && (op == PI_OP_INSERT || op == PI_OP_DELETE)) ? (int32_t)i : -1;
     return e;
 }
 
-__global__ __launch_bounds__(OT) void k_own_reduce(const uint64_t *__restrict__ sk, const uint32_t *__restrict__ sidx,
-                                                   const uint8_t *__restrict__ ops, uint32_t n,
-                                                   const DevState *st, Seg *__restrict__ agg) {
+__global__ __launch_bounds__(OT) void k_own_reduce(const uint64_t *__restrict__ sk, const uint8_t *__restrict__ sop,
+                                                   uint32_t n, const DevState *st, Seg *__restrict__ agg) {
     if (st->b_writers == 0) return;
     __shared__ Seg s_w[ONW];
     const uint32_t base = blockIdx.x * OTILE + threadIdx.x * OI;
     Seg run{0, -1};
     for (int e = 0; e < OI; e++) {
         const uint32_t i = base + e;
-        if (i < n) run = seg_op(run, element(sk, sidx, ops, i, sk[i]));
+        if (i < n) run = seg_op(run, element(sk, sop, i, sk[i]));
     }
     Seg tot;
     block_excl_scan_seg(run, s_w, &tot);
@@ -222,7 +229,7 @@ __global__ __launch_bounds__(OT) void k_own_prefix(Seg *__restrict__ agg, uint32
 }
 
 __global__ __launch_bounds__(OT) void k_own_apply(const uint64_t *__restrict__ sk, const uint32_t *__restrict__ sidx,
-                                                  const uint8_t *__restrict__ ops, const uint64_t *__restrict__ vals,
+                                                  const uint8_t *__restrict__ sop, const uint64_t *__restrict__ svin,
                                                   uint32_t n, const Seg *__restrict__ carry_in,
                                                   const uint64_t *__restrict__ res_val,
                                                   const uint8_t *__restrict__ res_flags,
@@ -240,7 +247,7 @@ __global__ __launch_bounds__(OT) void k_own_apply(const uint64_t *__restrict__ s
         const uint32_t i = base + e;
         if (i < n) {
             qk[e] = sk[i];
-            el[e] = element(sk, sidx, ops, i, qk[e]);
+            el[e] = element(sk, sop, i, qk[e]);
         } else {
             qk[e] = KEY_MAX;
             el[e] = Seg{0, -1};
@@ -268,9 +275,8 @@ __global__ __launch_bounds__(OT) void k_own_apply(const uint64_t *__restrict__ s
         uint64_t v;
         bool present;
         if (excl >= 0) {
-            const uint32_t jd = sidx[excl];
-            present = ops[jd] == PI_OP_INSERT;
-            v = present ? vals[jd] : 0;
+            present = sop[excl] == PI_OP_INSERT;
+            v = present ? svin[excl] : 0;
         } else {
             present = (fl & 2) != 0;
             v = res_val[i];
@@ -282,12 +288,11 @@ __global__ __launch_bounds__(OT) void k_own_apply(const uint64_t *__restrict__ s
         const bool last = (i + 1 == n) || sk[i + 1] != q;
         uint32_t nf = 0;
         if (last && incl >= 0) {
-            const uint32_t jd = sidx[incl];
             const uint32_t node = loc[i];
             const bool exists = fl & 1, live = (fl & 2) != 0;
-            if (ops[jd] == PI_OP_INSERT) {
+            if (sop[incl] == PI_OP_INSERT) {
                 if (exists) {
-                    sval[node] = vals[jd];
+                    sval[node] = svin[incl];
                     if (!live) {
                         smeta[node] = smeta[node] & (uint8_t)~META_DEL;
                         revs++;
@@ -314,8 +319,8 @@ __global__ __launch_bounds__(OT) void k_own_apply(const uint64_t *__restrict__ s
 }
 
 // compacts the new nodes (key order) with their predecessor
-__global__ void k_new_gather(const uint64_t *__restrict__ sk, const uint32_t *__restrict__ sidx,
-                             const uint64_t *__restrict__ vals, const uint32_t *__restrict__ newflag,
+__global__ void k_new_gather(const uint64_t *__restrict__ sk, const uint64_t *__restrict__ svin,
+                             const uint32_t *__restrict__ newflag,
                              const uint32_t *__restrict__ newpos, const int32_t *__restrict__ gw,
                              const uint32_t *__restrict__ loc, const uint32_t *__restrict__ locnext, uint32_t n,
                              const DevState *st, uint64_t *__restrict__ nk, uint64_t *__restrict__ nv,
@@ -325,7 +330,7 @@ __global__ void k_new_gather(const uint64_t *__restrict__ sk, const uint32_t *__
     if (i >= n || !newflag[i]) return;
     const uint32_t r = newpos[i];
     nk[r] = sk[i];
-    nv[r] = vals[sidx[gw[i]]];
+    nv[r] = svin[gw[i]];
     npred[r] = loc[i];
     npnext[r] = locnext[i];
 }
@@ -391,7 +396,7 @@ uint32_t blocks_for(uint64_t n, int t) { return (uint32_t)((n + t - 1) / t); }
 template <int MODE, int QPL, int DT>
 void launch_descend_q(Index &ix, hipStream_t s, const uint64_t *sk, const uint32_t *sidx, uint64_t n,
                       uint64_t *out_vals, uint8_t *out_status, uint64_t *res_val, uint8_t *res_flags, uint32_t *loc,
-                      uint32_t *locnext) {
+                      uint32_t *locnext, const uint8_t *ops, const uint64_t *vals, uint8_t *sop, uint64_t *svin) {
     const IndexDesc &d = ix.desc;
     const size_t lds = (size_t)d.lds_entries * 12;
     auto kern = k_descend<MODE, QPL, DT>;
@@ -399,23 +404,26 @@ void launch_descend_q(Index &ix, hipStream_t s, const uint64_t *sk, const uint32
     hipLaunchKernelGGL(kern, dim3(g), dim3(DT), lds, s, d, ix.arena_key.as<uint64_t>(), ix.arena_down.as<uint32_t>(),
                        ix.st.key.as<uint64_t>(), ix.st.val.as<uint64_t>(), ix.st.next.as<uint32_t>(),
                        ix.st.meta.as<uint8_t>(), sk, sidx, (uint32_t)n, ix.dstate, out_vals, out_status, res_val,
-                       res_flags, loc, locnext);
+                       res_flags, loc, locnext, ops, vals, sop, svin);
     PI_LAUNCH_CHECK();
 }
 
 template <int MODE, int DT>
 void launch_descend_b(Index &ix, hipStream_t s, const uint64_t *sk, const uint32_t *sidx, uint64_t n,
                       uint64_t *out_vals, uint8_t *out_status, uint64_t *res_val, uint8_t *res_flags, uint32_t *loc,
-                      uint32_t *locnext) {
+                      uint32_t *locnext, const uint8_t *ops, const uint64_t *vals, uint8_t *sop, uint64_t *svin) {
     switch (ix.cfg.queries_per_lane) {
         case 2:
-            launch_descend_q<MODE, 2, DT>(ix, s, sk, sidx, n, out_vals, out_status, res_val, res_flags, loc, locnext);
+            launch_descend_q<MODE, 2, DT>(ix, s, sk, sidx, n, out_vals, out_status, res_val, res_flags, loc, locnext,
+                ops, vals, sop, svin);
             break;
         case 4:
-            launch_descend_q<MODE, 4, DT>(ix, s, sk, sidx, n, out_vals, out_status, res_val, res_flags, loc, locnext);
+            launch_descend_q<MODE, 4, DT>(ix, s, sk, sidx, n, out_vals, out_status, res_val, res_flags, loc, locnext,
+                ops, vals, sop, svin);
             break;
         default:
-            launch_descend_q<MODE, 1, DT>(ix, s, sk, sidx, n, out_vals, out_status, res_val, res_flags, loc, locnext);
+            launch_descend_q<MODE, 1, DT>(ix, s, sk, sidx, n, out_vals, out_status, res_val, res_flags, loc, locnext,
+                ops, vals, sop, svin);
             break;
     }
 }
@@ -423,16 +431,19 @@ void launch_descend_b(Index &ix, hipStream_t s, const uint64_t *sk, const uint32
 template <int MODE>
 void launch_descend(Index &ix, hipStream_t s, const uint64_t *sk, const uint32_t *sidx, uint64_t n,
                     uint64_t *out_vals, uint8_t *out_status, uint64_t *res_val, uint8_t *res_flags, uint32_t *loc,
-                    uint32_t *locnext) {
+                    uint32_t *locnext, const uint8_t *ops, const uint64_t *vals, uint8_t *sop, uint64_t *svin) {
     switch (ix.cfg.descent_block) {
         case 256:
-            launch_descend_b<MODE, 256>(ix, s, sk, sidx, n, out_vals, out_status, res_val, res_flags, loc, locnext);
+            launch_descend_b<MODE, 256>(ix, s, sk, sidx, n, out_vals, out_status, res_val, res_flags, loc, locnext,
+                ops, vals, sop, svin);
             break;
         case 512:
-            launch_descend_b<MODE, 512>(ix, s, sk, sidx, n, out_vals, out_status, res_val, res_flags, loc, locnext);
+            launch_descend_b<MODE, 512>(ix, s, sk, sidx, n, out_vals, out_status, res_val, res_flags, loc, locnext,
+                ops, vals, sop, svin);
             break;
         default:
-            launch_descend_b<MODE, 1024>(ix, s, sk, sidx, n, out_vals, out_status, res_val, res_flags, loc, locnext);
+            launch_descend_b<MODE, 1024>(ix, s, sk, sidx, n, out_vals, out_status, res_val, res_flags, loc, locnext,
+                ops, vals, sop, svin);
             break;
     }
 }
@@ -451,6 +462,8 @@ void BatchWorkspace::ensure(uint64_t m) {
     gw.ensure(c * 4);
     const uint64_t nt = (c + OTILE - 1) / OTILE + 1;
     agg.ensure(nt * sizeof(Seg));
+    sop.ensure(c);
+    svin.ensure(c * 8);
     nk.ensure(c * 8);
     nv.ensure(c * 8);
     npred.ensure(c * 4);
@@ -459,7 +472,8 @@ void BatchWorkspace::ensure(uint64_t m) {
 }
 
 void BatchWorkspace::release() {
-    DevBuf *all[] = {&res_val, &res_flags, &loc, &locnext, &newflag, &newpos, &gw, &agg, &carry, &nk, &nv, &npred, &npnext};
+    DevBuf *all[] = {&res_val, &res_flags, &loc, &locnext, &newflag, &newpos, &gw, &agg,
+                     &carry, &nk, &nv, &npred, &npnext, &sop, &svin};
     for (DevBuf *b : all) b->release();
     n = 0;
 }
@@ -497,15 +511,17 @@ void execute_batch(Index &ix, const uint8_t *ops, const uint64_t *keys, const ui
 
     BatchWorkspace &w = ix.bws;
     launch_descend<0>(ix, s, sk, sidx, n, out_vals, out_status, w.res_val.as<uint64_t>(), w.res_flags.as<uint8_t>(),
-                      w.loc.as<uint32_t>(), w.locnext.as<uint32_t>());
+                      w.loc.as<uint32_t>(), w.locnext.as<uint32_t>(), ops, vals, w.sop.as<uint8_t>(),
+                      w.svin.as<uint64_t>());
     PI_LAUNCH_CHECK();
     mark(2);
 
     const uint32_t otiles = blocks_for(n, OTILE);
     Seg *agg = w.agg.as<Seg>();
-    hipLaunchKernelGGL(k_own_reduce, dim3(otiles), dim3(OT), 0, s, sk, sidx, ops, (uint32_t)n, st, agg);
+    hipLaunchKernelGGL(k_own_reduce, dim3(otiles), dim3(OT), 0, s, sk, w.sop.as<uint8_t>(), (uint32_t)n, st, agg);
     hipLaunchKernelGGL(k_own_prefix, dim3(1), dim3(OT), 0, s, agg, otiles, st);
-    hipLaunchKernelGGL(k_own_apply, dim3(otiles), dim3(OT), 0, s, sk, sidx, ops, vals, (uint32_t)n, agg,
+    hipLaunchKernelGGL(k_own_apply, dim3(otiles), dim3(OT), 0, s, sk, sidx, w.sop.as<uint8_t>(),
+                       w.svin.as<uint64_t>(), (uint32_t)n, agg,
                        w.res_val.as<uint64_t>(), w.res_flags.as<uint8_t>(), w.loc.as<uint32_t>(),
                        ix.st.val.as<uint64_t>(), ix.st.meta.as<uint8_t>(), out_vals, out_status,
                        w.newflag.as<uint32_t>(), w.gw.as<int32_t>(), st);
@@ -513,7 +529,7 @@ void execute_batch(Index &ix, const uint8_t *ops, const uint64_t *keys, const ui
     mark(3);
     exclusive_scan_u32(ix.scanws, w.newflag.as<uint32_t>(), w.newpos.as<uint32_t>(), n, &st->b_new,
                        &st->b_writers, s);
-    hipLaunchKernelGGL(k_new_gather, dim3(blocks_for(n, 256)), dim3(256), 0, s, sk, sidx, vals,
+    hipLaunchKernelGGL(k_new_gather, dim3(blocks_for(n, 256)), dim3(256), 0, s, sk, w.svin.as<uint64_t>(),
                        w.newflag.as<uint32_t>(), w.newpos.as<uint32_t>(), w.gw.as<int32_t>(), w.loc.as<uint32_t>(),
                        w.locnext.as<uint32_t>(), (uint32_t)n, st, w.nk.as<uint64_t>(), w.nv.as<uint64_t>(),
                        w.npred.as<uint32_t>(), w.npnext.as<uint32_t>());
@@ -622,7 +638,7 @@ std::vector<uint64_t> fingerprint(const Index &ix) {
     add(ix.scanws.tiles);
     const BatchWorkspace &w = ix.bws;
     add(w.res_val), add(w.res_flags), add(w.loc), add(w.locnext), add(w.newflag), add(w.newpos), add(w.gw);
-    add(w.agg), add(w.carry), add(w.nk), add(w.nv), add(w.npred), add(w.npnext);
+    add(w.agg), add(w.carry), add(w.nk), add(w.nv), add(w.npred), add(w.npnext), add(w.sop), add(w.svin);
     for (const DevBuf &b : ix.stage) add(b);
     f.push_back((uint64_t)(uintptr_t)ix.dstate);
     const uint64_t *d = reinterpret_cast<const uint64_t *>(&ix.desc);
@@ -697,7 +713,8 @@ void execute_batch_graph(Index &ix, const uint8_t *ops, const uint64_t *keys, co
 
 void debug_interceptions(Index &ix, const uint64_t *keys, uint64_t n, uint64_t *icpt_keys, uint8_t *is_head,
                          hipStream_t s) {
-    launch_descend<1>(ix, s, keys, nullptr, n, icpt_keys, is_head, nullptr, nullptr, nullptr, nullptr);
+    launch_descend<1>(ix, s, keys, nullptr, n, icpt_keys, is_head, nullptr, nullptr, nullptr, nullptr, nullptr,
+                      nullptr, nullptr, nullptr);
 }
 
 }  // namespace pi

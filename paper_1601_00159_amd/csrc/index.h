@@ -26,6 +26,7 @@ struct Storage {
 struct BatchWorkspace {
     DevBuf res_val, res_flags, loc, locnext, newflag, newpos, gw, agg, carry;
     DevBuf nk, nv, npred, npnext;
+    DevBuf sop, svin;  // op and inserted value of each sorted query (batches with updates)
     uint64_t n = 0;
     void ensure(uint64_t n);
     void release();
