@@ -152,7 +152,7 @@ def run_write(args):
     d = [(to_device_u8(b.ops, dev), to_device_u64(b.keys, dev), to_device_u64(b.vals, dev)) for b in w.batches]
     out_v = torch.empty(Q, dtype=torch.int64, device=dev)
     out_s = torch.empty(Q, dtype=torch.uint8, device=dev)
-    ix = Index(device=0, profile=1)
+    ix = Index(device=0, profile=1, rebuild_policy=args.rebuild_policy)
     ix.bulk_load(w.load_keys, w.load_vals)
     for i in range(WU):
         ix.execute_raw(*d[i], out_v, out_s)
@@ -185,7 +185,9 @@ def run_write(args):
         "latency_ms": {"p50": round(float(np.percentile(lat, 50)), 4), "p99": round(float(np.percentile(lat, 99)), 4),
                        "max": round(float(lat.max()), 4)},
         "stages_ms_per_batch": {k: round(prof[k] / nb, 4) for k in ("sort_ms", "descend_ms", "own_ms", "link_ms")},
+        "rebuild_policy": args.rebuild_policy,
         "rebuilds_in_timed_region": st["repairs"] - r0,
+        "index_rebuilds": st["index_rebuilds"],
         "rebuild_ms_total": round(prof["rebuild_ms"], 3),
         "live_nodes_after": st["live_nodes"], "correct_last_batch": None, "roofline": None,
         "cpu_baseline": None}), flush=True)
@@ -331,6 +333,8 @@ def main():
                          "write: write-heavy Zipf batches; serve: continuous batching of Poisson arrivals; "
                          "many: one batch on each of many indices per round")
     ap.add_argument("--indices", type=int, default=512, help="indices (--workload many)")
+    ap.add_argument("--rebuild-policy", default="threshold", choices=["threshold", "background", "never"],
+                    help="rebuild policy (--workload write)")
     ap.add_argument("--rates", default="50e6,200e6,500e6", help="offered queries/s (--workload serve)")
     ap.add_argument("--serve-ms", type=float, default=20.0, help="ms of arrivals per rate (--workload serve)")
     ap.add_argument("--ranges", type=int, default=8192, help="range queries per batch (--workload range)")

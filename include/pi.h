@@ -69,7 +69,12 @@ enum { PI_R_ABSENT = 0, PI_R_PRESENT = 1, PI_R_INVALID = 255 };
 enum {
     PI_REBUILD_THRESHOLD = 0, /* rebuild when changes >= fraction * live nodes */
     PI_REBUILD_NEVER = 1,     /* only pi_repair() rebuilds */
-    PI_REBUILD_ALWAYS = 2     /* rebuild after every batch that changed the structure */
+    PI_REBUILD_ALWAYS = 2,    /* rebuild after every batch that changed the structure */
+    PI_REBUILD_BACKGROUND = 3 /* when changes >= fraction * live nodes, rebuild the index layer over the
+                                 storage as it stands (new nodes included) on a second stream while
+                                 batches go on, and switch to it at a batch boundary (Section 4.3.5);
+                                 merge the storage itself (a full rebuild) only when the new and
+                                 deleted nodes reach compact_percent of the base region */
 };
 
 typedef struct {
@@ -92,7 +97,8 @@ typedef struct {
                                  hot path instead of ~26 launches; 12..22, 0 = never (default) */
     uint32_t small_batch_log2; /* batches of at most 2^small_batch_log2 queries run in one workgroup, one
                                  launch (0 = 10, i.e. 1024; 1..12; 255 = never) */
-    uint32_t reserved;
+    uint32_t compact_percent; /* PI_REBUILD_BACKGROUND: full rebuild when new + deleted nodes reach this
+                                 percentage of the base region (0 = 100) */
     uint64_t rebuild_min;     /* a threshold rebuild also needs at least this many changes (default 4096):
                                  an index of a few thousand keys is cheaper to walk than to rebuild */
 } pi_config;
@@ -125,6 +131,7 @@ typedef struct {
     uint32_t n_levels;        /* highest non-empty level (1 = no index levels) */
     uint32_t lds_from;        /* lowest level kept in LDS by the descent */
     uint64_t level_size[33];  /* keys on level l, l = 2..32 */
+    uint64_t index_rebuilds;  /* background index-layer rebuilds switched in */
 } pi_stats;
 
 /* Fills *cfg with the defaults listed above. */

@@ -17,7 +17,7 @@ PI_ERR_CAPACITY = -5
 
 PI_OP_SEARCH, PI_OP_INSERT, PI_OP_DELETE = 0, 1, 2
 PI_R_ABSENT, PI_R_PRESENT, PI_R_INVALID = 0, 1, 255
-PI_REBUILD_THRESHOLD, PI_REBUILD_NEVER, PI_REBUILD_ALWAYS = 0, 1, 2
+PI_REBUILD_THRESHOLD, PI_REBUILD_NEVER, PI_REBUILD_ALWAYS, PI_REBUILD_BACKGROUND = 0, 1, 2, 3
 
 STATUS_NAMES = {PI_OK: "PI_OK", PI_ERR_INVALID_ARG: "PI_ERR_INVALID_ARG",
                 PI_ERR_OUT_OF_MEMORY: "PI_ERR_OUT_OF_MEMORY", PI_ERR_STATE: "PI_ERR_STATE",
@@ -33,7 +33,7 @@ class pi_config(ctypes.Structure):
                 ("queries_per_lane", ctypes.c_uint32), ("blocks_per_cu", ctypes.c_uint32),
                 ("lds_budget", ctypes.c_uint32), ("descent_block", ctypes.c_uint32),
                 ("graph_max_log2", ctypes.c_uint32), ("small_batch_log2", ctypes.c_uint32),
-                ("reserved", ctypes.c_uint32), ("rebuild_min", ctypes.c_uint64)]
+                ("compact_percent", ctypes.c_uint32), ("rebuild_min", ctypes.c_uint64)]
 
 
 class pi_profile(ctypes.Structure):
@@ -48,7 +48,7 @@ class pi_stats(ctypes.Structure):
         "batches", "queries", "hits", "invalid", "new_nodes", "deletes", "revives", "changes",
         "repairs", "live_nodes", "base_nodes", "overflow_nodes", "capacity")] + [
         ("n_levels", ctypes.c_uint32), ("lds_from", ctypes.c_uint32),
-        ("level_size", ctypes.c_uint64 * 33)]
+        ("level_size", ctypes.c_uint64 * 33), ("index_rebuilds", ctypes.c_uint64)]
 
 
 EXPORTED = ["pi_config_default", "pi_create", "pi_destroy", "pi_bulk_load", "pi_execute_batch",

@@ -96,6 +96,7 @@ void release_all(pi::Index &ix) {
     for (auto &b : ix.tmp) b.release();
     for (auto &b : ix.rng) b.release();
     pi::release_graphs(ix);
+    pi::bg_release(ix);
     if (ix.dstate) (void)hipFree(ix.dstate);
     if (ix.hstate) (void)hipHostFree(ix.hstate);
     if (ix.hcounts) (void)hipHostFree(ix.hcounts);
@@ -116,10 +117,12 @@ void release_all(pi::Index &ix) {
 // lags the device by at most that many batches and the GPU queue never runs
 // dry because of it.
 void maybe_rebuild(pi::Index &ix, hipStream_t s) {
-    if (ix.cfg.rebuild_policy != PI_REBUILD_THRESHOLD) {
+    const uint32_t pol = ix.cfg.rebuild_policy;
+    if (pol != PI_REBUILD_THRESHOLD && pol != PI_REBUILD_BACKGROUND) {
         ix.ring_seen = ix.ring_head;
         return;
     }
+    if (pol == PI_REBUILD_BACKGROUND) pi::bg_advance(ix);
     bool have = false;
     pi::DevState latest{};
     while (ix.ring_seen < ix.ring_head) {
@@ -136,10 +139,24 @@ void maybe_rebuild(pi::Index &ix, hipStream_t s) {
     }
     if (!have) return;
     const double thr = pi::rebuild_threshold(ix);
-    if ((double)latest.changes >= thr) {
-        pi::rebuild(ix, s);
-        ix.ring_seen = ix.ring_head;  // copies taken before the rebuild are stale
+    if (pol == PI_REBUILD_THRESHOLD) {
+        if ((double)latest.changes >= thr) {
+            pi::rebuild(ix, s);
+            ix.ring_seen = ix.ring_head;  // copies taken before the rebuild are stale
+        }
+        return;
     }
+    // background: merge the storage when new and deleted nodes have piled up,
+    // else rebuild the index layer beside the batches
+    const double compact = (ix.cfg.compact_percent ? ix.cfg.compact_percent : 100) / 100.0 *
+                           (double)std::max<uint64_t>(ix.nbase, 1);
+    if ((double)latest.changes >= std::max(compact, thr)) {
+        pi::rebuild(ix, s);
+        ix.ring_seen = ix.ring_head;
+        return;
+    }
+    if (latest.changes >= ix.changes_base && (double)(latest.changes - ix.changes_base) >= thr)
+        pi::bg_start(ix, latest, s);
 }
 
 // Queues the copy of the counters after a batch.
@@ -222,7 +239,7 @@ pi_status pi_create(const pi_config *cfg_in, pi_index **out) {
         cfg = *cfg_in;
     }
     if (cfg.max_height < 2 || cfg.max_height > 32 || cfg.log2_inv_p < 1 || cfg.log2_inv_p > 8 ||
-        !(cfg.rebuild_fraction >= 0.0f) || cfg.rebuild_policy > PI_REBUILD_ALWAYS ||
+        !(cfg.rebuild_fraction >= 0.0f) || cfg.rebuild_policy > PI_REBUILD_BACKGROUND ||
         cfg.capacity_hint > (1ull << 32) - 64 ||
         (cfg.queries_per_lane != 0 && cfg.queries_per_lane != 1 && cfg.queries_per_lane != 2 &&
          cfg.queries_per_lane != 4) ||
@@ -434,6 +451,7 @@ pi_status pi_get_stats(pi_index *h, pi_stats *out) {
         out->n_levels = (uint32_t)ix.desc.top;
         out->lds_from = (uint32_t)ix.desc.lds_from;
         for (int l = 2; l <= ix.desc.top && l < 33; l++) out->level_size[l] = ix.desc.n[l];
+        out->index_rebuilds = ix.bg.done;
         return PI_OK;
     });
 }

@@ -28,7 +28,9 @@ constexpr int BNW = BT / 64;
 
 // ---- level construction ----------------------------------------------------
 
-__global__ __launch_bounds__(BT) void k_height_count(const uint64_t *__restrict__ skey, uint32_t nbase,
+// keys[0 .. n) in increasing order; counts per tile and level of the keys
+// whose tower reaches the level
+__global__ __launch_bounds__(BT) void k_height_count(const uint64_t *__restrict__ keys, uint32_t nbase,
                                                      uint64_t seed, uint32_t l2p, uint32_t maxh,
                                                      uint32_t *__restrict__ cnt, uint32_t ntiles) {
     __shared__ uint32_t h[MAX_LEVELS + 1];
@@ -38,7 +40,7 @@ __global__ __launch_bounds__(BT) void k_height_count(const uint64_t *__restrict_
     const uint32_t base = blockIdx.x * BTILE;
     for (int j = 0; j < BI; j++) {
         const uint32_t b = base + j * BT + tid;
-        if (b < nbase) atomicAdd(&h[tower_height(skey[1 + b], seed, l2p, maxh)], 1u);
+        if (b < nbase) atomicAdd(&h[tower_height(keys[b], seed, l2p, maxh)], 1u);
     }
     __syncthreads();
     if (tid < MAX_LEVELS) {
@@ -48,7 +50,11 @@ __global__ __launch_bounds__(BT) void k_height_count(const uint64_t *__restrict_
     }
 }
 
-__global__ __launch_bounds__(BT) void k_level_scatter(const uint64_t *__restrict__ skey, uint32_t nbase,
+// writes keys[0 .. n) into every level their tower reaches; the level-2 down
+// pointer is slots[b] (the storage slot), or 1 + b when slots is null (the
+// base region)
+__global__ __launch_bounds__(BT) void k_level_scatter(const uint64_t *__restrict__ keys,
+                                                      const uint32_t *__restrict__ slots, uint32_t nbase,
                                                       uint64_t seed, uint32_t l2p, uint32_t maxh,
                                                       const uint32_t *__restrict__ tileoff, uint32_t ntiles,
                                                       IndexDesc desc, uint64_t *__restrict__ lkey,
@@ -69,7 +75,7 @@ __global__ __launch_bounds__(BT) void k_level_scatter(const uint64_t *__restrict
     for (int r = 0; r < BI; r++) {
         const uint32_t b = wbase + r * 64 + lane;
         if (b < nbase) {
-            k[r] = skey[1 + b];
+            k[r] = keys[b];
             h[r] = tower_height(k[r], seed, l2p, maxh);
         } else {
             k[r] = KEY_MAX;
@@ -97,7 +103,8 @@ __global__ __launch_bounds__(BT) void k_level_scatter(const uint64_t *__restrict
     __syncthreads();
 #pragma unroll
     for (int r = 0; r < BI; r++) {
-        uint32_t prev = 1 + wbase + r * 64 + lane;  // storage slot: down pointer of level 2
+        const uint32_t b = wbase + r * 64 + lane;
+        uint32_t prev = slots ? (b < nbase ? slots[b] : 0u) : 1 + b;  // storage slot: down pointer of level 2
         for (uint32_t l = 2;; l++) {
             const bool in = h[r] >= l;
             const uint64_t m = ballot64(in);
@@ -105,8 +112,10 @@ __global__ __launch_bounds__(BT) void k_level_scatter(const uint64_t *__restrict
             const uint32_t before = s_cnt[w][l];
             if (in) {
                 const uint32_t p = 1 + s_toff[l] + before + mask_rank(m);
-                lkey[desc.off[l] + p] = k[r];
-                ldown[desc.off[l] + p] = prev;
+                if (p <= desc.n[l]) {  // sizes come from a separate count; never write past the level
+                    lkey[desc.off[l] + p] = k[r];
+                    ldown[desc.off[l] + p] = prev;
+                }
                 prev = p;
             }
             if (lane == 0) s_cnt[w][l] = before + (uint32_t)__popcll(m);
@@ -269,64 +278,99 @@ void read_state(Index &ix, hipStream_t s, DevState *out) {
     if (out->errors) throw Error{PI_ERR_DEVICE, "internal error: storage walk exceeded its bound"};
 }
 
-// Builds every index level from base slots 1..nbase.  Synchronises s.
-static void build_levels(Index &ix, hipStream_t s) {
+// Level sizes -> descriptor: 128-byte aligned levels in one arena, and the
+// top levels that fit the descent's LDS budget (Section 5.1 notes the top
+// levels are cache resident anyway; Section 7 proposes pinning them).
+IndexDesc make_desc(const Index &ix, const uint32_t *level_n, uint64_t *arena_entries) {
     IndexDesc d{};
     d.top = 1;
     d.lds_from = MAX_LEVELS;
-    const uint64_t nb = ix.nbase;
     const uint32_t maxh = ix.cfg.max_height;
+    for (int l = 2; l < MAX_LEVELS && l <= (int)maxh; l++) {
+        d.n[l] = level_n[l];
+        if (level_n[l] > 0) d.top = l;
+    }
+    uint64_t total = 0;
+    for (int l = 2; l <= d.top; l++) {
+        d.off[l] = total;
+        total += ((uint64_t)d.n[l] + 1 + LEVEL_PAD + 15) & ~15ull;
+    }
+    *arena_entries = total;
+    const uint32_t budget = ix.cfg.lds_budget ? ix.cfg.lds_budget : 12000;  // 12000 entries: 141 KB per block
+    uint32_t used = 0;
+    int from = d.top + 1;
+    const uint32_t want = ix.cfg.lds_levels ? ix.cfg.lds_levels : 64u;
+    for (int l = d.top; l >= 2 && (uint32_t)(d.top - l) < want; l--) {
+        const uint32_t e = d.n[l] + 1 + LEVEL_PAD;
+        if (used + e > budget) break;
+        d.lds_off[l] = used;
+        used += e;
+        from = l;
+    }
+    d.lds_from = d.top >= 2 ? from : MAX_LEVELS;
+    d.lds_entries = used;
+    return d;
+}
+
+// Writes the levels of d from keys[0 .. n) (increasing; level-2 down
+// pointers from slots, or 1 + position when slots is null) into the arena.
+// Asynchronous on s; cnt is per-tile scratch.
+void scatter_levels(const Index &ix, const uint64_t *keys, const uint32_t *slots, uint64_t n, const IndexDesc &d,
+                    DevBuf &cnt, DevBuf &tot, DevBuf &akey, DevBuf &adown, hipStream_t s) {
+    if (n == 0 || d.top < 2) return;
+    const uint32_t ntiles = blocks_for(n, BTILE);
+    cnt.ensure((size_t)MAX_LEVELS * ntiles * sizeof(uint32_t));
+    tot.ensure(MAX_LEVELS * sizeof(uint32_t));
+    hipLaunchKernelGGL(k_height_count, dim3(ntiles), dim3(BT), 0, s, keys, (uint32_t)n, ix.cfg.height_seed,
+                       ix.cfg.log2_inv_p, ix.cfg.max_height, cnt.as<uint32_t>(), ntiles);
+    PI_LAUNCH_CHECK();
+    column_scan(cnt.as<uint32_t>(), MAX_LEVELS, ntiles, tot.as<uint32_t>(), s);
+    hipLaunchKernelGGL(k_level_scatter, dim3(ntiles), dim3(BT), 0, s, keys, slots, (uint32_t)n, ix.cfg.height_seed,
+                       ix.cfg.log2_inv_p, ix.cfg.max_height, cnt.as<uint32_t>(), ntiles, d, akey.as<uint64_t>(),
+                       adown.as<uint32_t>());
+    hipLaunchKernelGGL(k_level_pad, dim3(MAX_LEVELS), dim3(64), 0, s, d, akey.as<uint64_t>(), adown.as<uint32_t>());
+    PI_LAUNCH_CHECK();
+}
+
+// Builds every index level from base slots 1..nbase.  Waits for the level
+// sizes.
+static void build_levels(Index &ix, hipStream_t s) {
+    const uint64_t nb = ix.nbase;
+    uint32_t level_n[MAX_LEVELS] = {};
     if (nb > 0) {
         const uint32_t ntiles = blocks_for(nb, BTILE);
         DevBuf &cnt = ix.tmp[8];  // not the merge's buffers: the merge may still be running
         DevBuf &tot = ix.tmp[9];
         cnt.ensure((size_t)MAX_LEVELS * ntiles * sizeof(uint32_t));
         tot.ensure(MAX_LEVELS * sizeof(uint32_t));
-        hipLaunchKernelGGL(k_height_count, dim3(ntiles), dim3(BT), 0, s, ix.st.key.as<uint64_t>(), (uint32_t)nb,
-                           ix.cfg.height_seed, ix.cfg.log2_inv_p, maxh, cnt.as<uint32_t>(), ntiles);
+        hipLaunchKernelGGL(k_height_count, dim3(ntiles), dim3(BT), 0, s, ix.st.key.as<uint64_t>() + 1, (uint32_t)nb,
+                           ix.cfg.height_seed, ix.cfg.log2_inv_p, ix.cfg.max_height, cnt.as<uint32_t>(), ntiles);
         PI_LAUNCH_CHECK();
         column_scan(cnt.as<uint32_t>(), MAX_LEVELS, ntiles, tot.as<uint32_t>(), s);
         uint32_t *htot = reinterpret_cast<uint32_t *>(ix.hcounts);
         PI_HIP(hipMemcpyAsync(htot, tot.p, MAX_LEVELS * sizeof(uint32_t), hipMemcpyDeviceToHost, s));
         PI_HIP(hipStreamSynchronize(s));
-        uint64_t total = 0;
-        for (int l = 2; l < MAX_LEVELS && l <= (int)maxh; l++) {
-            d.n[l] = htot[l];
-            if (htot[l] > 0) d.top = l;
-        }
-        for (int l = 2; l <= d.top; l++) {
-            d.off[l] = total;
-            total += ((uint64_t)d.n[l] + 1 + LEVEL_PAD + 15) & ~15ull;  // 128-byte aligned levels
-        }
-        if (d.top >= 2) {
-            // a quarter of headroom: levels grow with the inserts between
-            // rebuilds, and reallocating costs more than the spare bytes
-            if (ix.arena_key.bytes < total * sizeof(uint64_t)) ix.arena_key.ensure(total * sizeof(uint64_t) * 5 / 4);
-            if (ix.arena_down.bytes < total * sizeof(uint32_t)) ix.arena_down.ensure(total * sizeof(uint32_t) * 5 / 4);
-            hipLaunchKernelGGL(k_level_scatter, dim3(ntiles), dim3(BT), 0, s, ix.st.key.as<uint64_t>(),
-                               (uint32_t)nb, ix.cfg.height_seed, ix.cfg.log2_inv_p, maxh, cnt.as<uint32_t>(),
-                               ntiles, d, ix.arena_key.as<uint64_t>(), ix.arena_down.as<uint32_t>());
-            hipLaunchKernelGGL(k_level_pad, dim3(MAX_LEVELS), dim3(64), 0, s, d, ix.arena_key.as<uint64_t>(),
-                               ix.arena_down.as<uint32_t>());
-            PI_LAUNCH_CHECK();
-        }
-        // upper levels kept in LDS by the descent (Section 5.1 notes the top
-        // levels are cache resident anyway; Section 7 proposes pinning them)
-        const uint32_t budget = ix.cfg.lds_budget ? ix.cfg.lds_budget : 12000;  // 12000 entries: 141 KB per block
-        uint32_t used = 0;
-        int from = d.top + 1;
-        const uint32_t want = ix.cfg.lds_levels ? ix.cfg.lds_levels : 64u;
-        for (int l = d.top; l >= 2 && (uint32_t)(d.top - l) < want; l--) {
-            const uint32_t e = d.n[l] + 1 + LEVEL_PAD;
-            if (used + e > budget) break;
-            d.lds_off[l] = used;
-            used += e;
-            from = l;
-        }
-        d.lds_from = from;
-        d.lds_entries = used;
+        for (int l = 0; l < MAX_LEVELS; l++) level_n[l] = htot[l];
+    }
+    uint64_t total = 0;
+    IndexDesc d = make_desc(ix, level_n, &total);
+    if (nb > 0 && d.top >= 2) {
+        // a quarter of headroom: levels grow with the inserts between
+        // rebuilds, and reallocating costs more than the spare bytes
+        if (ix.arena_key.bytes < total * sizeof(uint64_t)) ix.arena_key.ensure(total * sizeof(uint64_t) * 5 / 4);
+        if (ix.arena_down.bytes < total * sizeof(uint32_t)) ix.arena_down.ensure(total * sizeof(uint32_t) * 5 / 4);
+        const uint32_t ntiles = blocks_for(nb, BTILE);
+        hipLaunchKernelGGL(k_level_scatter, dim3(ntiles), dim3(BT), 0, s, ix.st.key.as<uint64_t>() + 1, nullptr,
+                           (uint32_t)nb, ix.cfg.height_seed, ix.cfg.log2_inv_p, ix.cfg.max_height,
+                           ix.tmp[8].as<uint32_t>(), ntiles, d, ix.arena_key.as<uint64_t>(),
+                           ix.arena_down.as<uint32_t>());
+        hipLaunchKernelGGL(k_level_pad, dim3(MAX_LEVELS), dim3(64), 0, s, d, ix.arena_key.as<uint64_t>(),
+                           ix.arena_down.as<uint32_t>());
+        PI_LAUNCH_CHECK();
     }
     ix.desc = d;
+    // the base levels: what a background index rebuild adds the new nodes to
+    for (int l = 0; l < MAX_LEVELS; l++) ix.base_level_n[l] = level_n[l];
 }
 
 void init_empty(Index &ix, hipStream_t s) {
@@ -341,6 +385,7 @@ void init_empty(Index &ix, hipStream_t s) {
 
 void grow_storage(Index &ix, uint64_t need, hipStream_t s) {
     if (need <= ix.st.cap) return;
+    bg_quiesce(ix);
     DevState cur;
     read_state(ix, s, &cur);
     uint64_t ncap = std::max<uint64_t>(need, ix.st.cap + ix.st.cap / 2);
@@ -357,6 +402,8 @@ void grow_storage(Index &ix, uint64_t need, hipStream_t s) {
 }
 
 void bulk_load(Index &ix, const uint64_t *keys, const uint64_t *vals, uint64_t n, hipStream_t s) {
+    bg_quiesce(ix);
+    ix.changes_base = 0;
     const uint64_t *sk = nullptr;
     const uint32_t *sidx = nullptr;
     uint64_t nb = 0;
@@ -478,6 +525,7 @@ uint64_t export_live(Index &ix, uint64_t *okeys, uint64_t *ovals, uint64_t cap, 
 }
 
 void rebuild(Index &ix, hipStream_t s) {
+    bg_quiesce(ix);  // a background index rebuild reads the storage about to be replaced
     Profiler::Rec rec{};
     if (ix.prof.on) {
         rec.n = 2;
@@ -516,6 +564,7 @@ void rebuild(Index &ix, hipStream_t s) {
     PI_LAUNCH_CHECK();
     ix.used_upper = live + 2;
     ix.live_at_rebuild = live;
+    ix.changes_base = 0;
     ix.repairs++;
     build_levels(ix, s);
     if (ix.prof.on) {

@@ -117,9 +117,22 @@ void settle_previous(pi_group *g, hipStream_t s) {
         const DevState &st = g->h_states[k];
         if (st.errors) throw Error{PI_ERR_DEVICE, "internal error: storage walk exceeded its bound"};
         ix.used_upper = st.nused;
-        if (ix.cfg.rebuild_policy == PI_REBUILD_NEVER) continue;
+        const uint32_t pol = ix.cfg.rebuild_policy;
+        if (pol == PI_REBUILD_NEVER) continue;
         const double thr = rebuild_threshold(ix);
-        if ((ix.cfg.rebuild_policy == PI_REBUILD_ALWAYS && st.changes > 0) || (double)st.changes >= thr) {
+        if (pol == PI_REBUILD_BACKGROUND) {
+            bg_advance(ix);
+            const double compact = (ix.cfg.compact_percent ? ix.cfg.compact_percent : 100) / 100.0 *
+                                   (double)std::max<uint64_t>(ix.nbase, 1);
+            if ((double)st.changes >= std::max(compact, thr)) {
+                rebuild(ix, s);
+                ix.ring_seen = ix.ring_head;
+            } else if (st.changes >= ix.changes_base && (double)(st.changes - ix.changes_base) >= thr) {
+                bg_start(ix, st, s);
+            }
+            continue;
+        }
+        if ((pol == PI_REBUILD_ALWAYS && st.changes > 0) || (double)st.changes >= thr) {
             rebuild(ix, s);
             ix.ring_seen = ix.ring_head;
         }

@@ -89,6 +89,26 @@ struct Index {
         std::vector<uint64_t> fp;
     };
     Graph graphs[23];
+    // background index rebuild (rebuild policy BACKGROUND)
+    struct Background {
+        int phase = 0;                 // 0 idle, 1 counting the new nodes, 2 building the levels
+        hipStream_t side = nullptr;    // default priority, like every stream here
+        hipEvent_t ev_main = nullptr, ev_side = nullptr;
+        uint64_t first = 0, snap = 0;  // new nodes taken: storage slots [first, snap)
+        uint64_t changes_at = 0, live_at = 0;
+        SortWorkspace sortws;
+        MsdWorkspace msdws;
+        ScanWorkspace scanws;
+        DevBuf okeys, flags, pos, cnt, b2key, b2slot, o2key, o2slot, m2key, m2slot, tcnt, ttot;
+        DevBuf akey, adown;            // the levels being built; after the switch, the spare
+        const uint64_t *sk = nullptr;  // the new keys in key order (in the side stream's sort workspace)
+        const uint32_t *si = nullptr;  // ... and their positions in [first, snap)
+        uint32_t *h_cnt = nullptr;     // pinned: new-node counts per level
+        IndexDesc desc{};
+        uint64_t done = 0;
+    } bg;
+    uint32_t base_level_n[MAX_LEVELS] = {};  // level sizes of the base region alone
+    uint64_t changes_base = 0;     // DevState::changes when the index layer was last rebuilt
     DevBuf stage[5];               // graph inputs/outputs: ops, keys, values, answer values, answer status
     hipStream_t cap_stream = nullptr;
     uint64_t *hcounts = nullptr;   // pinned: level totals etc.
@@ -149,6 +169,17 @@ uint64_t serve_batch_limit(Index &ix, uint32_t inflight);
 // Returns the number of micro-batches (their end indices in batch_end).
 uint64_t serve_loop(const double *arrival_us, uint64_t n, const ServePlan &plan, hipStream_t s,
                     const std::function<void(uint64_t, uint64_t)> &launch, double *done_us, uint64_t *batch_end);
+
+// build.hip: level descriptor from sizes; level arrays from sorted keys
+IndexDesc make_desc(const Index &ix, const uint32_t *level_n, uint64_t *arena_entries);
+void scatter_levels(const Index &ix, const uint64_t *keys, const uint32_t *slots, uint64_t n, const IndexDesc &d,
+                    DevBuf &cnt, DevBuf &tot, DevBuf &akey, DevBuf &adown, hipStream_t s);
+
+// bgrebuild.hip: background index rebuild (rebuild policy BACKGROUND)
+void bg_start(Index &ix, const DevState &latest, hipStream_t s);  // enqueues the counting step
+void bg_advance(Index &ix);                                       // moves on when the side stream is done
+void bg_quiesce(Index &ix);                                       // waits and drops a rebuild in flight
+void bg_release(Index &ix);
 
 // range.hip
 void range_count(Index &ix, const uint64_t *lo, const uint64_t *hi, uint64_t n, uint64_t *offsets, hipStream_t s);

@@ -9,7 +9,7 @@ from . import _lib
 from ._lib import check
 
 _POLICY = {"threshold": _lib.PI_REBUILD_THRESHOLD, "never": _lib.PI_REBUILD_NEVER,
-           "always": _lib.PI_REBUILD_ALWAYS}
+           "always": _lib.PI_REBUILD_ALWAYS, "background": _lib.PI_REBUILD_BACKGROUND}
 
 
 def _ptr(t):
@@ -47,7 +47,7 @@ class Index:
                  rebuild_policy: str = "threshold", capacity_hint: int = 0, lds_levels: int = 0,
                  profile: int = 0, queries_per_lane: int = 0, blocks_per_cu: int = 0, lds_budget: int = 0,
                  descent_block: int = 0, graph_max_log2: int = 0, small_batch_log2: int = 0,
-                 rebuild_min: int = 4096):
+                 rebuild_min: int = 4096, compact_percent: int = 0):
         self._L = _lib.lib()
         cfg = _lib.pi_config()
         check(self._L.pi_config_default(ctypes.byref(cfg)))
@@ -67,6 +67,7 @@ class Index:
         cfg.graph_max_log2 = graph_max_log2
         cfg.small_batch_log2 = small_batch_log2
         cfg.rebuild_min = rebuild_min
+        cfg.compact_percent = compact_percent
         h = ctypes.c_void_p()
         check(self._L.pi_create(ctypes.byref(cfg), ctypes.byref(h)))
         self._h = h

@@ -615,3 +615,45 @@ def test_group_autotune_and_errors():
     finally:
         for ix in ixs:
             ix.close()
+
+
+# ---------------------------------------------------- background rebuild
+
+@pytest.mark.parametrize("compact", [0, 30])
+def test_background_index_rebuild(compact):
+    """Rebuild policy BACKGROUND: the index layer is rebuilt over the base
+    region and the new nodes on a second stream while batches go on, and
+    switched in at a batch boundary; with a small compact_percent the
+    storage is merged by full rebuilds too.  Every batch's answers and the
+    final set against the oracle; the levels stay well formed."""
+    rng = np.random.default_rng(40 + compact)
+    lk = rng.integers(0, 1 << 63, size=100_000, dtype=np.uint64)
+    lv = rng.integers(0, 1 << 64, size=100_000, dtype=np.uint64, endpoint=False)
+    pool = np.concatenate([lk[:40_000], rng.integers(0, 1 << 63, size=60_000, dtype=np.uint64)])
+    orc = SkipList()
+    orc.bulk_load(lk, lv)
+    with Index(rebuild_policy="background", rebuild_fraction=0.02, rebuild_min=1, compact_percent=compact) as ix:
+        ix.bulk_load(lk, lv)
+        for b in range(14):
+            n = [30_000, 700, 30_000, 5000][b % 4]
+            ops, keys, vals = _random_batch(rng, pool, n)
+            wv, ws = orc.execute_batch(ops, keys, vals)
+            gv, gs = run_gpu(ix, ops, keys, vals)
+            assert_same(gv, gs, wv, ws, f"batch {b} (n={n})")
+        ek, ev = export_np(ix)
+        ok, ov = orc.export()
+        assert np.array_equal(ek, ok) and np.array_equal(ev, ov)
+        st = ix.stats()
+        say(f"index rebuilds {st['index_rebuilds']}, full rebuilds {st['repairs']}, overflow {st['overflow_nodes']}")
+        if compact:
+            assert st["repairs"] >= 1  # the storage was merged (a full rebuild drops any build in flight)
+        else:
+            assert st["index_rebuilds"] >= 1 and st["repairs"] == 0
+        prev = None
+        for lvl in range(2, st["n_levels"] + 1):
+            k, d = ix.level(lvl)
+            k, d = to_numpy_u64(k), d.cpu().numpy().astype(np.int64)
+            assert np.all(k[1:] > k[:-1]), lvl
+            if prev is not None and k.size:
+                assert np.array_equal(prev[d - 1], k), lvl  # each key sits on the level below
+            prev = k
