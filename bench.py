@@ -196,9 +196,9 @@ def run_write(args):
 def run_serve(args):
     """Serving loop (--workload serve): 2^25 loaded keys, open-loop Poisson
     arrivals at each rate of --rates for --serve-ms of arrivals, 90/5/5
-    S/I/D with Zipf 0.8 keys.  Continuous batching (100 us deadline, 4
-    micro-batches in flight) beside launch-and-wait batching (1 in flight,
-    no deadline).  One JSON line per rate and mode."""
+    S/I/D with Zipf 0.8 keys.  Continuous batching (100 us deadline) with 1,
+    2 and 4 micro-batches in flight, each after a warm-up of SEARCH
+    batches.  One JSON line per rate and mode."""
     import numpy as np
     import torch
 
@@ -210,9 +210,15 @@ def run_serve(args):
         t0 = time.perf_counter()
         w = W.serving(args.load_log2 if args.load_log2 != 26 else 25, rate, n)
         log(f"workload {w.name}: {w.note}; generated in {time.perf_counter() - t0:.1f}s")
-        for mode, deadline, inflight in (("continuous", 100.0, 4), ("launch-and-wait", 0.0, 1)):
+        for mode, deadline, inflight in (("continuous", 100.0, 1), ("continuous", 100.0, 2),
+                                         ("continuous", 100.0, 4)):
             with Index(device=0) as ix:
                 ix.bulk_load(w.load_keys, w.load_vals)
+                # warm-up outside the measurement: SEARCH batches of every
+                # size class load the kernels and size the workspaces
+                for m in (1 << 10, 1 << 16, 1 << 22):
+                    m = min(m, n)
+                    ix.execute(np.zeros(m, dtype=np.uint8), w.keys[:m], w.vals[:m])
                 torch.cuda.synchronize()
                 gv, gs, done, ends = ix.serve(w.arrival_us, w.ops, w.keys, w.vals, deadline_us=deadline,
                                               max_inflight=inflight)

@@ -211,7 +211,7 @@ pi_status pi_range_collect(pi_index *idx, const uint64_t *d_lo, const uint64_t *
  * max_batch queries; a closed micro-batch is enqueued as one pi_execute_batch
  * on the stream when fewer than max_inflight micro-batches are still running
  * on the device, and keeps admitting arrivals (up to max_batch) while it
- * waits for a slot.  Micro-batches are contiguous runs of the arrival order
+ * waits for a slot; with no micro-batch on the device it is enqueued at once.  Micro-batches are contiguous runs of the arrival order
  * applied in that order, so every answer equals that of applying all n
  * queries one by one in arrival order (the serial semantics of
  * pi_execute_batch); the batching changes only when answers are ready.
@@ -225,7 +225,9 @@ pi_status pi_range_collect(pi_index *idx, const uint64_t *d_lo, const uint64_t *
  * decreasing arrival times. */
 typedef struct {
     uint32_t struct_size;   /* sizeof(pi_serve_config) */
-    uint32_t max_inflight;  /* micro-batches on the device at once (0 = 4) */
+    uint32_t max_inflight;  /* micro-batches on the device at once (0 = 1: the host's ~26 launches per
+                               micro-batch, not the device, bound the rate, and queued batches only
+                               add latency) */
     double deadline_us;     /* micro-batch deadline after its first arrival (default 100) */
     uint64_t max_batch;     /* queries per micro-batch (0 = as many as free device memory allows, <= 2^22) */
 } pi_serve_config;

@@ -190,7 +190,7 @@ pi_status pi_serve_config_default(pi_serve_config *cfg) {
     if (!cfg) return PI_ERR_INVALID_ARG;
     std::memset(cfg, 0, sizeof(*cfg));
     cfg->struct_size = sizeof(pi_serve_config);
-    cfg->max_inflight = 4;
+    cfg->max_inflight = 1;
     cfg->deadline_us = 100.0;
     cfg->max_batch = 0;
     return PI_OK;
@@ -373,7 +373,7 @@ pi_status pi_serve(pi_index *h, const pi_serve_config *cfg, const double *h_arri
         hipStream_t s = (hipStream_t)stream;
         pi::ServePlan plan;
         plan.deadline_us = cfg->deadline_us;
-        plan.max_inflight = cfg->max_inflight ? cfg->max_inflight : 4;
+        plan.max_inflight = cfg->max_inflight ? cfg->max_inflight : 1;
         plan.max_batch = cfg->max_batch ? cfg->max_batch : pi::serve_batch_limit(ix, plan.max_inflight);
         *n_batches = pi::serve_loop(
             h_arrival_us, n, plan, s,

@@ -5,7 +5,7 @@
 // consecutive arrivals; it closes when its first query has waited the
 // deadline or when it is full, and it is enqueued as one batch of the hot
 // path as soon as fewer than max_inflight micro-batches are still on the
-// device.  While it waits for a slot it keeps admitting arrivals, so the
+// device; an idle device takes what has arrived at once.  While it waits for a slot it keeps admitting arrivals, so the
 // batch size follows the load: small batches (low latency) when the device
 // keeps up, large ones (high throughput) when it does not.  The host never
 // blocks on the device while queries are arriving; it polls the completion
@@ -100,7 +100,9 @@ uint64_t serve_loop(const double *arrival, uint64_t n, const ServePlan &plan, hi
         const double *lim = arrival + std::min<uint64_t>(n, next + plan.max_batch);
         const uint64_t e = (uint64_t)(std::upper_bound(arrival + next, lim, t) - arrival);
         const bool full = e - next >= plan.max_batch;
-        const bool due = t >= arrival[next] + plan.deadline_us;
+        // the deadline bounds the wait; with nothing on the device there is
+        // nothing to wait for
+        const bool due = fl.empty() || t >= arrival[next] + plan.deadline_us;
         if (!full && !due) continue;                  // still collecting
         if (fl.size() >= plan.max_inflight) continue;  // no slot: keep admitting
         launch(next, e);

@@ -133,7 +133,7 @@ class Index:
         self._check(self._L.pi_export(self._h, _ptr(k), _ptr(v), n, ctypes.byref(got), _stream(stream)))
         return k[:got.value], v[:got.value]
 
-    def serve(self, arrival_us, ops, keys, values, deadline_us=100.0, max_batch=0, max_inflight=4, stream=None):
+    def serve(self, arrival_us, ops, keys, values, deadline_us=100.0, max_batch=0, max_inflight=1, stream=None):
         """Continuous batching of an arrival schedule (pi_serve).  Returns
         (values, status, done_us, batch_ends): device answers, host
         completion time per query and the end index of every micro-batch."""

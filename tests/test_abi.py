@@ -68,4 +68,4 @@ def test_config_default_without_gpu():
     scfg = _lib.pi_serve_config()
     assert L.pi_serve_config_default(ctypes.byref(scfg)) == _lib.PI_OK
     assert scfg.struct_size == ctypes.sizeof(_lib.pi_serve_config)
-    assert scfg.deadline_us == 100.0 and scfg.max_inflight == 4 and scfg.max_batch == 0
+    assert scfg.deadline_us == 100.0 and scfg.max_inflight == 1 and scfg.max_batch == 0
