@@ -92,6 +92,7 @@ def run_range(args):
 
     dev = torch.device("cuda", 0)
     K, WU = args.steps, args.warmup
+    orc = None
     for g in [int(x) for x in args.granularity.split(",")]:
         w = W.range_scan(args.load_log2, args.ranges, g, n_batches=K + WU)
         ix = Index(device=0)
@@ -100,17 +101,22 @@ def run_range(args):
         hi = [to_device_u64(b, dev) for _, b in w.batches]
         results = 0
         lat = []
+        coll_ms = 0.0
         torch.cuda.synchronize()
         for i in range(K + WU):
             t0 = time.perf_counter()
             off = ix.range_count(lo[i], hi[i])
             total = int(off[-1].item())
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
             k, v = ix.range_collect(lo[i], hi[i], off, total)
+            e1.record()
             torch.cuda.synchronize()
             dt = time.perf_counter() - t0
             if i >= WU:
                 lat.append(dt)
                 results += total
+                coll_ms += e0.elapsed_time(e1)
         # the last batch against sorted arrays (cheap check)
         order = np.argsort(w.load_keys, kind="stable")
         sk, sv = w.load_keys[order], w.load_vals[order]
@@ -120,6 +126,19 @@ def run_range(args):
         ok = bool(np.array_equal(to_numpy_u64(k), sk[idx]) and np.array_equal(to_numpy_u64(v), sv[idx]))
         ix.close()
         tot = sum(lat)
+        # the collect call (ordering, locate, compaction) against HBM: each
+        # result is read (key, value: 16 B) and written (16 B); each range
+        # reads its bounds and offsets (32 B)
+        algo = results * 32 + K * args.ranges * 32
+        achieved = algo / (coll_ms / 1e3) / 1e9
+        roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None, "kernel": "range collect call",
+                "kernel_ms": round(coll_ms / K, 4), "algorithmic_bytes_per_launch": int(algo / K)}
+        cpu = None
+        if not args.no_cpu_baseline:
+            if orc is None:
+                orc = range_oracle(w)
+            cpu = range_cpu_baseline(w, orc)
         print(json.dumps({
             "metric": "Mranges/s (range search, count + collect)", "value": round(K * args.ranges / tot / 1e6, 3),
             "unit": "Mranges/s", "n_gpus": 1, "steps": K, "warmup": WU, "ms_per_step": round(tot / K * 1e3, 4),
@@ -129,7 +148,58 @@ def run_range(args):
             "results_per_s_M": round(results / tot / 1e6, 2), "mean_results_per_range": round(results / K / args.ranges, 1),
             "latency_ms": {"p50": round(float(np.percentile(lat, 50)) * 1e3, 4),
                            "p99": round(float(np.percentile(lat, 99)) * 1e3, 4)},
-            "correct_last_batch": ok, "roofline": None, "cpu_baseline": None}), flush=True)
+            "correct_last_batch": ok, "roofline": roof, "cpu_baseline": cpu}), flush=True)
+
+
+def range_oracle(w):
+    """The CPU oracle holding the range workload's index (built once)."""
+    import numpy as np
+
+    from oracle.skiplist import SkipList
+
+    order = np.argsort(w.load_keys, kind="stable")
+    orc = SkipList()
+    orc.bulk_load_sorted(w.load_keys[order], w.load_vals[order])
+    return orc
+
+
+def range_cpu_baseline(w, orc, budget_s=8.0):
+    """The CPU oracle's range search on the same index and the first batch's
+    ranges, in chunks until budget_s seconds of work."""
+    lo, hi = w.batches[0]
+    done, elapsed, chunk = 0, 0.0, 256
+    while done < lo.size and elapsed < budget_s:
+        t = time.perf_counter()
+        orc.range_batch(lo[done:done + chunk], hi[done:done + chunk])
+        elapsed += time.perf_counter() - t
+        done += min(chunk, lo.size - done)
+    return {"value": round(done / elapsed / 1e6, 4), "unit": "Mranges/s", "cores": 1, "kind": "oracle",
+            "sample": f"{done} ranges of one batch against the full {w.load_keys.size}-key index "
+                      f"(single-threaded Pugh skip list, {elapsed:.1f}s timed)"}
+
+
+def write_cpu_baseline(w, budget_s=10.0):
+    """The CPU oracle on the write-heavy workload: the full index, the first
+    batch's queries in arrival order, in chunks until budget_s seconds."""
+    import numpy as np
+
+    from oracle.skiplist import SkipList
+
+    order = np.argsort(w.load_keys, kind="stable")
+    orc = SkipList()
+    orc.bulk_load_sorted(w.load_keys[order], w.load_vals[order])
+    b = w.batches[0]
+    done, elapsed, chunk = 0, 0.0, 1 << 16
+    while done < len(b) and elapsed < budget_s:
+        s_ = slice(done, done + chunk)
+        t = time.perf_counter()
+        orc.execute_batch(b.ops[s_], b.keys[s_], b.vals[s_])
+        elapsed += time.perf_counter() - t
+        done += b.ops[s_].size
+    orc.close()
+    return {"value": round(done / elapsed / 1e6, 4), "unit": "Mqueries/s", "cores": 1, "kind": "oracle",
+            "sample": f"{done} queries (40/50/10 S/I/D, Zipf 0.99) of one batch against the full "
+                      f"{w.load_keys.size}-key index (single-threaded Pugh skip list, {elapsed:.1f}s timed)"}
 
 
 def run_write(args):
@@ -190,7 +260,7 @@ def run_write(args):
         "index_rebuilds": st["index_rebuilds"],
         "rebuild_ms_total": round(prof["rebuild_ms"], 3),
         "live_nodes_after": st["live_nodes"], "correct_last_batch": None, "roofline": None,
-        "cpu_baseline": None}), flush=True)
+        "cpu_baseline": None if args.no_cpu_baseline else write_cpu_baseline(w)}), flush=True)
 
 
 def run_serve(args):
