@@ -149,6 +149,8 @@ def run_range(args):
             "latency_ms": {"p50": round(float(np.percentile(lat, 50)) * 1e3, 4),
                            "p99": round(float(np.percentile(lat, 99)) * 1e3, 4)},
             "correct_last_batch": ok, "roofline": roof, "cpu_baseline": cpu}), flush=True)
+    if orc is not None:
+        orc.close()
 
 
 def range_oracle(w):

@@ -374,7 +374,7 @@ pi_status pi_serve(pi_index *h, const pi_serve_config *cfg, const double *h_arri
         pi::ServePlan plan;
         plan.deadline_us = cfg->deadline_us;
         plan.max_inflight = cfg->max_inflight ? cfg->max_inflight : 1;
-        plan.max_batch = cfg->max_batch ? cfg->max_batch : pi::serve_batch_limit(ix, plan.max_inflight);
+        plan.max_batch = cfg->max_batch ? cfg->max_batch : pi::serve_batch_limit(plan.max_inflight);
         *n_batches = pi::serve_loop(
             h_arrival_us, n, plan, s,
             [&](uint64_t b, uint64_t e) {

@@ -164,7 +164,7 @@ struct ServePlan {
     uint32_t max_inflight = 4;
 };
 // Largest micro-batch that free device memory allows (at most 2^22).
-uint64_t serve_batch_limit(Index &ix, uint32_t inflight);
+uint64_t serve_batch_limit(uint32_t inflight);
 // Replays the arrival schedule; launch(b, e) enqueues queries [b, e) on s.
 // Returns the number of micro-batches (their end indices in batch_end).
 uint64_t serve_loop(const double *arrival_us, uint64_t n, const ServePlan &plan, hipStream_t s,

@@ -49,8 +49,7 @@ struct Flight {
 
 }  // namespace
 
-uint64_t serve_batch_limit(Index &ix, uint32_t inflight) {
-    (void)ix;
+uint64_t serve_batch_limit(uint32_t inflight) {
     size_t freeb = 0, total = 0;
     PI_HIP(hipMemGetInfo(&freeb, &total));
     // per query: batch workspaces (ordering 24 B, descent and ownership

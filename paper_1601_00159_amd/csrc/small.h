@@ -209,11 +209,10 @@ __device__ __forceinline__ void block_batch(const IndexView &v, const BatchView 
                                         &v.st->errors);
     }
 
-    // ---- ownership: writers and the segmented last-writer scan
+    // ---- ownership: the segmented last-writer scan
     uint8_t op[SBI];
     SSeg el[SBI];
     SSeg run{0, -1};
-    uint32_t writers = 0;
 #pragma unroll
     for (int e = 0; e < SBI; e++) {
         const uint32_t i = i0 + e;
@@ -222,7 +221,6 @@ __device__ __forceinline__ void block_batch(const IndexView &v, const BatchView 
         el[e].f = (mine && (i == 0 || s_key[i - 1] != q[e])) ? 1u : 0u;
         const bool w = op[e] == PI_OP_INSERT || op[e] == PI_OP_DELETE;
         el[e].v = w ? (int32_t)i : -1;
-        writers += w;
         run = sseg_op(run, el[e]);
     }
     SSeg pre = block_scan_sseg(run, s_seg);
@@ -322,7 +320,6 @@ __device__ __forceinline__ void block_batch(const IndexView &v, const BatchView 
         if (dels) atomicAdd(&s_cnt[2], dels);
         if (revs) atomicAdd(&s_cnt[3], revs);
     }
-    (void)writers;
     __syncthreads();
     if (tid == 0) {
         DevState *st = v.st;
