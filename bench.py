@@ -393,8 +393,10 @@ def run_many(args):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=32)
-    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--steps", type=int, default=None, help="timed steps (default 32; 4 rounds for --workload many)")
+    ap.add_argument("--warmup", type=int, default=None,
+                    help="untimed steps (default 3; 10 rounds for --workload many, whose per-index batch sizes "
+                         "change every round and reach steady-state buffer sizes after several rounds)")
     ap.add_argument("--theta", type=float, default=None)
     ap.add_argument("--load-log2", type=int, default=26)
     ap.add_argument("--batch-log2", type=int, default=22)
@@ -418,6 +420,10 @@ def main():
     ap.add_argument("--ranges", type=int, default=8192, help="range queries per batch (--workload range)")
     ap.add_argument("--granularity", default="1,10,100,1000", help="mean keys per range (--workload range)")
     args = ap.parse_args()
+    if args.steps is None:
+        args.steps = 4 if args.workload == "many" else 32
+    if args.warmup is None:
+        args.warmup = 10 if args.workload == "many" else 3
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the index shards by key range "
               "across GPUs, which this build does not run.", file=sys.stderr)

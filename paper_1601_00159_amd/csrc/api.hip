@@ -12,15 +12,22 @@ namespace pi {
 
 void DevBuf::ensure(size_t need) {
     if (need <= bytes && p) return;
-    // a buffer that has to grow again gets half as much again as asked:
-    // batch sizes that vary from call to call settle after a few reallocations
+    // Buffers up to 16 MiB (batch workspaces, the storage of small indices)
+    // take the next power of two, so sizes that vary from call to call
+    // reallocate at most once per doubling; a larger buffer is allocated as
+    // asked the first time and gets half as much again when it has to grow.
     const bool regrow = p != nullptr;
     if (p) {
         PI_HIP(hipFree(p));
         p = nullptr;
         bytes = 0;
     }
-    const size_t b = std::max<size_t>(regrow ? need + need / 2 : need, 256);
+    constexpr size_t POW2_MAX = size_t(16) << 20;
+    size_t b = 256;
+    if (need <= POW2_MAX)
+        while (b < need) b <<= 1;
+    else
+        b = regrow ? need + need / 2 : need;
     void *q = nullptr;
     hipError_t e = hipMalloc(&q, b);
     if (e != hipSuccess) {
@@ -138,6 +145,11 @@ void maybe_rebuild(pi::Index &ix, hipStream_t s) {
         ix.ring_seen++;
     }
     if (!have) return;
+    // a tighter bound on the storage in use: the newest counters plus the
+    // queries of the batches queued after them
+    uint64_t queued = 0;
+    for (uint64_t k = ix.ring_seen; k < ix.ring_head; k++) queued += ix.ring_n[k % pi::Index::STATE_RING];
+    ix.used_upper = std::min<uint64_t>(ix.used_upper, latest.nused + queued);
     const double thr = pi::rebuild_threshold(ix);
     if (pol == PI_REBUILD_THRESHOLD) {
         if ((double)latest.changes >= thr) {
@@ -160,8 +172,9 @@ void maybe_rebuild(pi::Index &ix, hipStream_t s) {
 }
 
 // Queues the copy of the counters after a batch.
-void push_state(pi::Index &ix, hipStream_t s) {
+void push_state(pi::Index &ix, uint64_t n, hipStream_t s) {
     const int slot = (int)(ix.ring_head % pi::Index::STATE_RING);
+    ix.ring_n[slot] = n;
     PI_HIP(hipMemcpyAsync(ix.hring + slot, ix.dstate, sizeof(pi::DevState), hipMemcpyDeviceToHost, s));
     PI_HIP(hipEventRecord(ix.ev_ring[slot], s));
     ix.ring_head++;
@@ -179,7 +192,9 @@ void ensure_capacity(pi::Index &ix, const uint8_t *ops, const uint64_t *keys, ui
                                                  std::to_string(ix.st.cap - cur.nused) + " slots free"};
         return;
     }
-    pi::grow_storage(ix, std::max<uint64_t>(cur.nused + n, ix.st.cap * 2), s);
+    // room for two batches of this size: batch sizes that vary do not force a
+    // counter read (a wait for the stream) on every call
+    pi::grow_storage(ix, std::max<uint64_t>(cur.nused + 2 * n, ix.st.cap * 2), s);
 }
 
 }  // namespace
@@ -333,7 +348,7 @@ void batch_step(pi::Index &ix, const uint8_t *d_ops, const uint64_t *d_keys, con
     else
         pi::execute_batch(ix, d_ops, d_keys, d_values, n, d_out_values, d_out_status, s);
     ix.used_upper = std::min<uint64_t>(ix.used_upper + n, ~0ull);
-    push_state(ix, s);
+    push_state(ix, n, s);
     if (ix.cfg.rebuild_policy == PI_REBUILD_ALWAYS) {
         pi::DevState cur;
         pi::read_state(ix, s, &cur);

@@ -142,6 +142,95 @@ __device__ __forceinline__ uint32_t wide_finish(const uint64_t *__restrict__ K, 
 constexpr int WIN_KP = 4;
 constexpr int WIN_DQ = 3;
 
+// Shared window of a whole wave.  On the upper global levels the 64 sorted
+// queries of a wave stand on the same few entries, yet the per-lane window
+// above costs seven vector loads that each pass all 64 lane addresses through
+// the texture addresser -- the unit that bounds the descent.  When every lane
+// stands within UW_SLACK entries of the first lane's entry w0, one load by 12
+// lanes fetches the wave's window instead: lanes 0..7 the 8 key pairs from the
+// even entry kb at or below w0+1, lanes 8..11 the 4 down quads from the
+// multiple of 4 at or below w0.  The keys go to every lane (readlane), and
+// each lane counts those <= its query: every key between w0 and the lane's own
+// entry is <= its query (it is at most the key the lane stands on), so the
+// count is the lane's new entry minus w0.  Its key and down pointer come from
+// the holding lane (bpermute).
+constexpr uint32_t UW_SLACK = 8;
+
+// Reads keys kb .. kb+15 and downs db .. db+15: inside the level and its
+// +infinity pad (w0 <= n, LEVEL_PAD >= 16).
+__device__ __forceinline__ uint4 uni_load(const uint64_t *__restrict__ K, const uint32_t *__restrict__ D,
+                                          uint32_t w0) {
+    const uint32_t lane = (uint32_t)lane_id();
+    const uint32_t kb = (w0 + 1) & ~1u, db = w0 & ~3u;
+    // one load instruction: a per-lane address into either array
+    const uint4 *src = lane < 8 ? reinterpret_cast<const uint4 *>(K + kb) + lane
+                                : reinterpret_cast<const uint4 *>(D + db) + (lane - 8);
+    uint4 v = make_uint4(0, 0, 0, 0);
+    if (lane < 12) v = *src;
+    return v;
+}
+
+__device__ __forceinline__ uint32_t lane_u32(uint32_t x, uint32_t src) {
+    return (uint32_t)__builtin_amdgcn_ds_bpermute((int)(src << 2), (int)x);
+}
+
+// The u64 held as (lo, hi) by lane i (a wave-uniform value); the halves are
+// widened unsigned.
+__device__ __forceinline__ uint64_t lane_key(uint32_t lo, uint32_t hi, int i) {
+    const uint32_t l = (uint32_t)__builtin_amdgcn_readlane((int)lo, i);
+    const uint32_t h = (uint32_t)__builtin_amdgcn_readlane((int)hi, i);
+    return ((uint64_t)h << 32) | l;
+}
+
+__device__ __forceinline__ uint32_t uni_finish(const uint64_t *__restrict__ K, const uint32_t *__restrict__ D,
+                                               const uint4 &v, uint64_t q, uint32_t w0, uint64_t &last) {
+    const uint32_t kb = (w0 + 1) & ~1u, db = w0 & ~3u;
+    // keys <= q among entries w0+1 .. kb+15 (entry kb is w0 itself when w0 is even)
+    uint32_t c = 0;
+#pragma unroll
+    for (int i = 0; i < 8; i++) {
+        const uint64_t k0 = lane_key(v.x, v.y, i), k1 = lane_key(v.z, v.w, i);
+        if (i > 0 || kb > w0) c += k0 <= q ? 1u : 0u;
+        c += k1 <= q ? 1u : 0u;
+    }
+    const uint32_t p = w0 + c;
+    // the stop's key and down pointer from the lanes holding them
+    const uint32_t ko = p - kb;  // < 16 unless every window key is <= q
+    const uint32_t ksrc = (ko >> 1) & 7u;
+    const uint32_t x = lane_u32(v.x, ksrc), y = lane_u32(v.y, ksrc), z = lane_u32(v.z, ksrc),
+                   w = lane_u32(v.w, ksrc);
+    const uint32_t dof = p - db;
+    const uint32_t dsrc = 8 + ((dof >> 2) & 3u);
+    const uint32_t dx = lane_u32(v.x, dsrc), dy = lane_u32(v.y, dsrc), dz = lane_u32(v.z, dsrc),
+                   dw = lane_u32(v.w, dsrc);
+    if (p < kb + 15) {
+        if (c > 0) last = (ko & 1u) ? (((uint64_t)w << 32) | z) : (((uint64_t)y << 32) | x);
+        if (dof >= 16) return D[p];
+        const uint32_t s = dof & 3u;
+        return s == 0 ? dx : s == 1 ? dy : s == 2 ? dz : dw;
+    }
+    // every window key <= q: one key at a time from entry kb+15
+    uint32_t r = kb + 15;
+    last = lane_key(v.z, v.w, 7);
+    for (;;) {
+        const uint64_t kn = K[r + 1];
+        if (kn > q) return D[r];
+        last = kn;
+        r++;
+    }
+}
+
+// True (for the whole wave) when the wave is complete and every lane's QPL
+// entries lie in [w0, w0 + UW_SLACK], w0 being lane 0's first entry.
+template <int QPL>
+__device__ __forceinline__ bool uni_fits(const uint32_t (&pos)[QPL], uint32_t &w0) {
+    w0 = __builtin_amdgcn_readfirstlane(pos[0]);
+    bool ok = true;
+#pragma unroll
+    for (int j = 0; j < QPL; j++) ok &= (pos[j] - w0) <= UW_SLACK;
+    return __builtin_amdgcn_ballot_w64(true) == ~0ull && __builtin_amdgcn_ballot_w64(ok) == ~0ull;
+}
+
 // Descends QPL independent queries together, level by level (the group
 // processing of Section 4.3.4): every query's loads for a level are issued
 // before any of them is used.  Returns, per query, the storage slot of the
@@ -168,6 +257,13 @@ __device__ __forceinline__ void descend_index(const uint64_t (&q)[QPL], const In
         } else {
             const uint64_t *K = lkey + d.off[l];
             const uint32_t *D = ldown + d.off[l];
+            uint32_t w0;
+            if (uni_fits<QPL>(pos, w0)) {
+                const uint4 u = uni_load(K, D, w0);
+#pragma unroll
+                for (int j = 0; j < QPL; j++) pos[j] = uni_finish(K, D, u, q[j], w0, last[j]);
+                continue;
+            }
             Wide<WIN_KP, WIN_DQ> wd[QPL];
 #pragma unroll
             for (int j = 0; j < QPL; j++) wd[j] = wide_load<WIN_KP, WIN_DQ>(K, D, pos[j]);

@@ -152,7 +152,7 @@ void group_capacity(Index &ix, const pi_batch &b, hipStream_t s) {
         if (cur.nused + ins > ix.st.cap) throw GroupError{PI_ERR_CAPACITY, "an index of the group has no room"};
         return;
     }
-    grow_storage(ix, std::max<uint64_t>(cur.nused + b.n, ix.st.cap * 2), s);
+    grow_storage(ix, std::max<uint64_t>(cur.nused + 2 * b.n, ix.st.cap * 2), s);
 }
 
 void run_group(pi_group *g, pi_index *const *indices, const pi_batch *batches, uint32_t count, hipStream_t s,

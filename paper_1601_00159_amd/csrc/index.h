@@ -72,6 +72,7 @@ struct Index {
     static constexpr int STATE_RING = 4;
     DevState *hring = nullptr;
     hipEvent_t ev_ring[STATE_RING] = {};
+    uint64_t ring_n[STATE_RING] = {};  // queries of the batch each copy follows
     uint64_t ring_head = 0;        // copies enqueued
     uint64_t ring_seen = 0;        // copies consumed (or dropped)
 
