@@ -129,11 +129,41 @@ __device__ __forceinline__ uint32_t wide_finish(const uint64_t *__restrict__ K, 
         for (int i = 1; i < ND; i++) d = ((uint32_t)i == di) ? downs[i] : d;
         return d;
     }
-    for (;;) {  // long run of keys <= q: one key at a time
-        const uint64_t kn = K[p + 1];
-        if (kn > q) return D[p];
-        last = kn;
-        p++;
+    for (;;) {  // window exhausted: the next window from p
+        const Wide<KP, DQ> w2 = wide_load<KP, DQ>(K, D, p);
+        uint64_t k2[NK];
+#pragma unroll
+        for (int i = 0; i < KP; i++) {
+            k2[2 * i] = w2.kp[i].x;
+            k2[2 * i + 1] = w2.kp[i].y;
+        }
+        const uint32_t sk2 = (p + 1) & 1u;
+        const uint32_t c2 = leading_le<NK>(k2, sk2, q);
+        if (c2 > 0) {
+            const uint32_t li2 = sk2 + c2 - 1;
+            uint64_t lk = k2[0];
+#pragma unroll
+            for (int i = 1; i < NK; i++) lk = ((uint32_t)i == li2) ? k2[i] : lk;
+            last = lk;
+        }
+        const uint32_t p0 = p;
+        p += c2;
+        if (c2 < NK - sk2) {
+            const uint32_t di = p - (p0 & ~3u);
+            if (di >= (uint32_t)ND) return D[p];
+            uint32_t downs[ND];
+#pragma unroll
+            for (int i = 0; i < DQ; i++) {
+                downs[4 * i] = w2.dq[i].x;
+                downs[4 * i + 1] = w2.dq[i].y;
+                downs[4 * i + 2] = w2.dq[i].z;
+                downs[4 * i + 3] = w2.dq[i].w;
+            }
+            uint32_t d = downs[0];
+#pragma unroll
+            for (int i = 1; i < ND; i++) d = ((uint32_t)i == di) ? downs[i] : d;
+            return d;
+        }
     }
 }
 
