@@ -255,7 +255,7 @@ def run_write(args):
                    "op_mix": "40/50/10 S/I/D", "key_distribution": "zipf 0.99 (inserts fresh uniform)",
                    "parallelism": "single GPU"},
         "latency_ms": {"p50": round(float(np.percentile(lat, 50)), 4), "p99": round(float(np.percentile(lat, 99)), 4),
-                       "max": round(float(lat.max()), 4)},
+                       "max": round(float(lat.max()), 4), "per_batch": [round(float(x), 3) for x in lat]},
         "stages_ms_per_batch": {k: round(prof[k] / nb, 4) for k in ("sort_ms", "descend_ms", "own_ms", "link_ms")},
         "rebuild_policy": args.rebuild_policy,
         "rebuilds_in_timed_region": st["repairs"] - r0,
@@ -413,7 +413,7 @@ def main():
                          "write: write-heavy Zipf batches; serve: continuous batching of Poisson arrivals; "
                          "many: one batch on each of many indices per round")
     ap.add_argument("--indices", type=int, default=512, help="indices (--workload many)")
-    ap.add_argument("--rebuild-policy", default="threshold", choices=["threshold", "background", "never"],
+    ap.add_argument("--rebuild-policy", default="background", choices=["threshold", "background", "never"],
                     help="rebuild policy (--workload write)")
     ap.add_argument("--rates", default="50e6,200e6,500e6", help="offered queries/s (--workload serve)")
     ap.add_argument("--serve-ms", type=float, default=20.0, help="ms of arrivals per rate (--workload serve)")

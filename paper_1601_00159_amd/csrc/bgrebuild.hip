@@ -258,6 +258,25 @@ void bg_release(Index &ix) {
     b.phase = 0;
 }
 
+void bg_reserve(Index &ix) {
+    if (ix.cfg.rebuild_policy != PI_REBUILD_BACKGROUND) return;
+    Index::Background &b = ix.bg;
+    const uint64_t cap = std::max<uint64_t>(ix.st.cap, 1);
+    b.okeys.ensure(cap * 8);
+    b.cnt.ensure(64 * sizeof(uint32_t));
+    b.sortws.ensure(cap);
+    b.msdws.ensure(cap);
+    b.scanws.ensure(cap);
+    b.flags.ensure(cap * 4);
+    b.pos.ensure(cap * 4);
+    for (DevBuf *k : {&b.b2key, &b.o2key, &b.m2key}) k->ensure(cap * 8);
+    for (DevBuf *k : {&b.b2slot, &b.o2slot, &b.m2slot}) k->ensure(cap * 4);
+    scatter_reserve(b.tcnt, b.ttot, cap);
+    const uint64_t e = arena_entries_for(cap);
+    b.akey.ensure(e * 8);
+    b.adown.ensure(e * 4);
+}
+
 void bg_quiesce(Index &ix) {
     if (ix.bg.phase == 0) return;
     PI_HIP(hipStreamSynchronize(ix.bg.side));

@@ -251,6 +251,27 @@ uint32_t blocks_for(uint64_t n, int t) { return (uint32_t)((n + t - 1) / t); }
 
 }  // namespace
 
+// Storage slots beyond the live keys after a bulk load or a storage merge.
+// Under the background policy the storage is merged only when new + deleted
+// nodes reach compact_percent of the base region, so the room covers that
+// many new nodes (plus a quarter): the storage then never grows in between.
+uint64_t storage_room(const Index &ix, uint64_t live) {
+    uint64_t room = std::max<uint64_t>(live / 4, 1 << 16);
+    if (ix.cfg.rebuild_policy == PI_REBUILD_BACKGROUND) {
+        const uint64_t pct = ix.cfg.compact_percent ? ix.cfg.compact_percent : 100;
+        room += live * pct / 100;
+    }
+    return room;
+}
+
+// Index entries an arena needs for any index over a storage of cap slots.
+uint64_t arena_entries_for(uint64_t cap) { return cap + (uint64_t)MAX_LEVELS * (1 + LEVEL_PAD + 16); }
+
+void scatter_reserve(DevBuf &cnt, DevBuf &tot, uint64_t n) {
+    cnt.ensure((size_t)MAX_LEVELS * blocks_for(std::max<uint64_t>(n, 1), BTILE) * sizeof(uint32_t));
+    tot.ensure(MAX_LEVELS * sizeof(uint32_t));
+}
+
 // STORAGE_SLACK slots past the capacity keep the speculative reads of the
 // storage walk (up to two slots past a node) inside the allocation.
 void Storage::alloc(uint64_t c) {
@@ -357,8 +378,13 @@ static void build_levels(Index &ix, hipStream_t s) {
     if (nb > 0 && d.top >= 2) {
         // a quarter of headroom: levels grow with the inserts between
         // rebuilds, and reallocating costs more than the spare bytes
-        if (ix.arena_key.bytes < total * sizeof(uint64_t)) ix.arena_key.ensure(total * sizeof(uint64_t) * 5 / 4);
-        if (ix.arena_down.bytes < total * sizeof(uint32_t)) ix.arena_down.ensure(total * sizeof(uint32_t) * 5 / 4);
+        // (the background policy sizes it for the whole storage: its rebuilds
+        // build into the other arena while batches run, and must not wait)
+        const uint64_t want = ix.cfg.rebuild_policy == PI_REBUILD_BACKGROUND
+                                  ? std::max<uint64_t>(total, arena_entries_for(ix.st.cap))
+                                  : total * 5 / 4;
+        if (ix.arena_key.bytes < total * sizeof(uint64_t)) ix.arena_key.ensure(want * sizeof(uint64_t));
+        if (ix.arena_down.bytes < total * sizeof(uint32_t)) ix.arena_down.ensure(want * sizeof(uint32_t));
         const uint32_t ntiles = blocks_for(nb, BTILE);
         hipLaunchKernelGGL(k_level_scatter, dim3(ntiles), dim3(BT), 0, s, ix.st.key.as<uint64_t>() + 1, nullptr,
                            (uint32_t)nb, ix.cfg.height_seed, ix.cfg.log2_inv_p, ix.cfg.max_height,
@@ -399,6 +425,7 @@ void grow_storage(Index &ix, uint64_t need, hipStream_t s) {
     PI_HIP(hipStreamSynchronize(s));
     ix.st.release();
     ix.st = ns;
+    bg_reserve(ix);
 }
 
 void bulk_load(Index &ix, const uint64_t *keys, const uint64_t *vals, uint64_t n, hipStream_t s) {
@@ -426,8 +453,7 @@ void bulk_load(Index &ix, const uint64_t *keys, const uint64_t *vals, uint64_t n
         // a nonzero capacity_hint is a fixed capacity; otherwise leave room to grow
         if (ix.cfg.capacity_hint && nb + 2 > ix.cfg.capacity_hint)
             throw Error{PI_ERR_CAPACITY, "bulk load exceeds capacity_hint"};
-        const uint64_t want = ix.cfg.capacity_hint ? ix.cfg.capacity_hint
-                                                   : nb + 2 + std::max<uint64_t>(nb / 4, 1 << 16);
+        const uint64_t want = ix.cfg.capacity_hint ? ix.cfg.capacity_hint : nb + 2 + storage_room(ix, nb);
         if (want > ix.st.cap) {
             Storage ns;
             ns.alloc(want);
@@ -446,6 +472,7 @@ void bulk_load(Index &ix, const uint64_t *keys, const uint64_t *vals, uint64_t n
     ix.used_upper = nb + 2;
     ix.live_at_rebuild = nb;
     build_levels(ix, s);
+    bg_reserve(ix);
 }
 
 // Writes the live pairs in key order to okey/oval (+ slot_off), and, when
@@ -536,7 +563,7 @@ void rebuild(Index &ix, hipStream_t s) {
     read_state(ix, s, &cur);
     const uint64_t live = cur.n_live;
     uint64_t ncap = ix.cfg.capacity_hint ? ix.cfg.capacity_hint
-                                         : std::max<uint64_t>(ix.st.cap, live + 2 + std::max<uint64_t>(live / 4, 1 << 16));
+                                         : std::max<uint64_t>(ix.st.cap, live + 2 + storage_room(ix, live));
     // the new base region goes to the spare storage (the one replaced by the
     // previous rebuild) when it is large enough; the current one becomes the
     // spare
@@ -567,6 +594,7 @@ void rebuild(Index &ix, hipStream_t s) {
     ix.changes_base = 0;
     ix.repairs++;
     build_levels(ix, s);
+    bg_reserve(ix);
     if (ix.prof.on) {
         rec.e[1] = ix.prof.take();
         PI_HIP(hipEventRecord(rec.e[1], s));

@@ -181,6 +181,12 @@ void bg_start(Index &ix, const DevState &latest, hipStream_t s);  // enqueues th
 void bg_advance(Index &ix);                                       // moves on when the side stream is done
 void bg_quiesce(Index &ix);                                       // waits and drops a rebuild in flight
 void bg_release(Index &ix);
+// Sizes every buffer of the background rebuild for the storage capacity, so
+// that none is reallocated (a device-wide wait) inside a batch call.
+void bg_reserve(Index &ix);
+uint64_t storage_room(const Index &ix, uint64_t live);
+uint64_t arena_entries_for(uint64_t cap);
+void scatter_reserve(DevBuf &cnt, DevBuf &tot, uint64_t n);
 
 // range.hip
 void range_count(Index &ix, const uint64_t *lo, const uint64_t *hi, uint64_t n, uint64_t *offsets, hipStream_t s);
