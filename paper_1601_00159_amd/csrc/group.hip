@@ -370,10 +370,13 @@ pi_status pi_group_autotune(pi_group *g, pi_index *const *indices, const pi_batc
         // all-SEARCH replays: a zero op array as long as the longest batch
         g->d_zero_ops.ensure(std::max<uint64_t>(nmax, 1));
         PI_HIP(hipMemsetAsync(g->d_zero_ops.p, 0, std::max<uint64_t>(nmax, 1), s));
-        const uint64_t candidates[] = {0, 1024, 4096, 16384, 65536};
+        const uint64_t candidates[] = {0, 1024, 4096, 16384, 65536, 262144, 1048576};
         double best = 1e30;
         uint64_t pick = g->cfg.fused_max;
+        uint64_t prev = 0;
         for (uint64_t t : candidates) {
+            if (t > 0 && prev >= nmax) break;  // the previous threshold already fused every batch
+            prev = t;
             double tmin = 1e30;
             for (int rep = 0; rep < 2; rep++) {
                 PI_HIP(hipStreamSynchronize(s));
