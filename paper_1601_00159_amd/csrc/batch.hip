@@ -504,8 +504,10 @@ void execute_batch(Index &ix, const uint8_t *ops, const uint64_t *keys, const ui
         PI_HIP(hipEventRecord(rec.e[k], s));
     };
     mark(0);
-    hipLaunchKernelGGL(k_batch_begin, dim3(1), dim3(64), 0, s, st, (uint32_t)n);
-    PI_LAUNCH_CHECK();
+    if (n == 0) {  // (otherwise the ordering step clears the per-batch counters)
+        hipLaunchKernelGGL(k_batch_begin, dim3(1), dim3(64), 0, s, st, (uint32_t)n);
+        PI_LAUNCH_CHECK();
+    }
     sort_batch_by_range(ix.sortws, ix.msdws, keys, ops, n, st, s, &sk, &sidx);
     mark(1);
 

@@ -183,6 +183,7 @@ __global__ void k_reset_region(uint64_t *__restrict__ skey, uint64_t *__restrict
     }
     st->b_writers = st->b_new = st->b_deletes = st->b_revives = st->b_hits = st->b_invalid = 0;
     st->b_n = 0;
+    st->b_pad = 0;
 }
 
 // ---- merge of the base region with the overflow nodes -----------------------

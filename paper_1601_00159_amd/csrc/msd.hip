@@ -90,8 +90,10 @@ __global__ __launch_bounds__(MT) void k_minmax(const uint64_t *__restrict__ keys
     }
 }
 
+// Also clears the big-window count and, for a query batch (st given), the
+// per-batch counters (the first kernels to touch them run after this one).
 __global__ __launch_bounds__(MT) void k_make_map(const uint64_t *__restrict__ partials, uint32_t nparts,
-                                                 RangeMap *map) {
+                                                 RangeMap *map, unsigned int *nbig, DevState *st, uint32_t n) {
     __shared__ uint64_t s_red[MNW * 2];
     uint64_t lo = ~0ull, hi = 0;
     for (uint32_t i = threadIdx.x; i < nparts; i += MT) {
@@ -124,6 +126,11 @@ __global__ __launch_bounds__(MT) void k_make_map(const uint64_t *__restrict__ pa
         m.shift = sbits > RANGE_BITS ? sbits - RANGE_BITS : 0;
         m.pad_ = 0;
         *map = m;
+        *nbig = 0;
+        if (st) {
+            st->b_writers = st->b_new = st->b_deletes = st->b_revives = st->b_hits = st->b_invalid = 0;
+            st->b_n = n;
+        }
     }
 }
 
@@ -673,10 +680,6 @@ __global__ __launch_bounds__(WT) void k_big_fixup(uint64_t *__restrict__ kk, uin
     }
 }
 
-__global__ void k_zero_count(unsigned int *c) {
-    if (threadIdx.x == 0) *c = 0;
-}
-
 }  // namespace
 
 void MsdWorkspace::ensure(uint64_t n) {
@@ -709,8 +712,8 @@ void sort_batch_by_range(SortWorkspace &ws, MsdWorkspace &mw, const uint64_t *ke
     RangeMap *map = mw.map.as<RangeMap>();
     const uint32_t parts = std::max<uint32_t>(1, std::min<uint32_t>(MM_BLOCKS, (nn + MT * 16 - 1) / (MT * 16)));
     hipLaunchKernelGGL(k_minmax, dim3(parts), dim3(MT), 0, s, keys, nn, mw.partials.as<uint64_t>());
-    hipLaunchKernelGGL(k_make_map, dim3(1), dim3(MT), 0, s, mw.partials.as<uint64_t>(), parts, map);
-    hipLaunchKernelGGL(k_zero_count, dim3(1), dim3(64), 0, s, mw.nbig.as<unsigned int>());
+    hipLaunchKernelGGL(k_make_map, dim3(1), dim3(MT), 0, s, mw.partials.as<uint64_t>(), parts, map,
+                       mw.nbig.as<unsigned int>(), st, nn);
     PI_LAUNCH_CHECK();
     // group by the 24-bit position inside the span, one byte per pass
     radix_pass(ws, keys, nullptr, ops, nn, 0, map, st, ka, ia, s);

@@ -194,7 +194,8 @@ void sort_pairs(SortWorkspace &ws, const uint64_t *keys, const uint32_t *payload
                 hipStream_t s, const uint64_t **out_keys, const uint32_t **out_payload);
 
 // Ordering of a query batch: partition by key range, then LDS sort of each
-// range (msd.hip).  Same contract as sort_keys_with_index.
+// range (msd.hip).  Same contract as sort_keys_with_index; with st given it
+// also clears st's per-batch counters (b_pad excepted) for a non-empty batch.
 struct MsdWorkspace {
     DevBuf partials, map, big, nbig, dirty;
     void ensure(uint64_t n);

@@ -189,6 +189,7 @@ def test_mixed_batches_vs_oracle(policy):
     orc.bulk_load(lk, lv)
     with Index(rebuild_policy=policy, rebuild_fraction=0.05, rebuild_min=1) as ix:
         ix.bulk_load(lk, lv)
+        tot = {"queries": 0, "hits": 0, "invalid": 0}
         for b in range(6):
             n = [40_000, 1, 4097, 65_536, 12_345, 40_000][b]
             ops, keys, vals = _random_batch(rng, pool, n)
@@ -196,11 +197,18 @@ def test_mixed_batches_vs_oracle(policy):
             wv, ws = orc.execute_batch(ops, keys, vals)
             gv, gs = run_gpu(ix, ops, keys, vals)
             assert_same(gv, gs, wv, ws, f"batch {b}")
+            ws = np.asarray(ws, dtype=np.uint8)
+            tot["queries"] += n
+            tot["hits"] += int((ws == 1).sum())
+            tot["invalid"] += int((ws == 255).sum())
         ek, ev = export_np(ix)
         ok, ov = orc.export()
         assert np.array_equal(ek, ok) and np.array_equal(ev, ov)
         st = ix.stats()
         assert st["live_nodes"] == len(orc)
+        # the library's counters agree with the oracle's answers
+        for k, v in tot.items():
+            assert st[k] == v, (k, st[k], v)
         if policy == "always":
             assert st["repairs"] >= 1 and st["overflow_nodes"] == 0
         # after a rebuild the levels are the canonical ones again
