@@ -28,11 +28,28 @@ def log(*a):
     print("[bench]", *a, file=sys.stderr, flush=True)
 
 
+def _block_from(text, start):
+    """Text of the top-level definition that starts at `start` (up to the
+    first line that is a lone closing brace)."""
+    i = text.index(start)
+    j = text.index("\n}\n", i)
+    return text[i:j + 3]
+
+
 def kernel_source_hash():
+    """Hash of the code the descent kernel is built and launched from: the
+    device headers in full, and from batch.hip the kernel itself and its
+    launch functions (host code elsewhere in that file does not count)."""
+    csrc = os.path.join(ROOT, "paper_1601_00159_amd", "csrc")
     h = hashlib.sha256()
-    for f in ("batch.hip", "descent.h", "pi_internal.h"):
-        with open(os.path.join(ROOT, "paper_1601_00159_amd", "csrc", f), "rb") as fh:
+    for f in ("descent.h", "pi_internal.h", "index.h"):
+        with open(os.path.join(csrc, f), "rb") as fh:
             h.update(fh.read())
+    with open(os.path.join(csrc, "batch.hip")) as fh:
+        b = fh.read()
+    h.update(_block_from(b, "template <int MODE, int QPL, int DT>\n__global__").encode())
+    for name in ("launch_descend_q", "launch_descend_b", "launch_descend("):
+        h.update(_block_from(b, "void " + name).encode())
     return h.hexdigest()[:16]
 
 
