@@ -189,16 +189,63 @@ __device__ __forceinline__ Seg element(const uint64_t *__restrict__ sk, const ui
     return e;
 }
 
+// A thread's OI consecutive sorted queries from base (a multiple of OI):
+// their keys and ops, read with 16- and 4-byte loads when all OI are inside
+// the batch, plus the key before the run (group start) and whether a key
+// follows it (group end).  Past n: key +infinity, no op.
+struct Run {
+    uint64_t k[OI];
+    uint8_t op[OI];
+    uint64_t prev, next;
+    bool has_next;
+};
+
+__device__ __forceinline__ Run load_run(const uint64_t *__restrict__ sk, const uint8_t *__restrict__ sop,
+                                        uint32_t n, uint32_t base) {
+    static_assert(OI == 4, "two key pairs and one op word per run");
+    Run r;
+    if (base + OI <= n) {
+        const ulonglong2 a = *reinterpret_cast<const ulonglong2 *>(sk + base);
+        const ulonglong2 b = *reinterpret_cast<const ulonglong2 *>(sk + base + 2);
+        r.k[0] = a.x, r.k[1] = a.y, r.k[2] = b.x, r.k[3] = b.y;
+        const uint32_t o4 = *reinterpret_cast<const uint32_t *>(sop + base);
+#pragma unroll
+        for (int e = 0; e < OI; e++) r.op[e] = (uint8_t)(o4 >> (8 * e));
+    } else {
+#pragma unroll
+        for (int e = 0; e < OI; e++) {
+            const uint32_t i = base + e;
+            r.k[e] = i < n ? sk[i] : KEY_MAX;
+            r.op[e] = i < n ? sop[i] : (uint8_t)255;
+        }
+    }
+    r.prev = base > 0 && base <= n ? sk[base - 1] : 0;
+    r.has_next = base + OI < n;
+    r.next = r.has_next ? sk[base + OI] : KEY_MAX;
+    return r;
+}
+
+// element e of a run (see element above)
+__device__ __forceinline__ Seg run_element(const Run &r, uint32_t base, int e) {
+    Seg x;
+    const uint64_t q = r.k[e];
+    const uint64_t before = e == 0 ? r.prev : r.k[e > 0 ? e - 1 : 0];
+    x.f = (base + e == 0 || before != q) ? 1u : 0u;
+    const uint8_t op = r.op[e];
+    x.v = (q != KEY_MAX && (op == PI_OP_INSERT || op == PI_OP_DELETE)) ? (int32_t)(base + e) : -1;
+    return x;
+}
+
 __global__ __launch_bounds__(OT) void k_own_reduce(const uint64_t *__restrict__ sk, const uint8_t *__restrict__ sop,
                                                    uint32_t n, const DevState *st, Seg *__restrict__ agg) {
     if (st->b_writers == 0) return;
     __shared__ Seg s_w[ONW];
     const uint32_t base = blockIdx.x * OTILE + threadIdx.x * OI;
+    const Run r = load_run(sk, sop, n, base);
     Seg run{0, -1};
-    for (int e = 0; e < OI; e++) {
-        const uint32_t i = base + e;
-        if (i < n) run = seg_op(run, element(sk, sop, i, sk[i]));
-    }
+#pragma unroll
+    for (int e = 0; e < OI; e++)
+        if (base + e < n) run = seg_op(run, run_element(r, base, e));
     Seg tot;
     block_excl_scan_seg(run, s_w, &tot);
     if (threadIdx.x == 0) agg[blockIdx.x] = tot;
@@ -240,36 +287,55 @@ __global__ __launch_bounds__(OT) void k_own_apply(const uint64_t *__restrict__ s
     if (st->b_writers == 0) return;
     __shared__ Seg s_w[ONW];
     const uint32_t base = blockIdx.x * OTILE + threadIdx.x * OI;
+    const Run r = load_run(sk, sop, n, base);
+    const bool whole = base + OI <= n;
     Seg el[OI];
-    uint64_t qk[OI];
     Seg run{0, -1};
+#pragma unroll
     for (int e = 0; e < OI; e++) {
-        const uint32_t i = base + e;
-        if (i < n) {
-            qk[e] = sk[i];
-            el[e] = element(sk, sop, i, qk[e]);
-        } else {
-            qk[e] = KEY_MAX;
-            el[e] = Seg{0, -1};
-        }
+        el[e] = base + e < n ? run_element(r, base, e) : Seg{0, -1};
         run = seg_op(run, el[e]);
+    }
+    // the per-query state of the descent, four at a time when whole
+    uint32_t id4[OI], loc4[OI];
+    uint8_t fl4[OI];
+    uint64_t rv4[OI];
+    if (whole) {
+        const uint4 a = *reinterpret_cast<const uint4 *>(sidx + base);
+        const uint4 l = *reinterpret_cast<const uint4 *>(loc + base);
+        const uint32_t f = *reinterpret_cast<const uint32_t *>(res_flags + base);
+        const ulonglong2 v0 = *reinterpret_cast<const ulonglong2 *>(res_val + base);
+        const ulonglong2 v1 = *reinterpret_cast<const ulonglong2 *>(res_val + base + 2);
+        id4[0] = a.x, id4[1] = a.y, id4[2] = a.z, id4[3] = a.w;
+        loc4[0] = l.x, loc4[1] = l.y, loc4[2] = l.z, loc4[3] = l.w;
+#pragma unroll
+        for (int e = 0; e < OI; e++) fl4[e] = (uint8_t)(f >> (8 * e));
+        rv4[0] = v0.x, rv4[1] = v0.y, rv4[2] = v1.x, rv4[3] = v1.y;
+    } else {
+#pragma unroll
+        for (int e = 0; e < OI; e++) {
+            const uint32_t i = base + e;
+            id4[e] = i < n ? sidx[i] : 0;
+            loc4[e] = i < n ? loc[i] : 0;
+            fl4[e] = i < n ? res_flags[i] : 0;
+            rv4[e] = i < n ? res_val[i] : 0;
+        }
     }
     Seg tot;
     Seg pre = seg_op(carry_in[blockIdx.x], block_excl_scan_seg(run, s_w, &tot));
     uint32_t hits = 0, dels = 0, revs = 0;
+    uint32_t nf4[OI] = {0, 0, 0, 0};
+#pragma unroll
     for (int e = 0; e < OI; e++) {
         const uint32_t i = base + e;
         if (i >= n) break;
         const int32_t excl = el[e].f ? -1 : pre.v;
         pre = seg_op(pre, el[e]);
         const int32_t incl = pre.v;
-        const uint64_t q = qk[e];
-        if (q == KEY_MAX) {  // invalid: answered by the descent, no effect
-            newflag[i] = 0;
-            continue;
-        }
-        const uint32_t id = sidx[i];
-        const uint8_t fl = res_flags[i];
+        const uint64_t q = r.k[e];
+        if (q == KEY_MAX) continue;  // invalid: answered by the descent, no effect
+        const uint32_t id = id4[e];
+        const uint8_t fl = fl4[e];
         // answer: the state left by the last update before i on this key,
         // else the state found in storage
         uint64_t v;
@@ -279,16 +345,16 @@ __global__ __launch_bounds__(OT) void k_own_apply(const uint64_t *__restrict__ s
             v = present ? svin[excl] : 0;
         } else {
             present = (fl & 2) != 0;
-            v = res_val[i];
+            v = rv4[e];
         }
         out_vals[id] = v;
         out_status[id] = present ? PI_R_PRESENT : PI_R_ABSENT;
         hits += present;
         // the group's last query owns the key's node
-        const bool last = (i + 1 == n) || sk[i + 1] != q;
+        const bool last = e + 1 < OI ? r.k[e + 1 < OI ? e + 1 : 0] != q : (!r.has_next || r.next != q);
         uint32_t nf = 0;
         if (last && incl >= 0) {
-            const uint32_t node = loc[i];
+            const uint32_t node = loc4[e];
             const bool exists = fl & 1, live = (fl & 2) != 0;
             if (sop[incl] == PI_OP_INSERT) {
                 if (exists) {
@@ -306,7 +372,14 @@ __global__ __launch_bounds__(OT) void k_own_apply(const uint64_t *__restrict__ s
                 dels++;
             }
         }
-        newflag[i] = nf;
+        nf4[e] = nf;
+    }
+    if (whole) {
+        *reinterpret_cast<uint4 *>(newflag + base) = make_uint4(nf4[0], nf4[1], nf4[2], nf4[3]);
+    } else {
+#pragma unroll
+        for (int e = 0; e < OI; e++)
+            if (base + e < n) newflag[base + e] = nf4[e];
     }
     hits = wave_sum_u32(hits);
     dels = wave_sum_u32(dels);
