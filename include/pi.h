@@ -74,11 +74,12 @@ enum {
                                  storage as it stands (new nodes included) on a second stream while
                                  batches go on, and switch to it at a batch boundary (Section 4.3.5);
                                  merge the storage itself (a full rebuild) only when the new and
-                                 deleted nodes reach compact_percent of the base region.  No batch
-                                 call waits for the device under this policy: the storage keeps room
-                                 for new nodes up to that merge point, and the buffers of the
-                                 background rebuild (about 88 bytes per storage slot) are reserved
-                                 when the storage is loaded, merged or grown */
+                                 deleted nodes reach compact_percent of the base region.  Batch calls
+                                 neither allocate nor free device memory under this policy (freeing
+                                 waits for the whole device): the storage keeps room for new nodes
+                                 up to that merge point, and the buffers of the background rebuild
+                                 (about 88 bytes per storage slot) are reserved when the storage is
+                                 loaded, merged or grown */
 };
 
 typedef struct {
