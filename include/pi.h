@@ -199,8 +199,11 @@ pi_status pi_export(pi_index *idx, uint64_t *d_keys, uint64_t *d_values, uint64_
  *                    a range may fill fewer entries than reserved.
  *
  * Inputs d_lo, d_hi u64[n] and d_offsets are device memory owned by the
- * caller; both calls are asynchronous on the stream and do not change the
- * index.  n = 0 writes d_offsets[0] = 0.  Errors: PI_ERR_INVALID_ARG for
+ * caller, and d_lo, d_hi hold the same ranges in both calls; both calls are
+ * asynchronous on the stream and do not change the index.  A collect that
+ * follows the count of the same arrays with no other call on this index in
+ * between reuses the count's ordering of the ranges and their
+ * interceptions instead of computing them again.  n = 0 writes d_offsets[0] = 0.  Errors: PI_ERR_INVALID_ARG for
  * NULL pointers or n above 2^31 - 1. */
 pi_status pi_range_count(pi_index *idx, const uint64_t *d_lo, const uint64_t *d_hi, uint64_t n,
                          uint64_t *d_offsets, pi_stream stream);

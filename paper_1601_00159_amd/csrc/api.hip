@@ -65,11 +65,15 @@ struct DeviceGuard {
     }
 };
 
+// keeps_state: the call changes neither the storage nor the ordering
+// workspace (a range collect, a counter read), so a cached range location
+// stays valid across it.
 template <class F>
-pi_status guarded(pi_index *h, F &&f) {
+pi_status guarded(pi_index *h, F &&f, bool keeps_state = false) {
     if (!h) return PI_ERR_INVALID_ARG;
     pi::Index &ix = h->ix;
     if (ix.failed) return PI_ERR_DEVICE;
+    if (!keeps_state) ix.epoch++;
     try {
         DeviceGuard g(ix.device);
         pi_status r = f(ix);
@@ -440,7 +444,7 @@ pi_status pi_range_collect(pi_index *h, const uint64_t *d_lo, const uint64_t *d_
             return fail(ix, PI_ERR_INVALID_ARG, "NULL pointer");
         pi::range_collect(ix, d_lo, d_hi, n, d_offsets, d_keys, d_values, (hipStream_t)stream);
         return PI_OK;
-    });
+    }, true);
 }
 
 pi_status pi_get_stats(pi_index *h, pi_stats *out) {

@@ -82,6 +82,16 @@ struct Index {
     BatchWorkspace bws;
     DevBuf tmp[10];                // rebuild / export scratch
     DevBuf rng[4];                 // range search: first node, end slot, counts, scan tiles
+    // Bumped by every call that may change the storage or reuse the ordering
+    // workspace; a range collect right after the count of the same ranges
+    // (same arrays, same epoch) reuses the count's ordering and interceptions.
+    uint64_t epoch = 0;
+    struct RangeCache {
+        const uint64_t *lo = nullptr, *hi = nullptr;
+        uint64_t n = 0, epoch = ~0ull;
+        const uint64_t *slo = nullptr;
+        const uint32_t *sperm = nullptr;
+    } rcache;
     // captured hot path per batch-size class 2^c (queries padded with invalid
     // ones), valid while the buffers and launch parameters it was captured
     // with are unchanged

@@ -305,6 +305,7 @@ void range_count(Index &ix, const uint64_t *lo, const uint64_t *hi, uint64_t n, 
     hipLaunchKernelGGL(k_off_tiles, dim3(1), dim3(ST_), 0, s, tiles, ntiles, offsets + n);
     hipLaunchKernelGGL(k_off_down, dim3(ntiles), dim3(ST_), 0, s, counts, n, tiles, offsets);
     PI_LAUNCH_CHECK();
+    ix.rcache = Index::RangeCache{lo, hi, n, ix.epoch, slo, sperm};
 }
 
 void range_collect(Index &ix, const uint64_t *lo, const uint64_t *hi, uint64_t n, const uint64_t *offsets,
@@ -312,7 +313,14 @@ void range_collect(Index &ix, const uint64_t *lo, const uint64_t *hi, uint64_t n
     if (n == 0) return;
     const uint64_t *slo;
     const uint32_t *sperm;
-    locate(ix, lo, hi, n, s, &slo, &sperm);
+    const Index::RangeCache &c = ix.rcache;
+    if (c.epoch == ix.epoch && c.lo == lo && c.hi == hi && c.n == n) {
+        // the count of these ranges ran last: its order and interceptions stand
+        slo = c.slo;
+        sperm = c.sperm;
+    } else {
+        locate(ix, lo, hi, n, s, &slo, &sperm);
+    }
     hipLaunchKernelGGL(k_range_slots, dim3(wave_grid(ix, n)), dim3(WT), 0, s, ix.rng[0].as<uint32_t>(),
                        ix.rng[1].as<uint32_t>(), sperm, (uint32_t)n, ix.st.key.as<uint64_t>(),
                        ix.st.val.as<uint64_t>(), ix.st.meta.as<uint8_t>(), (const DevState *)ix.dstate, nullptr,
