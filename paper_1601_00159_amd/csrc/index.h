@@ -83,8 +83,9 @@ struct Index {
     DevBuf tmp[10];                // rebuild / export scratch
     DevBuf rng[4];                 // range search: first node, end slot, counts, scan tiles
     // Bumped by every call that may change the storage or reuse the ordering
-    // workspace; a range collect right after the count of the same ranges
-    // (same arrays, same epoch) reuses the count's ordering and interceptions.
+    // workspace.  rcache names the ranges whose order and interceptions the
+    // workspaces hold (set by every range location); a range collect of the
+    // same arrays in the same epoch reuses them.
     uint64_t epoch = 0;
     struct RangeCache {
         const uint64_t *lo = nullptr, *hi = nullptr;

@@ -270,6 +270,8 @@ void locate(Index &ix, const uint64_t *lo, const uint64_t *hi, uint64_t n, hipSt
                        ix.st.meta.as<uint8_t>(), *slo, *sperm, hi, (uint32_t)n, ix.dstate, ix.rng[0].as<uint32_t>(),
                        ix.rng[1].as<uint32_t>());
     PI_LAUNCH_CHECK();
+    // the workspaces now hold the location of these ranges
+    ix.rcache = Index::RangeCache{lo, hi, n, ix.epoch, *slo, *sperm};
 }
 
 uint32_t wave_grid(const Index &ix, uint64_t n) {
@@ -305,7 +307,6 @@ void range_count(Index &ix, const uint64_t *lo, const uint64_t *hi, uint64_t n, 
     hipLaunchKernelGGL(k_off_tiles, dim3(1), dim3(ST_), 0, s, tiles, ntiles, offsets + n);
     hipLaunchKernelGGL(k_off_down, dim3(ntiles), dim3(ST_), 0, s, counts, n, tiles, offsets);
     PI_LAUNCH_CHECK();
-    ix.rcache = Index::RangeCache{lo, hi, n, ix.epoch, slo, sperm};
 }
 
 void range_collect(Index &ix, const uint64_t *lo, const uint64_t *hi, uint64_t n, const uint64_t *offsets,
@@ -315,7 +316,7 @@ void range_collect(Index &ix, const uint64_t *lo, const uint64_t *hi, uint64_t n
     const uint32_t *sperm;
     const Index::RangeCache &c = ix.rcache;
     if (c.epoch == ix.epoch && c.lo == lo && c.hi == hi && c.n == n) {
-        // the count of these ranges ran last: its order and interceptions stand
+        // these ranges were the last located: their order and interceptions stand
         slo = c.slo;
         sperm = c.sperm;
     } else {

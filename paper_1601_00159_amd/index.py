@@ -180,6 +180,8 @@ class Index:
     def range_search(self, lo, hi, stream=None):
         """(counts, keys, values): every live pair of each range [lo[i], hi[i]],
         concatenated in range order.  Synchronises to size the output."""
+        lo = to_device_u64(lo, self.device)  # one device copy for both calls
+        hi = to_device_u64(hi, self.device)
         off = self.range_count(lo, hi, stream)
         total = int(off[-1].item())
         k, v = self.range_collect(lo, hi, off, total, stream)

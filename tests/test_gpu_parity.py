@@ -16,7 +16,7 @@ from oracle import mapref
 from oracle.skiplist import SkipList
 from paper_1601_00159_amd import workloads as W
 from paper_1601_00159_amd._lib import PI_ERR_CAPACITY, PI_ERR_STATE, PiError
-from paper_1601_00159_amd.index import Index, to_numpy_u64
+from paper_1601_00159_amd.index import Index, to_device_u64, to_numpy_u64
 
 pytestmark = pytest.mark.gpu
 KMAX = (1 << 64) - 1
@@ -440,6 +440,31 @@ def test_range_search_vs_oracle(state):
         torch.cuda.synchronize()
         assert np.array_equal(gc.cpu().numpy().astype(np.uint64), wc)
         assert np.array_equal(to_numpy_u64(gk), wk) and np.array_equal(to_numpy_u64(gv), wv)
+
+
+def test_range_collect_after_other_counts():
+    """A collect reuses the ordering of the count just before it only when
+    that count was of the same ranges: two counts, then the two collects in
+    the other order, give the oracle's pairs for both."""
+    rng = np.random.default_rng(12)
+    lk = rng.integers(0, 1 << 63, size=50_000, dtype=np.uint64)
+    lv = rng.integers(0, 1 << 64, size=50_000, dtype=np.uint64, endpoint=False)
+    orc = SkipList()
+    orc.bulk_load(lk, lv)
+    ok, _ = orc.export()
+    sets = [_ranges(rng, ok, 3_000), _ranges(rng, ok, 5_000)]
+    with Index() as ix:
+        ix.bulk_load(lk, lv)
+        dev = [(to_device_u64(lo, ix.device), to_device_u64(hi, ix.device)) for lo, hi in sets]
+        offs = [ix.range_count(lo, hi) for lo, hi in dev]
+        for j in (0, 1, 1):  # the other set's count came last; then the same set twice
+            lo, hi = dev[j]
+            total = int(offs[j][-1].item())
+            gk, gv = ix.range_collect(lo, hi, offs[j], total)
+            torch.cuda.synchronize()
+            wc, wk, wv = orc.range_batch(*sets[j])
+            assert np.array_equal((offs[j][1:] - offs[j][:-1]).cpu().numpy().astype(np.uint64), wc)
+            assert np.array_equal(to_numpy_u64(gk), wk) and np.array_equal(to_numpy_u64(gv), wv), j
 
 
 def test_range_search_edges():
