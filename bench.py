@@ -365,9 +365,12 @@ def run_many(args):
         torch.cuda.synchronize()
         g = Group() if mode == "group" else None
         fused = None
+        shape = None
         if g is not None:
             fused = g.autotune(ixs, dev_rounds[-1])
-            log(f"autotuner picked fused_max={fused}")
+            _, tb, tl = g.tuning()
+            shape = {"block": tb, "lds_budget": tl}
+            log(f"autotuner picked fused_max={fused}, descent block {tb}, LDS budget {tl}")
 
         def one_round(r):
             if g is not None:
@@ -401,7 +404,9 @@ def run_many(args):
             "scaling": "weak", "vs_baseline": None, "dtype": "u64", "data": "synthetic",
             "config": {"workload": w.name, "indices": args.indices, "total_keys": int(total_keys),
                        "queries_per_round": int(np.mean(q_per_round)), "op_mix": "90/5/5 S/I/D", "mode": mode,
-                       "fused_max": fused, "parallelism": "single GPU"},
+                       "fused_max": fused,
+                       "descent_shape": shape,
+                       "parallelism": "single GPU"},
             "latency_ms": {"round_p50": round(float(np.percentile(lat, 50)) * 1e3, 3),
                            "round_p99": round(float(np.percentile(lat, 99)) * 1e3, 3)},
             "roofline": None, "cpu_baseline": None}), flush=True)

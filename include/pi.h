@@ -290,11 +290,19 @@ pi_status pi_group_destroy(pi_group *g);
 pi_status pi_group_execute(pi_group *g, pi_index *const *indices, const pi_batch *batches, uint32_t count,
                            pi_stream stream);
 /* Autotuner: replays the given batches as SEARCH-only (the indices' contents
- * do not change; their query counters do) under several fused_max
- * thresholds, keeps the fastest in the group and returns it in *fused_max
- * (host).  Synchronises the stream. */
+ * do not change; their query counters do).  First under several fused_max
+ * thresholds (the batch size that still runs in the fused launch): keeps the
+ * fastest in the group and returns it in *fused_max (host).  Then, when some
+ * batch exceeds it, under several descent shapes for the multi-kernel path
+ * -- threads per workgroup (256/512/1024: the key range one workgroup's
+ * tiles cover) with an LDS staging budget (3000..12000 entries) -- and sets
+ * the fastest as descent_block and lds_budget of every given index.
+ * Synchronises the stream. */
 pi_status pi_group_autotune(pi_group *g, pi_index *const *indices, const pi_batch *batches, uint32_t count,
                             pi_stream stream, uint64_t *fused_max);
+/* What the last autotune chose: the fused threshold, and the descent shape it
+ * applied to the indices (0, 0 when it tried none).  Host pointers. */
+pi_status pi_group_tuning(const pi_group *g, uint64_t *fused_max, uint32_t *descent_block, uint32_t *lds_budget);
 /* Message of the last error of the group. */
 const char *pi_group_last_error(const pi_group *g);
 

@@ -53,7 +53,7 @@ class pi_stats(ctypes.Structure):
 
 EXPORTED = ["pi_config_default", "pi_create", "pi_destroy", "pi_bulk_load", "pi_execute_batch",
             "pi_repair", "pi_export", "pi_range_count", "pi_range_collect", "pi_serve_config_default", "pi_serve", "pi_group_config_default", "pi_group_create",
-            "pi_group_destroy", "pi_group_execute", "pi_group_autotune", "pi_group_last_error", "pi_get_stats", "pi_get_profile", "pi_last_error", "pi_debug_interceptions",
+            "pi_group_destroy", "pi_group_execute", "pi_group_autotune", "pi_group_tuning", "pi_group_last_error", "pi_get_stats", "pi_get_profile", "pi_last_error", "pi_debug_interceptions",
             "pi_debug_level", "pi_debug_sort"]
 
 
@@ -100,6 +100,7 @@ def load(path: str = LIB_PATH):
         "pi_group_destroy": ([vp], i32),
         "pi_group_execute": ([vp, vp, ctypes.POINTER(pi_batch), u32, vp], i32),
         "pi_group_autotune": ([vp, vp, ctypes.POINTER(pi_batch), u32, vp, ctypes.POINTER(u64)], i32),
+        "pi_group_tuning": ([vp, ctypes.POINTER(u64), ctypes.POINTER(u32), ctypes.POINTER(u32)], i32),
         "pi_group_last_error": ([vp], ctypes.c_char_p),
         "pi_get_stats": ([vp, ctypes.POINTER(pi_stats)], i32),
         "pi_get_profile": ([vp, ctypes.POINTER(pi_profile), i32], i32),

@@ -318,6 +318,12 @@ IndexDesc make_desc(const Index &ix, const uint32_t *level_n, uint64_t *arena_en
         total += ((uint64_t)d.n[l] + 1 + LEVEL_PAD + 15) & ~15ull;
     }
     *arena_entries = total;
+    select_lds_levels(ix, d);
+    return d;
+}
+
+// The top levels that fit the descent's LDS budget (and the lds_levels cap).
+void select_lds_levels(const Index &ix, IndexDesc &d) {
     const uint32_t budget = ix.cfg.lds_budget ? ix.cfg.lds_budget : 12000;  // 12000 entries: 141 KB per block
     uint32_t used = 0;
     int from = d.top + 1;
@@ -331,7 +337,6 @@ IndexDesc make_desc(const Index &ix, const uint32_t *level_n, uint64_t *arena_en
     }
     d.lds_from = d.top >= 2 ? from : MAX_LEVELS;
     d.lds_entries = used;
-    return d;
 }
 
 // Writes the levels of d from keys[0 .. n) (increasing; level-2 down

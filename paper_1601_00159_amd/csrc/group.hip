@@ -82,6 +82,7 @@ struct pi_group {
     hipStream_t fstream = nullptr;                      // the fused launch runs beside the large batches
     bool pending = false;
     bool lds_attr = false;
+    uint32_t tuned_block = 0, tuned_lds = 0;  // descent shape the autotuner applied (0 = none)
     std::string err;
 };
 
@@ -394,8 +395,55 @@ pi_status pi_group_autotune(pi_group *g, pi_index *const *indices, const pi_batc
         }
         g->cfg.fused_max = pick;
         *fused_max = pick;
+        // then the descent shape of the batches left to the multi-kernel path:
+        // threads per workgroup (the key range one workgroup's tiles cover)
+        // and the LDS staging depth
+        bool any_large = false;
+        for (uint32_t i = 0; i < count; i++) any_large |= batches[i].n > pick;
+        if (!any_large) return PI_OK;
+        struct Shape {
+            uint32_t block, lds;
+        };
+        const Shape shapes[] = {{1024, 12000}, {1024, 4000}, {512, 6000}, {256, 3000}};
+        auto apply = [&](const Shape &sh) {
+            for (uint32_t i = 0; i < count; i++) {
+                pi::Index &ix = indices[i]->ix;
+                ix.cfg.descent_block = sh.block;
+                ix.cfg.lds_budget = sh.lds;
+                pi::select_lds_levels(ix, ix.desc);
+            }
+        };
+        double best_shape = 1e30;
+        Shape keep = shapes[0];
+        for (const Shape &sh : shapes) {
+            apply(sh);
+            double tmin = 1e30;
+            for (int rep = 0; rep < 2; rep++) {
+                PI_HIP(hipStreamSynchronize(s));
+                const auto t0 = std::chrono::steady_clock::now();
+                pi::run_group(g, indices, batches, count, s, pick, g->d_zero_ops.as<uint8_t>());
+                PI_HIP(hipStreamSynchronize(s));
+                const double dt = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+                tmin = std::min(tmin, dt);
+            }
+            if (tmin < best_shape) {
+                best_shape = tmin;
+                keep = sh;
+            }
+        }
+        apply(keep);
+        g->tuned_block = keep.block;
+        g->tuned_lds = keep.lds;
         return PI_OK;
     });
+}
+
+pi_status pi_group_tuning(const pi_group *g, uint64_t *fused_max, uint32_t *descent_block, uint32_t *lds_budget) {
+    if (!g || !fused_max || !descent_block || !lds_budget) return PI_ERR_INVALID_ARG;
+    *fused_max = g->cfg.fused_max;
+    *descent_block = g->tuned_block;
+    *lds_budget = g->tuned_lds;
+    return PI_OK;
 }
 
 const char *pi_group_last_error(const pi_group *g) { return g ? g->err.c_str() : ""; }

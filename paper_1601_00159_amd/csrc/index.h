@@ -184,6 +184,7 @@ uint64_t serve_loop(const double *arrival_us, uint64_t n, const ServePlan &plan,
 
 // build.hip: level descriptor from sizes; level arrays from sorted keys
 IndexDesc make_desc(const Index &ix, const uint32_t *level_n, uint64_t *arena_entries);
+void select_lds_levels(const Index &ix, IndexDesc &d);
 void scatter_levels(const Index &ix, const uint64_t *keys, const uint32_t *slots, uint64_t n, const IndexDesc &d,
                     DevBuf &cnt, DevBuf &tot, DevBuf &akey, DevBuf &adown, hipStream_t s);
 

@@ -291,3 +291,10 @@ class Group:
         out = ctypes.c_uint64()
         self._check(self._L.pi_group_autotune(self._h, hs, bs, len(indices), _stream(stream), ctypes.byref(out)))
         return out.value
+
+    def tuning(self):
+        """(fused_max, descent_block, lds_budget) chosen by the last autotune
+        (0, 0 for the descent shape when it tried none)."""
+        f, b, l = ctypes.c_uint64(), ctypes.c_uint32(), ctypes.c_uint32()
+        self._check(self._L.pi_group_tuning(self._h, ctypes.byref(f), ctypes.byref(b), ctypes.byref(l)))
+        return f.value, b.value, l.value

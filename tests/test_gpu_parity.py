@@ -637,14 +637,59 @@ def test_group_autotune_and_errors():
                   torch.empty(len(x), dtype=torch.uint8, device=dev)) for x in b]
         with Group() as g:
             t = g.autotune(ixs, dev_b)
-            assert t in (0, 1024, 4096, 16384, 65536)
+            assert t in (0, 1024, 4096, 16384, 65536, 262144, 1048576)
+            ft, blk, lds = g.tuning()
+            assert ft == t
+            if any(len(x) > t for x in b):  # the descent shape was tuned and applied
+                assert blk in (256, 512, 1024) and 3000 <= lds <= 12000
+                assert all(ix.stats()["lds_from"] >= 2 for ix in ixs)
+            else:
+                assert (blk, lds) == (0, 0)
             # the SEARCH-only replays left every index as it was
             for ix, (k0, v0) in zip(ixs, before):
                 k1, v1 = export_np(ix)
                 assert np.array_equal(k0, k1) and np.array_equal(v0, v1)
+            # and the tuned group still gives every index its serial answers
+            orcs = []
+            for (k, v) in w.loads:
+                o = SkipList()
+                o.bulk_load(k, v)
+                orcs.append(o)
+            g.execute(ixs, dev_b)
+            torch.cuda.synchronize()
+            for j, (o, x) in enumerate(zip(orcs, b)):
+                wv, ws = o.execute_batch(x.ops, x.keys, x.vals)
+                assert_same(to_numpy_u64(dev_b[j][3]), dev_b[j][4].cpu().numpy(), wv, ws, f"index {j}")
             with pytest.raises(PiError) as e:
                 g.execute([ixs[0], ixs[0]], [dev_b[0], dev_b[0]])  # one index twice
             assert e.value.status == PI_ERR_INVALID_ARG
+    finally:
+        for ix in ixs:
+            ix.close()
+    # batches too large to fuse: the descent shape is tuned, and applied
+    w = W.many_indices(n_indices=2, size_log2=(14, 15), batch_log2=(18.3, 18.4), n_rounds=1, seed_id=21)
+    ixs = [Index() for _ in w.loads]
+    try:
+        orcs = []
+        for ix, (k, v) in zip(ixs, w.loads):
+            ix.bulk_load(k, v)
+            o = SkipList()
+            o.bulk_load(k, v)
+            orcs.append(o)
+        b = w.rounds[0]
+        dev_b = [(d8(x.ops, dev), d64(x.keys, dev), d64(x.vals, dev), torch.empty(len(x), dtype=torch.int64, device=dev),
+                  torch.empty(len(x), dtype=torch.uint8, device=dev)) for x in b]
+        with Group() as g:
+            t = g.autotune(ixs, dev_b)
+            ft, blk, lds = g.tuning()
+            say(f"fused_max {t}, descent block {blk}, lds budget {lds}")
+            assert ft == t and t < min(len(x) for x in b)
+            assert blk in (256, 512, 1024) and 3000 <= lds <= 12000
+            g.execute(ixs, dev_b)
+            torch.cuda.synchronize()
+            for j, (o, x) in enumerate(zip(orcs, b)):
+                wv, ws = o.execute_batch(x.ops, x.keys, x.vals)
+                assert_same(to_numpy_u64(dev_b[j][3]), dev_b[j][4].cpu().numpy(), wv, ws, f"index {j}")
     finally:
         for ix in ixs:
             ix.close()
