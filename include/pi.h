@@ -103,7 +103,8 @@ typedef struct {
     uint32_t small_batch_log2; /* batches of at most 2^small_batch_log2 queries run in one workgroup, one
                                  launch (0 = 10, i.e. 1024; 1..12; 255 = never) */
     uint32_t compact_percent; /* PI_REBUILD_BACKGROUND: full rebuild when new + deleted nodes reach this
-                                 percentage of the base region (0 = 100) */
+                                 percentage of the base region (0 = 100, at most 1000); the storage
+                                 keeps room for that many new nodes */
     uint64_t rebuild_min;     /* a threshold rebuild also needs at least this many changes (default 4096):
                                  an index of a few thousand keys is cheaper to walk than to rebuild */
 } pi_config;

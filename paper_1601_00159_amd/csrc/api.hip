@@ -266,7 +266,7 @@ pi_status pi_create(const pi_config *cfg_in, pi_index **out) {
         (cfg.descent_block != 0 && cfg.descent_block != 256 && cfg.descent_block != 512 &&
          cfg.descent_block != 1024) ||
         (cfg.graph_max_log2 != 0 && (cfg.graph_max_log2 < 12 || cfg.graph_max_log2 > 22)) ||
-        (cfg.small_batch_log2 > 12 && cfg.small_batch_log2 != 255)) {
+        (cfg.small_batch_log2 > 12 && cfg.small_batch_log2 != 255) || cfg.compact_percent > 1000) {
         set_err("invalid pi_config field");
         return PI_ERR_INVALID_ARG;
     }

@@ -69,3 +69,21 @@ def test_config_default_without_gpu():
     assert L.pi_serve_config_default(ctypes.byref(scfg)) == _lib.PI_OK
     assert scfg.struct_size == ctypes.sizeof(_lib.pi_serve_config)
     assert scfg.deadline_us == 100.0 and scfg.max_inflight == 1 and scfg.max_batch == 0
+
+
+@pytest.mark.parametrize("field,value", [("compact_percent", 1001), ("lds_budget", 13001), ("descent_block", 300),
+                                         ("queries_per_lane", 3), ("small_batch_log2", 13), ("graph_max_log2", 11),
+                                         ("max_height", 1), ("log2_inv_p", 9), ("rebuild_policy", 4)])
+def test_create_rejects_bad_config_before_device_work(field, value):
+    """Every range check of pi_config runs before any device call: on this
+    GPU-less host the error names the field, not the missing device."""
+    if not os.path.exists(_lib.LIB_PATH):
+        pytest.skip("libpi.so not built")
+    L = _lib.load()
+    cfg = _lib.pi_config()
+    assert L.pi_config_default(ctypes.byref(cfg)) == _lib.PI_OK
+    setattr(cfg, field, value)
+    h = ctypes.c_void_p()
+    assert L.pi_create(ctypes.byref(cfg), ctypes.byref(h)) == _lib.PI_ERR_INVALID_ARG
+    assert not h.value
+    assert b"invalid pi_config field" in L.pi_last_error(None)
