@@ -171,17 +171,23 @@ void build_phase(Index &ix) {
 
 }  // namespace
 
+// The side stream, its events and the pinned count buffer (made once; at
+// load time under the background policy, so that no batch call makes them).
+static void bg_open(Index &ix) {
+    Index::Background &b = ix.bg;
+    if (b.side) return;
+    PI_HIP(hipStreamCreateWithFlags(&b.side, hipStreamNonBlocking));
+    PI_HIP(hipEventCreateWithFlags(&b.ev_main, hipEventDisableTiming));
+    PI_HIP(hipEventCreateWithFlags(&b.ev_side, hipEventDisableTiming));
+    PI_HIP(hipHostMalloc(&b.h_cnt, 64 * sizeof(uint32_t), hipHostMallocDefault));
+}
+
 void bg_start(Index &ix, const DevState &latest, hipStream_t s) {
     Index::Background &b = ix.bg;
     if (b.phase != 0) return;
     const uint64_t first = ix.nbase + 2;
     if (latest.nused <= first) return;  // no new node to index
-    if (!b.side) {
-        PI_HIP(hipStreamCreateWithFlags(&b.side, hipStreamNonBlocking));
-        PI_HIP(hipEventCreateWithFlags(&b.ev_main, hipEventDisableTiming));
-        PI_HIP(hipEventCreateWithFlags(&b.ev_side, hipEventDisableTiming));
-        PI_HIP(hipHostMalloc(&b.h_cnt, 64 * sizeof(uint32_t), hipHostMallocDefault));
-    }
+    bg_open(ix);
     b.first = first;
     b.snap = latest.nused;
     b.changes_at = latest.changes;
@@ -260,6 +266,7 @@ void bg_release(Index &ix) {
 
 void bg_reserve(Index &ix) {
     if (ix.cfg.rebuild_policy != PI_REBUILD_BACKGROUND) return;
+    bg_open(ix);
     Index::Background &b = ix.bg;
     const uint64_t cap = std::max<uint64_t>(ix.st.cap, 1);
     b.okeys.ensure(cap * 8);
