@@ -13,6 +13,7 @@ import argparse
 import hashlib
 import json
 import os
+import re
 import platform
 import sys
 import time
@@ -36,6 +37,14 @@ def _block_from(text, start):
     return text[i:j + 3]
 
 
+def _code_only(text):
+    """Source text without comments and with whitespace collapsed, so that a
+    comment edit does not count as a kernel change."""
+    text = re.sub(r"/\*.*?\*/", " ", text, flags=re.S)
+    text = re.sub(r"//[^\n]*", " ", text)
+    return " ".join(text.split())
+
+
 def kernel_source_hash():
     """Hash of the code the descent kernel is built and launched from: the
     device headers in full, and from batch.hip the kernel itself and its
@@ -43,13 +52,13 @@ def kernel_source_hash():
     csrc = os.path.join(ROOT, "paper_1601_00159_amd", "csrc")
     h = hashlib.sha256()
     for f in ("descent.h", "pi_internal.h", "index.h"):
-        with open(os.path.join(csrc, f), "rb") as fh:
-            h.update(fh.read())
+        with open(os.path.join(csrc, f)) as fh:
+            h.update(_code_only(fh.read()).encode())
     with open(os.path.join(csrc, "batch.hip")) as fh:
         b = fh.read()
-    h.update(_block_from(b, "template <int MODE, int QPL, int DT>\n__global__").encode())
+    h.update(_code_only(_block_from(b, "template <int MODE, int QPL, int DT>\n__global__")).encode())
     for name in ("launch_descend_q", "launch_descend_b", "launch_descend("):
-        h.update(_block_from(b, "void " + name).encode())
+        h.update(_code_only(_block_from(b, "void " + name)).encode())
     return h.hexdigest()[:16]
 
 

@@ -175,7 +175,7 @@ constexpr int WIN_DQ = 3;
 // Shared window of a whole wave.  On the upper global levels the 64 sorted
 // queries of a wave stand on the same few entries, yet the per-lane window
 // above costs seven vector loads that each pass all 64 lane addresses through
-// the texture addresser -- the unit that bounds the descent.  When every lane
+// the texture addresser, the busiest unit of the descent.  When every lane
 // stands within UW_SLACK entries of the first lane's entry w0, one load by 12
 // lanes fetches the wave's window instead: lanes 0..7 the 8 key pairs from the
 // even entry kb at or below w0+1, lanes 8..11 the 4 down quads from the
