@@ -80,6 +80,9 @@ struct pi_group {
     hipEvent_t ev = nullptr;
     hipEvent_t ev_start = nullptr, ev_fused = nullptr;  // fork/join of the fused launch
     hipStream_t fstream = nullptr;                      // the fused launch runs beside the large batches
+    static constexpr int LANES = 4;                     // streams the large batches are spread over
+    hipStream_t lane[LANES] = {};
+    hipEvent_t ev_fork = nullptr, ev_lane[LANES] = {};
     bool pending = false;
     bool lds_attr = false;
     uint32_t tuned_block = 0, tuned_lds = 0;  // descent shape the autotuner applied (0 = none)
@@ -206,12 +209,34 @@ void run_group(pi_group *g, pi_index *const *indices, const pi_batch *batches, u
         PI_LAUNCH_CHECK();
         PI_HIP(hipEventRecord(g->ev_fused, fs));
     }
-    // large batches: the GPU-wide path on the caller's stream
-    for (uint32_t i = 0; i < count; i++) {
-        const pi_batch &b = batches[i];
-        if (!b.n || b.n <= fused_max) continue;
-        execute_batch(indices[i]->ix, ops_override ? ops_override : b.d_ops, b.d_keys, b.d_values, b.n,
-                      b.d_out_values, b.d_out_status, s);
+    // large batches: the GPU-wide path, spread round-robin over the group's
+    // lane streams (the indices are disjoint, and one batch of a few hundred
+    // thousand queries does not fill the GPU), joined back into the caller's
+    // stream
+    uint32_t nlarge = 0;
+    for (uint32_t i = 0; i < count; i++) nlarge += batches[i].n > fused_max;
+    const int lanes = (int)std::min<uint32_t>(nlarge, pi_group::LANES);
+    if (lanes > 0) {
+        if (!g->ev_fork) {
+            PI_HIP(hipEventCreateWithFlags(&g->ev_fork, hipEventDisableTiming));
+            for (int k = 0; k < pi_group::LANES; k++) {
+                PI_HIP(hipStreamCreateWithFlags(&g->lane[k], hipStreamNonBlocking));
+                PI_HIP(hipEventCreateWithFlags(&g->ev_lane[k], hipEventDisableTiming));
+            }
+        }
+        PI_HIP(hipEventRecord(g->ev_fork, s));
+        for (int k = 0; k < lanes; k++) PI_HIP(hipStreamWaitEvent(g->lane[k], g->ev_fork, 0));
+        uint32_t r = 0;
+        for (uint32_t i = 0; i < count; i++) {
+            const pi_batch &b = batches[i];
+            if (!b.n || b.n <= fused_max) continue;
+            execute_batch(indices[i]->ix, ops_override ? ops_override : b.d_ops, b.d_keys, b.d_values, b.n,
+                          b.d_out_values, b.d_out_status, g->lane[r++ % lanes]);
+        }
+        for (int k = 0; k < lanes; k++) {
+            PI_HIP(hipEventRecord(g->ev_lane[k], g->lane[k]));
+            PI_HIP(hipStreamWaitEvent(s, g->ev_lane[k], 0));
+        }
     }
     if (!fused.empty()) PI_HIP(hipStreamWaitEvent(s, g->ev_fused, 0));
     // one copy of every index's counters
@@ -336,6 +361,14 @@ pi_status pi_group_destroy(pi_group *g) {
         (void)hipStreamSynchronize(g->fstream);
         (void)hipStreamDestroy(g->fstream);
     }
+    for (int k = 0; k < pi_group::LANES; k++) {
+        if (g->lane[k]) {
+            (void)hipStreamSynchronize(g->lane[k]);
+            (void)hipStreamDestroy(g->lane[k]);
+        }
+        if (g->ev_lane[k]) (void)hipEventDestroy(g->ev_lane[k]);
+    }
+    if (g->ev_fork) (void)hipEventDestroy(g->ev_fork);
     delete g;
     return PI_OK;
 }
