@@ -283,7 +283,8 @@ __global__ __launch_bounds__(OT) void k_own_apply(const uint64_t *__restrict__ s
                                                   const uint32_t *__restrict__ loc, uint64_t *__restrict__ sval,
                                                   uint8_t *__restrict__ smeta, uint64_t *__restrict__ out_vals,
                                                   uint8_t *__restrict__ out_status, uint32_t *__restrict__ newflag,
-                                                  int32_t *__restrict__ gw, DevState *st) {
+                                                  int32_t *__restrict__ gw, uint4 *__restrict__ part,
+                                                  const DevState *st) {
     if (st->b_writers == 0) return;
     __shared__ Seg s_w[ONW];
     const uint32_t base = blockIdx.x * OTILE + threadIdx.x * OI;
@@ -381,13 +382,26 @@ __global__ __launch_bounds__(OT) void k_own_apply(const uint64_t *__restrict__ s
         for (int e = 0; e < OI; e++)
             if (base + e < n) newflag[base + e] = nf4[e];
     }
+    // the tile's counts go to its own slot; the batch's end sums them (one
+    // atomic per wave on three shared counters cost more than the apply)
     hits = wave_sum_u32(hits);
     dels = wave_sum_u32(dels);
     revs = wave_sum_u32(revs);
+    __shared__ uint32_t s_c[3][ONW];
     if (lane_id() == 0) {
-        if (hits) atomicAdd(&st->b_hits, hits);
-        if (dels) atomicAdd(&st->b_deletes, dels);
-        if (revs) atomicAdd(&st->b_revives, revs);
+        s_c[0][threadIdx.x >> 6] = hits;
+        s_c[1][threadIdx.x >> 6] = dels;
+        s_c[2][threadIdx.x >> 6] = revs;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        uint4 c = make_uint4(0, 0, 0, 0);
+        for (int w = 0; w < ONW; w++) {
+            c.x += s_c[0][w];
+            c.y += s_c[1][w];
+            c.z += s_c[2][w];
+        }
+        part[blockIdx.x] = c;
     }
 }
 
@@ -434,7 +448,34 @@ __global__ void k_batch_begin(DevState *st, uint32_t n) {
     st->b_n = n;
 }
 
-__global__ void k_batch_end(DevState *st) {
+// Sums the apply tiles' counts (batches with updates; one 256-thread block),
+// then folds the batch into the cumulative counters.
+__global__ __launch_bounds__(256) void k_batch_end(DevState *st, const uint4 *__restrict__ part, uint32_t ntiles) {
+    __shared__ uint32_t s_c[3][4];
+    if (st->b_writers != 0) {
+        uint32_t h = 0, d = 0, r = 0;
+        for (uint32_t t = threadIdx.x; t < ntiles; t += 256) {
+            const uint4 c = part[t];
+            h += c.x;
+            d += c.y;
+            r += c.z;
+        }
+        h = wave_sum_u32(h);
+        d = wave_sum_u32(d);
+        r = wave_sum_u32(r);
+        if (lane_id() == 0) {
+            s_c[0][threadIdx.x >> 6] = h;
+            s_c[1][threadIdx.x >> 6] = d;
+            s_c[2][threadIdx.x >> 6] = r;
+        }
+        __syncthreads();
+        if (threadIdx.x == 0)
+            for (int w = 0; w < 4; w++) {
+                st->b_hits += s_c[0][w];
+                st->b_deletes += s_c[1][w];
+                st->b_revives += s_c[2][w];
+            }
+    }
     if (threadIdx.x != 0) return;
     const unsigned int nn = st->b_new;
     st->nused += nn;
@@ -535,6 +576,7 @@ void BatchWorkspace::ensure(uint64_t m) {
     gw.ensure(c * 4);
     const uint64_t nt = (c + OTILE - 1) / OTILE + 1;
     agg.ensure(nt * sizeof(Seg));
+    part.ensure(nt * sizeof(uint4));
     sop.ensure(c);
     svin.ensure(c * 8);
     nk.ensure(c * 8);
@@ -546,7 +588,7 @@ void BatchWorkspace::ensure(uint64_t m) {
 
 void BatchWorkspace::release() {
     DevBuf *all[] = {&res_val, &res_flags, &loc, &locnext, &newflag, &newpos, &gw, &agg,
-                     &carry, &nk, &nv, &npred, &npnext, &sop, &svin};
+                     &part, &nk, &nv, &npred, &npnext, &sop, &svin};
     for (DevBuf *b : all) b->release();
     n = 0;
 }
@@ -599,7 +641,7 @@ void execute_batch(Index &ix, const uint8_t *ops, const uint64_t *keys, const ui
                        w.svin.as<uint64_t>(), (uint32_t)n, agg,
                        w.res_val.as<uint64_t>(), w.res_flags.as<uint8_t>(), w.loc.as<uint32_t>(),
                        ix.st.val.as<uint64_t>(), ix.st.meta.as<uint8_t>(), out_vals, out_status,
-                       w.newflag.as<uint32_t>(), w.gw.as<int32_t>(), st);
+                       w.newflag.as<uint32_t>(), w.gw.as<int32_t>(), w.part.as<uint4>(), st);
     PI_LAUNCH_CHECK();
     mark(3);
     exclusive_scan_u32(ix.scanws, w.newflag.as<uint32_t>(), w.newpos.as<uint32_t>(), n, &st->b_new,
@@ -611,7 +653,7 @@ void execute_batch(Index &ix, const uint8_t *ops, const uint64_t *keys, const ui
     hipLaunchKernelGGL(k_link, dim3(blocks_for(n, 256)), dim3(256), 0, s, w.nk.as<uint64_t>(), w.nv.as<uint64_t>(),
                        w.npred.as<uint32_t>(), w.npnext.as<uint32_t>(), st, ix.st.key.as<uint64_t>(),
                        ix.st.val.as<uint64_t>(), ix.st.next.as<uint32_t>(), ix.st.meta.as<uint8_t>());
-    hipLaunchKernelGGL(k_batch_end, dim3(1), dim3(64), 0, s, st);
+    hipLaunchKernelGGL(k_batch_end, dim3(1), dim3(256), 0, s, st, (const uint4 *)w.part.as<uint4>(), otiles);
     PI_LAUNCH_CHECK();
     mark(4);
     if (ix.prof.on) {
@@ -713,7 +755,7 @@ std::vector<uint64_t> fingerprint(const Index &ix) {
     add(ix.scanws.tiles);
     const BatchWorkspace &w = ix.bws;
     add(w.res_val), add(w.res_flags), add(w.loc), add(w.locnext), add(w.newflag), add(w.newpos), add(w.gw);
-    add(w.agg), add(w.carry), add(w.nk), add(w.nv), add(w.npred), add(w.npnext), add(w.sop), add(w.svin);
+    add(w.agg), add(w.part), add(w.nk), add(w.nv), add(w.npred), add(w.npnext), add(w.sop), add(w.svin);
     for (const DevBuf &b : ix.stage) add(b);
     f.push_back((uint64_t)(uintptr_t)ix.dstate);
     const uint64_t *d = reinterpret_cast<const uint64_t *>(&ix.desc);

@@ -24,7 +24,8 @@ struct Storage {
 };
 
 struct BatchWorkspace {
-    DevBuf res_val, res_flags, loc, locnext, newflag, newpos, gw, agg, carry;
+    DevBuf res_val, res_flags, loc, locnext, newflag, newpos, gw, agg;
+    DevBuf part;       // per apply tile: hits, deletes, revives (summed at the batch's end)
     DevBuf nk, nv, npred, npnext;
     DevBuf sop, svin;  // op and inserted value of each sorted query (batches with updates)
     uint64_t n = 0;

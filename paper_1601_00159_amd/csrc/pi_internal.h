@@ -46,7 +46,8 @@ struct DevState {
     // cumulative
     unsigned long long batches, queries, hits, invalid, new_nodes, deletes, revives;
     // current batch
-    unsigned int b_writers, b_new, b_deletes, b_revives, b_hits, b_invalid;
+    unsigned int b_writers;      // nonzero: the batch has INSERT/DELETE queries
+    unsigned int b_new, b_deletes, b_revives, b_hits, b_invalid;
     unsigned int b_n;
     unsigned int b_pad;          // padding queries of a graph replay (not counted)
     unsigned int errors;         // internal consistency failures (must stay 0)
@@ -184,8 +185,9 @@ struct SortWorkspace {
     void release();
 };
 // Stable LSD radix sort of keys (payload = input position).  When ops is not
-// null, keys whose op is > 2 sort as KEY_MAX, and b_writers of st counts the
-// valid INSERT/DELETE queries.  Returns pointers into the workspace.
+// null, keys whose op is > 2 sort as KEY_MAX, and b_writers of st is set
+// (nonzero) when there is a valid INSERT/DELETE query.  Returns pointers into
+// the workspace.
 void sort_keys_with_index(SortWorkspace &ws, const uint64_t *keys, const uint8_t *ops, uint64_t n,
                           DevState *st, hipStream_t s, const uint64_t **out_keys,
                           const uint32_t **out_idx);
@@ -207,7 +209,8 @@ void sort_batch_by_range(SortWorkspace &ws, MsdWorkspace &mw, const uint64_t *ke
 // One stable 8-bit LSD pass (hist, column scan, scatter).  The digit is
 // (key >> shift) & 255, or, when map is not null, (range_pos(key) >> shift)
 // & 255.  idx_in null = input positions; ops not null = keys whose op is
-// invalid count as KEY_MAX, and st->b_writers counts INSERT/DELETE queries.
+// invalid count as KEY_MAX, and st->b_writers is set when there is an
+// INSERT/DELETE query.
 void radix_pass(SortWorkspace &ws, const uint64_t *kin, const uint32_t *iin, const uint8_t *ops, uint32_t n,
                 uint32_t shift, const RangeMap *map, DevState *st, uint64_t *kout, uint32_t *iout, hipStream_t s);
 

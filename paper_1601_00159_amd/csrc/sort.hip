@@ -71,12 +71,11 @@ __global__ __launch_bounds__(ST) void k_hist(const uint64_t *__restrict__ keys, 
             atomicAdd(&h[dg(k)], 1u);
         }
     }
-    __syncthreads();
+    // b_writers is a flag (nonzero: the batch has INSERT/DELETE queries): one
+    // plain store per tile that has any, not an atomic per wave on one word
+    const int any = __syncthreads_or(writers != 0);
     if (tid < R) tile_hist[(size_t)tid * ntiles + blockIdx.x] = h[tid];
-    if (st) {
-        const uint32_t w = wave_sum_u32(writers);
-        if (lane_id() == 0 && w) atomicAdd(&st->b_writers, w);
-    }
+    if (st && any && tid == 0) st->b_writers = 1;
 }
 
 __global__ __launch_bounds__(CT) void k_colscan(uint32_t *__restrict__ tile_hist, uint32_t ntiles,
