@@ -82,3 +82,13 @@ def test_exact_model_equals_brute_force():
                                     rng.integers(0, 1 << 40, size=n_q - n_q // 2, dtype=np.uint64)]))
         got = BM.descent_bytes(sk, q, lds_from=lds_from)
         assert got["bytes"] == _brute_force_bytes(sk, q, lds_from), (n_keys, n_q, lds_from)
+
+
+def test_traffic_summary_matches_the_descent_source():
+    """The committed counter summary of the descent was taken on the kernel
+    as it stands (the bench reports `traffic` only then); comments and white
+    space do not count as a change."""
+    import bench
+
+    assert bench._code_only("a; // x\n/* y\n z */  b;") == "a; b;"
+    assert bench.load_traffic("search-2^26-uniform") is not None
