@@ -282,9 +282,12 @@ pi_status pi_group_config_default(pi_group_config *cfg);
 pi_status pi_group_create(const pi_group_config *cfg, pi_group **out);
 /* Waits for the group's last call, then frees it (NULL ok). */
 pi_status pi_group_destroy(pi_group *g);
-/* Runs batches[i] on indices[i] for i < count, asynchronously on the stream.
- * The indices must be distinct, live on one device and not be used by other
- * calls until this one completes.  Errors: PI_ERR_INVALID_ARG (NULL pointers,
+/* Runs batches[i] on indices[i] for i < count, asynchronously on the stream:
+ * batches of at most fused_max queries in one persistent fused launch on a
+ * stream of the group's own, the others on the multi-kernel path spread over
+ * four lane streams of the group; all of it is joined back into the caller's
+ * stream.  The indices must be distinct, live on one device and not be used
+ * by other calls until this one completes.  Errors: PI_ERR_INVALID_ARG (NULL pointers,
  * count above max_indices, a repeated index, mixed devices, n above 2^31 - 1),
  * PI_ERR_CAPACITY (an index with a fixed capacity has no room; nothing is
  * enqueued). */
