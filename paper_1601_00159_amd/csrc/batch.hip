@@ -413,13 +413,14 @@ __global__ void k_new_gather(const uint64_t *__restrict__ sk, const uint64_t *__
                              const DevState *st, uint64_t *__restrict__ nk, uint64_t *__restrict__ nv,
                              uint32_t *__restrict__ npred, uint32_t *__restrict__ npnext) {
     if (st->b_writers == 0) return;
-    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n || !newflag[i]) return;
-    const uint32_t r = newpos[i];
-    nk[r] = sk[i];
-    nv[r] = svin[gw[i]];
-    npred[r] = loc[i];
-    npnext[r] = locnext[i];
+    for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+        if (!newflag[i]) continue;
+        const uint32_t r = newpos[i];
+        nk[r] = sk[i];
+        nv[r] = svin[gw[i]];
+        npred[r] = loc[i];
+        npnext[r] = locnext[i];
+    }
 }
 
 // writes the new nodes and links them (Algorithm 4 insertNode)
@@ -428,17 +429,19 @@ __global__ void k_link(const uint64_t *__restrict__ nk, const uint64_t *__restri
                        uint64_t *__restrict__ skey, uint64_t *__restrict__ sval, uint32_t *__restrict__ snext,
                        uint8_t *__restrict__ smeta) {
     const uint32_t nnew = st->b_new;
-    const uint32_t r = blockIdx.x * blockDim.x + threadIdx.x;
-    if (r >= nnew) return;
-    const uint32_t slot = (uint32_t)st->nused + r;
-    const uint32_t pr = npred[r];
-    skey[slot] = nk[r];
-    sval[slot] = nv[r];
-    smeta[slot] = META_LINK;
-    snext[slot] = (r + 1 < nnew && npred[r + 1] == pr) ? slot + 1 : npnext[r];
-    if (r == 0 || npred[r - 1] != pr) {
-        snext[pr] = slot;
-        smeta[pr] = smeta[pr] | META_LINK;
+    if (nnew == 0) return;
+    const uint32_t first = (uint32_t)st->nused;
+    for (uint32_t r = blockIdx.x * blockDim.x + threadIdx.x; r < nnew; r += gridDim.x * blockDim.x) {
+        const uint32_t slot = first + r;
+        const uint32_t pr = npred[r];
+        skey[slot] = nk[r];
+        sval[slot] = nv[r];
+        smeta[slot] = META_LINK;
+        snext[slot] = (r + 1 < nnew && npred[r + 1] == pr) ? slot + 1 : npnext[r];
+        if (r == 0 || npred[r - 1] != pr) {
+            snext[pr] = slot;
+            smeta[pr] = smeta[pr] | META_LINK;
+        }
     }
 }
 
@@ -646,11 +649,14 @@ void execute_batch(Index &ix, const uint8_t *ops, const uint64_t *keys, const ui
     mark(3);
     exclusive_scan_u32(ix.scanws, w.newflag.as<uint32_t>(), w.newpos.as<uint32_t>(), n, &st->b_new,
                        &st->b_writers, s);
-    hipLaunchKernelGGL(k_new_gather, dim3(blocks_for(n, 256)), dim3(256), 0, s, sk, w.svin.as<uint64_t>(),
+    // grid-stride launches of at most 8 blocks per CU: batches without
+    // updates leave at once, and a smaller grid dispatches faster
+    const uint32_t lgrid = std::min<uint32_t>(blocks_for(n, 256), (uint32_t)ix.num_cus * 8);
+    hipLaunchKernelGGL(k_new_gather, dim3(lgrid), dim3(256), 0, s, sk, w.svin.as<uint64_t>(),
                        w.newflag.as<uint32_t>(), w.newpos.as<uint32_t>(), w.gw.as<int32_t>(), w.loc.as<uint32_t>(),
                        w.locnext.as<uint32_t>(), (uint32_t)n, st, w.nk.as<uint64_t>(), w.nv.as<uint64_t>(),
                        w.npred.as<uint32_t>(), w.npnext.as<uint32_t>());
-    hipLaunchKernelGGL(k_link, dim3(blocks_for(n, 256)), dim3(256), 0, s, w.nk.as<uint64_t>(), w.nv.as<uint64_t>(),
+    hipLaunchKernelGGL(k_link, dim3(lgrid), dim3(256), 0, s, w.nk.as<uint64_t>(), w.nv.as<uint64_t>(),
                        w.npred.as<uint32_t>(), w.npnext.as<uint32_t>(), st, ix.st.key.as<uint64_t>(),
                        ix.st.val.as<uint64_t>(), ix.st.next.as<uint32_t>(), ix.st.meta.as<uint8_t>());
     hipLaunchKernelGGL(k_batch_end, dim3(1), dim3(256), 0, s, st, (const uint4 *)w.part.as<uint4>(), otiles);
