@@ -75,10 +75,51 @@ def load_traffic(workload_name):
     return d.get("bytes_per_launch")
 
 
+def cpu_model():
+    """The host CPU's model name (from /proc/cpuinfo), else the machine type."""
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return platform.processor() or platform.machine()
+
+
+class OneCore:
+    """Pins this process to one core of those it may use for the duration of
+    the CPU-baseline leg (the oracle is single-threaded), then restores the
+    affinity."""
+
+    def __enter__(self):
+        self.prev = os.sched_getaffinity(0)
+        self.core = min(self.prev)
+        os.sched_setaffinity(0, {self.core})
+        return self
+
+    def __exit__(self, *a):
+        os.sched_setaffinity(0, self.prev)
+
+
+def oracle_rate(orc, b, limit, budget_s, chunk):
+    """Queries per second of the oracle over the first `limit` queries of
+    batch b, in chunks until `budget_s` seconds of work; each chunk is timed
+    by the oracle itself (monotonic clock around its loop)."""
+    done, elapsed_ns = 0, 0
+    while done < min(limit, len(b)) and elapsed_ns < budget_s * 1e9:
+        s_ = slice(done, done + chunk)
+        _, _, ns = orc.execute_batch_timed(b.ops[s_], b.keys[s_], b.vals[s_])
+        elapsed_ns += ns
+        done += b.ops[s_].size
+    return done, elapsed_ns / 1e9
+
+
 def cpu_baseline(w, sample_queries, budget_s=12.0):
     """The CPU oracle (single-threaded Pugh skip list) on a bounded sample of
     the same workload: the full index, the first `sample_queries` queries of
-    the first timed batch, in chunks until `budget_s` seconds of work."""
+    the first timed batch, in chunks until `budget_s` seconds of work, on one
+    pinned core."""
     import numpy as np
 
     from oracle.skiplist import SkipList
@@ -90,20 +131,13 @@ def cpu_baseline(w, sample_queries, budget_s=12.0):
     orc = SkipList()
     orc.bulk_load_sorted(sk, sv)
     log(f"oracle built in {time.perf_counter() - t0:.1f}s")
-    b = w.batches[0]
-    done, elapsed = 0, 0.0
-    chunk = 1 << 18
-    while done < min(sample_queries, len(b)) and elapsed < budget_s:
-        s = slice(done, done + chunk)
-        t = time.perf_counter()
-        orc.execute_batch(b.ops[s], b.keys[s], b.vals[s])
-        elapsed += time.perf_counter() - t
-        done += b.ops[s].size
+    with OneCore() as pin:
+        done, elapsed = oracle_rate(orc, w.batches[0], sample_queries, budget_s, 1 << 18)
     orc.close()
     return {"value": done / elapsed / 1e6, "unit": "Mqueries/s", "cores": 1, "kind": "oracle",
             "sample": f"{done} SEARCH queries of one batch against the full {w.load_keys.size}-key index "
-                      f"(single-threaded Pugh skip list, {elapsed:.1f}s timed; host {platform.processor() or platform.machine()}, "
-                      f"{os.cpu_count()} logical CPUs)"}
+                      f"(single-threaded Pugh skip list pinned to core {pin.core}, {elapsed:.1f}s timed inside "
+                      f"the oracle; host CPU {cpu_model()}, {os.cpu_count()} logical CPUs)"}
 
 
 def run_range(args):
@@ -206,9 +240,36 @@ def range_cpu_baseline(w, orc, budget_s=8.0):
                       f"(single-threaded Pugh skip list, {elapsed:.1f}s timed)"}
 
 
+def write_oracle_replay(w):
+    """Starts the CPU oracle's replay of every batch of the write workload in
+    a thread of its own (its ctypes calls release the interpreter lock): the
+    last batch's answers and the final set check the GPU run.  Returns a
+    future of (last answers, final keys, final values)."""
+    import concurrent.futures as cf
+
+    import numpy as np
+
+    from oracle.skiplist import SkipList
+
+    def replay():
+        order = np.argsort(w.load_keys, kind="stable")
+        orc = SkipList()
+        orc.bulk_load_sorted(w.load_keys[order], w.load_vals[order])
+        last = None
+        for i, b in enumerate(w.batches):
+            last = orc.execute_batch(b.ops, b.keys, b.vals)
+            log(f"oracle replay: batch {i + 1} of {len(w.batches)}")
+        k, v = orc.export()
+        orc.close()
+        return last, k, v
+
+    return cf.ThreadPoolExecutor(1).submit(replay)
+
+
 def write_cpu_baseline(w, budget_s=10.0):
     """The CPU oracle on the write-heavy workload: the full index, the first
-    batch's queries in arrival order, in chunks until budget_s seconds."""
+    batch's queries in arrival order, in chunks until budget_s seconds, on one
+    pinned core."""
     import numpy as np
 
     from oracle.skiplist import SkipList
@@ -216,18 +277,13 @@ def write_cpu_baseline(w, budget_s=10.0):
     order = np.argsort(w.load_keys, kind="stable")
     orc = SkipList()
     orc.bulk_load_sorted(w.load_keys[order], w.load_vals[order])
-    b = w.batches[0]
-    done, elapsed, chunk = 0, 0.0, 1 << 16
-    while done < len(b) and elapsed < budget_s:
-        s_ = slice(done, done + chunk)
-        t = time.perf_counter()
-        orc.execute_batch(b.ops[s_], b.keys[s_], b.vals[s_])
-        elapsed += time.perf_counter() - t
-        done += b.ops[s_].size
+    with OneCore() as pin:
+        done, elapsed = oracle_rate(orc, w.batches[0], len(w.batches[0]), budget_s, 1 << 16)
     orc.close()
     return {"value": round(done / elapsed / 1e6, 4), "unit": "Mqueries/s", "cores": 1, "kind": "oracle",
             "sample": f"{done} queries (40/50/10 S/I/D, Zipf 0.99) of one batch against the full "
-                      f"{w.load_keys.size}-key index (single-threaded Pugh skip list, {elapsed:.1f}s timed)"}
+                      f"{w.load_keys.size}-key index (single-threaded Pugh skip list pinned to core {pin.core}, "
+                      f"{elapsed:.1f}s timed inside the oracle; host CPU {cpu_model()})"}
 
 
 def run_write(args):

@@ -231,7 +231,14 @@ pi_status pi_range_collect(pi_index *idx, const uint64_t *d_lo, const uint64_t *
  * micro-batch, *n_batches of them.  Returns when every query is answered
  * (synchronises the stream).  Errors: PI_ERR_INVALID_ARG for NULL pointers,
  * a wrong struct_size, max_batch above 2^31 - 1, max_inflight above 64 or
- * decreasing arrival times. */
+ * decreasing arrival times; PI_ERR_CAPACITY when the index has a fixed
+ * capacity_hint and the stream's INSERT queries could need more slots than
+ * are free at the start.  These are checked before the first micro-batch and
+ * leave the index unchanged.  An error met later (storage growth failing with
+ * PI_ERR_OUT_OF_MEMORY, PI_ERR_DEVICE) stops the loop between micro-batches:
+ * the micro-batches before it took effect, *n_batches and h_batch_end
+ * describe them and their answers and h_done_us are written; no query after
+ * them was applied. */
 typedef struct {
     uint32_t struct_size;   /* sizeof(pi_serve_config) */
     uint32_t max_inflight;  /* micro-batches on the device at once (0 = 1: the host's ~26 launches per
@@ -345,6 +352,13 @@ pi_status pi_debug_level(pi_index *idx, uint32_t level, uint64_t *d_keys, uint32
  * workspace. */
 pi_status pi_debug_sort(pi_index *idx, const uint64_t *d_keys, uint64_t n,
                         uint64_t *d_sorted_keys, uint32_t *d_perm, pi_stream stream);
+
+/* Test hook: sets the host's upper bound on the storage slots in use, the
+ * bound that decides whether a batch needs room checked before it is
+ * enqueued.  A bound below the truth must never let a batch write past the
+ * capacity: the kernels then drop that batch's new nodes, and the next call
+ * that reads the counters fails the handle with PI_ERR_DEVICE.  Tests only. */
+pi_status pi_debug_set_storage_bound(pi_index *idx, uint64_t used_upper);
 
 #ifdef __cplusplus
 }

@@ -28,9 +28,11 @@
  * A test hook lets a caller force the height of an inserted key; it exists
  * only to reproduce hand-worked examples whose heights are given.
  */
+#define _POSIX_C_SOURCE 199309L
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
+#include <time.h>
 
 #define ORC_MAX_LEVELS 64
 
@@ -51,6 +53,9 @@ typedef struct orc_list {
     uint64_t seed;
     uint64_t size;
     int32_t forced_height; /* 0 = use the rule; test hook */
+    /* a planted structural fault (test hook, see orc_debug_plant) */
+    int32_t plant;
+    orc_node *pa, *pb;
 } orc_list;
 
 /* ---------------------------------------------------------------- heights */
@@ -115,9 +120,12 @@ orc_list *orc_create(int32_t max_height, int32_t log2_inv_p, uint64_t seed)
     return s;
 }
 
+void orc_debug_restore(orc_list *s);
+
 void orc_destroy(orc_list *s)
 {
     if (!s) return;
+    if (s->plant) orc_debug_restore(s);
     orc_node *n = s->head->fwd[0];
     while (n) {
         orc_node *nx = n->fwd[0];
@@ -233,6 +241,19 @@ int32_t orc_execute_batch(orc_list *s, const uint8_t *ops, const uint64_t *keys,
 /* Bulk load = inserting the pairs in array order into an empty list, so the
  * last occurrence of a duplicated key wins.  Returns 0, -1 on allocation
  * failure, -2 if the list is not empty. */
+/* orc_execute_batch timed with the monotonic clock around the whole loop
+ * (the CPU baseline of the benchmark): *elapsed_ns receives the time. */
+int32_t orc_execute_batch_timed(orc_list *s, const uint8_t *ops, const uint64_t *keys, const uint64_t *vals,
+                                uint64_t n, uint64_t *out_vals, uint8_t *out_status, uint64_t *elapsed_ns)
+{
+    struct timespec a, b;
+    clock_gettime(CLOCK_MONOTONIC, &a);
+    const int32_t r = orc_execute_batch(s, ops, keys, vals, n, out_vals, out_status);
+    clock_gettime(CLOCK_MONOTONIC, &b);
+    *elapsed_ns = (uint64_t)(b.tv_sec - a.tv_sec) * UINT64_C(1000000000) + (uint64_t)b.tv_nsec - (uint64_t)a.tv_nsec;
+    return r;
+}
+
 int32_t orc_bulk_load(orc_list *s, const uint64_t *keys, const uint64_t *vals, uint64_t n)
 {
     if (s->size != 0) return -2;
@@ -281,7 +302,7 @@ uint64_t orc_export(const orc_list *s, uint64_t *keys, uint64_t *vals, uint64_t 
     return i;
 }
 
-/* Range search (the paper's range query of Section 4.3, SEARCH only): the
+/* Range search (the paper's range query of Section 3.2.5, SEARCH only): the
  * pairs with lo <= key <= hi, in key order -- the descent to the first key
  * >= lo, then the storage-level walk until a key passes hi.  Writes at most
  * cap of them and returns how many there are (none when lo > hi). */
@@ -375,4 +396,71 @@ int32_t orc_check(const orc_list *s)
         }
     }
     return 0;
+}
+
+/* ------------------------------------------------------------ test hooks */
+
+/* Plants one structural fault so that the tests can show orc_check rejects
+ * it (test infrastructure only); orc_debug_restore undoes it:
+ *   1  two adjacent nodes of height 1 swap keys: level 1 is out of order
+ *      (check code 1)
+ *   2  the first node of height >= 2 is unlinked from level 1 only, the size
+ *      adjusted: a level-2 key is missing one level below (code 2)
+ *   3  the recorded height of the first height-1 node is raised by one: it
+ *      differs from the height rule (code 3)
+ *   4  the size is off by one (code 4)
+ * Returns 0 when planted, -1 when no node fits or a fault is already
+ * planted. */
+int32_t orc_debug_plant(orc_list *s, int32_t kind)
+{
+    if (s->plant) return -1;
+    orc_node *prev = s->head;
+    for (orc_node *n = s->head->fwd[0]; n; prev = n, n = n->fwd[0]) {
+        if (kind == 1 && n->height == 1 && n->fwd[0] && n->fwd[0]->height == 1) {
+            const uint64_t k = n->key;
+            n->key = n->fwd[0]->key;
+            n->fwd[0]->key = k;
+            s->pa = n;
+            s->plant = 1;
+            return 0;
+        }
+        if (kind == 2 && n->height >= 2) {
+            prev->fwd[0] = n->fwd[0];
+            s->size--;
+            s->pa = prev;
+            s->pb = n;
+            s->plant = 2;
+            return 0;
+        }
+        if (kind == 3 && n->height == 1) {
+            n->height = 2;
+            s->pa = n;
+            s->plant = 3;
+            return 0;
+        }
+    }
+    if (kind == 4) {
+        s->size++;
+        s->plant = 4;
+        return 0;
+    }
+    return -1;
+}
+
+void orc_debug_restore(orc_list *s)
+{
+    if (s->plant == 1) {
+        const uint64_t k = s->pa->key;
+        s->pa->key = s->pa->fwd[0]->key;
+        s->pa->fwd[0]->key = k;
+    } else if (s->plant == 2) {
+        s->pa->fwd[0] = s->pb;
+        s->size++;
+    } else if (s->plant == 3) {
+        s->pa->height = 1;
+    } else if (s->plant == 4) {
+        s->size--;
+    }
+    s->plant = 0;
+    s->pa = s->pb = NULL;
 }

@@ -47,6 +47,8 @@ def _load():
     lib.orc_erase.argtypes = [vp, u64, ctypes.POINTER(u64)]
     lib.orc_execute_batch.restype = i32
     lib.orc_execute_batch.argtypes = [vp, vp, vp, vp, u64, vp, vp]
+    lib.orc_execute_batch_timed.restype = i32
+    lib.orc_execute_batch_timed.argtypes = [vp, vp, vp, vp, u64, vp, vp, ctypes.POINTER(u64)]
     lib.orc_bulk_load.restype = i32
     lib.orc_bulk_load.argtypes = [vp, vp, vp, u64]
     lib.orc_bulk_load_sorted.restype = i32
@@ -63,6 +65,9 @@ def _load():
     lib.orc_range_batch.argtypes = [vp, vp, vp, u64, vp, vp, vp, u64]
     lib.orc_check.restype = i32
     lib.orc_check.argtypes = [vp]
+    lib.orc_debug_plant.restype = i32
+    lib.orc_debug_plant.argtypes = [vp, i32]
+    lib.orc_debug_restore.argtypes = [vp]
     _lib = lib
     return lib
 
@@ -143,6 +148,22 @@ class SkipList:
             raise MemoryError
         return out_v, out_s
 
+    def execute_batch_timed(self, ops, keys, vals):
+        """execute_batch, plus the nanoseconds the C loop took (monotonic
+        clock read inside the library)."""
+        ops = np.ascontiguousarray(ops, dtype=np.uint8)
+        keys = np.ascontiguousarray(keys, dtype=np.uint64)
+        vals = np.ascontiguousarray(vals, dtype=np.uint64)
+        n = ops.size
+        out_v = np.zeros(n, dtype=np.uint64)
+        out_s = np.zeros(n, dtype=np.uint8)
+        ns = ctypes.c_uint64()
+        r = self._lib.orc_execute_batch_timed(self._h, _ptr(ops), _ptr(keys), _ptr(vals), n, _ptr(out_v),
+                                              _ptr(out_s), ctypes.byref(ns))
+        if r != 0:
+            raise MemoryError
+        return out_v, out_s, int(ns.value)
+
     def bulk_load(self, keys, vals):
         keys = np.ascontiguousarray(keys, dtype=np.uint64)
         vals = np.ascontiguousarray(vals, dtype=np.uint64)
@@ -199,3 +220,11 @@ class SkipList:
 
     def check(self) -> int:
         return int(self._lib.orc_check(self._h))
+
+    def plant(self, kind: int) -> int:
+        """Test hook: plants a structural fault (see orc_debug_plant)."""
+        return int(self._lib.orc_debug_plant(self._h, kind))
+
+    def restore(self):
+        """Test hook: undoes the planted fault."""
+        self._lib.orc_debug_restore(self._h)

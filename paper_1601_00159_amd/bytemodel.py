@@ -143,3 +143,21 @@ def descent_bytes(sorted_keys, queries_sorted, lds_from=None, seed=0x9E3779B97F4
     return {"bytes": int(total), "per_query": total / max(nq, 1), "index_lines": int(index_lines),
             "storage_key_lines": int(storage_lines), "value_lines": int(value_lines),
             "lds_bytes": int(lds_bytes), "io_bytes": int(io), "queries": int(nq), "top": int(top)}
+
+
+# Reference bytes per query of the parts of a batch outside the descent: the
+# ordering step as a two-pass key-range partition that reads each query's key
+# and op twice (2 x 9 B), writes the ordered key, position and op (13 B) which
+# the descent reads back (13 B), and the answers written in arrival order
+# (value and status, 9 B).
+PARTITION_BYTES_PER_QUERY = 2 * (8 + 1) + (8 + 4 + 1) + (8 + 4 + 1)
+ANSWER_BYTES_PER_QUERY = 8 + 1
+
+
+def batch_bytes(descent, n_queries):
+    """Algorithmic bytes of one whole batch (ordering, descent, answers) from
+    a ``descent_bytes`` result: its index, storage and value lines (and the
+    LDS-staged levels), plus the reference ordering and answer bytes in place
+    of the descent's own input and output terms."""
+    return int(descent["bytes"] - descent["io_bytes"] +
+               n_queries * (PARTITION_BYTES_PER_QUERY + ANSWER_BYTES_PER_QUERY))

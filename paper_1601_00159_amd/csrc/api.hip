@@ -129,31 +129,38 @@ void release_all(pi::Index &ix) {
 // dry because of it.
 void maybe_rebuild(pi::Index &ix, hipStream_t s) {
     const uint32_t pol = ix.cfg.rebuild_policy;
-    if (pol != PI_REBUILD_THRESHOLD && pol != PI_REBUILD_BACKGROUND) {
-        ix.ring_seen = ix.ring_head;
-        return;
-    }
+    // only the threshold and background policies decide from the counters;
+    // the others read the copies that have landed (device errors, the
+    // storage bound) and never wait for one
+    const bool decides = pol == PI_REBUILD_THRESHOLD || pol == PI_REBUILD_BACKGROUND;
     if (pol == PI_REBUILD_BACKGROUND) pi::bg_advance(ix);
     bool have = false;
     pi::DevState latest{};
+    uint64_t latest_enq = 0;
     while (ix.ring_seen < ix.ring_head) {
         const int slot = (int)(ix.ring_seen % pi::Index::STATE_RING);
-        if (ix.ring_head - ix.ring_seen >= (uint64_t)pi::Index::STATE_RING) {
+        const bool full = ix.ring_head - ix.ring_seen >= (uint64_t)pi::Index::STATE_RING;
+        if (full && decides) {
             PI_HIP(hipEventSynchronize(ix.ev_ring[slot]));
         } else if (hipEventQuery(ix.ev_ring[slot]) != hipSuccess) {
             (void)hipGetLastError();
+            if (full) {  // the slot is about to be reused: drop the copy unread
+                ix.ring_seen++;
+                continue;
+            }
             break;
         }
         latest = ix.hring[slot];
+        latest_enq = ix.ring_enq[slot];
         have = true;
         ix.ring_seen++;
+        if (latest.errors) throw pi::Error{PI_ERR_DEVICE, pi::device_error_text(latest.errors)};
     }
     if (!have) return;
-    // a tighter bound on the storage in use: the newest counters plus the
-    // queries of the batches queued after them
-    uint64_t queued = 0;
-    for (uint64_t k = ix.ring_seen; k < ix.ring_head; k++) queued += ix.ring_n[k % pi::Index::STATE_RING];
-    ix.used_upper = std::min<uint64_t>(ix.used_upper, latest.nused + queued);
+    // a tighter bound on the storage in use: the counters of the copy plus
+    // every query enqueued on the index after it, whatever path took them
+    ix.used_upper = std::min<uint64_t>(ix.used_upper, latest.nused + (ix.enq_queries - latest_enq));
+    if (!decides) return;
     const double thr = pi::rebuild_threshold(ix);
     if (pol == PI_REBUILD_THRESHOLD) {
         if ((double)latest.changes >= thr) {
@@ -176,9 +183,9 @@ void maybe_rebuild(pi::Index &ix, hipStream_t s) {
 }
 
 // Queues the copy of the counters after a batch.
-void push_state(pi::Index &ix, uint64_t n, hipStream_t s) {
+void push_state(pi::Index &ix, hipStream_t s) {
     const int slot = (int)(ix.ring_head % pi::Index::STATE_RING);
-    ix.ring_n[slot] = n;
+    ix.ring_enq[slot] = ix.enq_queries;
     PI_HIP(hipMemcpyAsync(ix.hring + slot, ix.dstate, sizeof(pi::DevState), hipMemcpyDeviceToHost, s));
     PI_HIP(hipEventRecord(ix.ev_ring[slot], s));
     ix.ring_head++;
@@ -352,7 +359,8 @@ void batch_step(pi::Index &ix, const uint8_t *d_ops, const uint64_t *d_keys, con
     else
         pi::execute_batch(ix, d_ops, d_keys, d_values, n, d_out_values, d_out_status, s);
     ix.used_upper = std::min<uint64_t>(ix.used_upper + n, ~0ull);
-    push_state(ix, n, s);
+    ix.enq_queries += n;
+    push_state(ix, s);
     if (ix.cfg.rebuild_policy == PI_REBUILD_ALWAYS) {
         pi::DevState cur;
         pi::read_state(ix, s, &cur);
@@ -390,16 +398,28 @@ pi_status pi_serve(pi_index *h, const pi_serve_config *cfg, const double *h_arri
             if (!(h_arrival_us[i] >= h_arrival_us[i - 1]))
                 return fail(ix, PI_ERR_INVALID_ARG, "arrival times must be non-decreasing");
         hipStream_t s = (hipStream_t)stream;
+        if (ix.cfg.capacity_hint) {
+            // a fixed capacity must hold every insert of the stream: checked
+            // before the first micro-batch, so this error leaves the index
+            // unchanged
+            pi::DevState cur;
+            pi::read_state(ix, s, &cur);
+            if (cur.nused + n > ix.st.cap) {
+                const uint64_t ins = pi::count_inserts(ix, d_ops, d_keys, n, s);
+                if (cur.nused + ins > ix.st.cap)
+                    return fail(ix, PI_ERR_CAPACITY, "the stream's inserts do not fit the fixed capacity");
+            }
+        }
         pi::ServePlan plan;
         plan.deadline_us = cfg->deadline_us;
         plan.max_inflight = cfg->max_inflight ? cfg->max_inflight : 1;
         plan.max_batch = cfg->max_batch ? cfg->max_batch : pi::serve_batch_limit(plan.max_inflight);
-        *n_batches = pi::serve_loop(
+        pi::serve_loop(
             h_arrival_us, n, plan, s,
             [&](uint64_t b, uint64_t e) {
                 batch_step(ix, d_ops + b, d_keys + b, d_values + b, e - b, d_out_values + b, d_out_status + b, s);
             },
-            h_done_us, h_batch_end);
+            h_done_us, h_batch_end, *n_batches);
         return PI_OK;
     });
 }
@@ -523,6 +543,13 @@ pi_status pi_debug_level(pi_index *h, uint32_t level, uint64_t *d_keys, uint32_t
         PI_HIP(hipStreamSynchronize(s));
         return PI_OK;
     });
+}
+
+pi_status pi_debug_set_storage_bound(pi_index *h, uint64_t used_upper) {
+    return guarded(h, [&](pi::Index &ix) -> pi_status {
+        ix.used_upper = used_upper;
+        return PI_OK;
+    }, true);
 }
 
 pi_status pi_debug_sort(pi_index *h, const uint64_t *d_keys, uint64_t n, uint64_t *d_sorted_keys, uint32_t *d_perm,

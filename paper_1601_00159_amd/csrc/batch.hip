@@ -423,13 +423,17 @@ __global__ void k_new_gather(const uint64_t *__restrict__ sk, const uint64_t *__
     }
 }
 
-// writes the new nodes and links them (Algorithm 4 insertNode)
+// writes the new nodes and links them (Algorithm 4 insertNode).  The host
+// reserves room for every batch before it is enqueued; should that ever fail,
+// nothing is written past the capacity: the batch's new nodes are dropped
+// (k_batch_end flags ERR_CAPACITY, which fails the handle).
 __global__ void k_link(const uint64_t *__restrict__ nk, const uint64_t *__restrict__ nv,
                        const uint32_t *__restrict__ npred, const uint32_t *__restrict__ npnext, DevState *st,
-                       uint64_t *__restrict__ skey, uint64_t *__restrict__ sval, uint32_t *__restrict__ snext,
-                       uint8_t *__restrict__ smeta) {
+                       uint64_t cap, uint64_t *__restrict__ skey, uint64_t *__restrict__ sval,
+                       uint32_t *__restrict__ snext, uint8_t *__restrict__ smeta) {
     const uint32_t nnew = st->b_new;
     if (nnew == 0) return;
+    if (st->nused + nnew > cap) return;
     const uint32_t first = (uint32_t)st->nused;
     for (uint32_t r = blockIdx.x * blockDim.x + threadIdx.x; r < nnew; r += gridDim.x * blockDim.x) {
         const uint32_t slot = first + r;
@@ -453,7 +457,8 @@ __global__ void k_batch_begin(DevState *st, uint32_t n) {
 
 // Sums the apply tiles' counts (batches with updates; one 256-thread block),
 // then folds the batch into the cumulative counters.
-__global__ __launch_bounds__(256) void k_batch_end(DevState *st, const uint4 *__restrict__ part, uint32_t ntiles) {
+__global__ __launch_bounds__(256) void k_batch_end(DevState *st, const uint4 *__restrict__ part, uint32_t ntiles,
+                                                   uint64_t cap) {
     __shared__ uint32_t s_c[3][4];
     if (st->b_writers != 0) {
         uint32_t h = 0, d = 0, r = 0;
@@ -480,7 +485,11 @@ __global__ __launch_bounds__(256) void k_batch_end(DevState *st, const uint4 *__
             }
     }
     if (threadIdx.x != 0) return;
-    const unsigned int nn = st->b_new;
+    unsigned int nn = st->b_new;
+    if (st->nused + nn > cap) {  // k_link wrote nothing
+        st->errors |= ERR_CAPACITY;
+        nn = 0;
+    }
     st->nused += nn;
     st->n_live = st->n_live + nn + st->b_revives - st->b_deletes;
     st->changes += nn + st->b_deletes;
@@ -657,9 +666,10 @@ void execute_batch(Index &ix, const uint8_t *ops, const uint64_t *keys, const ui
                        w.locnext.as<uint32_t>(), (uint32_t)n, st, w.nk.as<uint64_t>(), w.nv.as<uint64_t>(),
                        w.npred.as<uint32_t>(), w.npnext.as<uint32_t>());
     hipLaunchKernelGGL(k_link, dim3(lgrid), dim3(256), 0, s, w.nk.as<uint64_t>(), w.nv.as<uint64_t>(),
-                       w.npred.as<uint32_t>(), w.npnext.as<uint32_t>(), st, ix.st.key.as<uint64_t>(),
+                       w.npred.as<uint32_t>(), w.npnext.as<uint32_t>(), st, ix.st.cap, ix.st.key.as<uint64_t>(),
                        ix.st.val.as<uint64_t>(), ix.st.next.as<uint32_t>(), ix.st.meta.as<uint8_t>());
-    hipLaunchKernelGGL(k_batch_end, dim3(1), dim3(256), 0, s, st, (const uint4 *)w.part.as<uint4>(), otiles);
+    hipLaunchKernelGGL(k_batch_end, dim3(1), dim3(256), 0, s, st, (const uint4 *)w.part.as<uint4>(), otiles,
+                       ix.st.cap);
     PI_LAUNCH_CHECK();
     mark(4);
     if (ix.prof.on) {

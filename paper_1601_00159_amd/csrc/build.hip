@@ -297,7 +297,7 @@ void read_state(Index &ix, hipStream_t s, DevState *out) {
     PI_HIP(hipStreamSynchronize(s));
     *out = *ix.hstate;
     ix.used_upper = out->nused;
-    if (out->errors) throw Error{PI_ERR_DEVICE, "internal error: storage walk exceeded its bound"};
+    if (out->errors) throw Error{PI_ERR_DEVICE, device_error_text(out->errors)};
 }
 
 // Level sizes -> descriptor: 128-byte aligned levels in one arena, and the

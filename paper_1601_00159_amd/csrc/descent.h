@@ -356,7 +356,7 @@ __device__ __forceinline__ Found walk_storage(uint64_t q, uint32_t cur, uint64_t
         if (cnt == 8 - skip) {
             for (uint32_t steps = 0;; steps++) {
                 if (steps >= WALK_LIMIT) {
-                    atomicAdd(errors, 1u);
+                    atomicOr(errors, ERR_WALK);
                     break;
                 }
                 const uint64_t kn = skey[cur + 1];
@@ -371,7 +371,7 @@ __device__ __forceinline__ Found walk_storage(uint64_t q, uint32_t cur, uint64_t
         uint32_t nxt = cur + 1;
         for (uint32_t steps = 0;; steps++) {
             if (steps >= WALK_LIMIT) {  // a well-formed list never gets here
-                atomicAdd(errors, 1u);
+                atomicOr(errors, ERR_WALK);
                 break;
             }
             mc = smeta[cur];

@@ -77,6 +77,7 @@ struct pi_group {
     pi::DevState *h_states = nullptr;
     uint32_t cap_items = 0;
     std::vector<pi_index *> last;  // indices whose counters h_states holds
+    std::vector<uint64_t> last_enq;  // their enq_queries when the copy was enqueued
     hipEvent_t ev = nullptr;
     hipEvent_t ev_start = nullptr, ev_fused = nullptr;  // fork/join of the fused launch
     hipStream_t fstream = nullptr;                      // the fused launch runs beside the large batches
@@ -119,8 +120,14 @@ void settle_previous(pi_group *g, hipStream_t s) {
     for (size_t k = 0; k < g->last.size(); k++) {
         Index &ix = g->last[k]->ix;
         const DevState &st = g->h_states[k];
-        if (st.errors) throw Error{PI_ERR_DEVICE, "internal error: storage walk exceeded its bound"};
-        ix.used_upper = st.nused;
+        if (st.errors) {
+            ix.failed = true;
+            ix.err = device_error_text(st.errors);
+            throw Error{PI_ERR_DEVICE, ix.err};
+        }
+        // nused in the copy plus every query enqueued on the index since the
+        // copy (group or single calls) bounds the storage in use now
+        ix.used_upper = std::min<uint64_t>(ix.used_upper, st.nused + (ix.enq_queries - g->last_enq[k]));
         const uint32_t pol = ix.cfg.rebuild_policy;
         if (pol == PI_REBUILD_NEVER) continue;
         const double thr = rebuild_threshold(ix);
@@ -142,6 +149,7 @@ void settle_previous(pi_group *g, hipStream_t s) {
         }
     }
     g->last.clear();
+    g->last_enq.clear();
 }
 
 // Room for the batch's new nodes (the host bound first, the device count
@@ -172,6 +180,7 @@ void run_group(pi_group *g, pi_index *const *indices, const pi_batch *batches, u
         if (!b.n) continue;
         if (b.n <= fused_max) fused.push_back(i);
         indices[i]->ix.used_upper = std::min<uint64_t>(indices[i]->ix.used_upper + b.n, ~0ull);
+        indices[i]->ix.enq_queries += b.n;
     }
     // small batches: one persistent launch, largest first, on the group's
     // own stream so that it overlaps the large batches below
@@ -242,10 +251,12 @@ void run_group(pi_group *g, pi_index *const *indices, const pi_batch *batches, u
     // one copy of every index's counters
     uint32_t ns = 0;
     g->last.clear();
+    g->last_enq.clear();
     for (uint32_t i = 0; i < count; i++) {
         if (!batches[i].n) continue;
         g->h_ptrs[ns++] = indices[i]->ix.dstate;
         g->last.push_back(indices[i]);
+        g->last_enq.push_back(indices[i]->ix.enq_queries);
     }
     if (ns) {
         g->d_ptrs.ensure((size_t)g->cap_items * sizeof(DevState *));

@@ -58,6 +58,12 @@ struct Index {
     Storage spare;                 // the previous storage, reused by the next rebuild
     uint64_t nbase = 0;        // base-region nodes
     uint64_t used_upper = 2;   // host upper bound of DevState::nused
+    // Queries enqueued on this index so far, by any path (single batches,
+    // group calls, serving).  Every counter copy records the value at the
+    // time it was enqueued, so nused in the copy plus the queries enqueued
+    // since then (each adds at most one node) bounds nused now, whichever
+    // path the later batches took.
+    uint64_t enq_queries = 0;
     uint64_t live_at_rebuild = 0;
     uint64_t repairs = 0;
 
@@ -73,7 +79,7 @@ struct Index {
     static constexpr int STATE_RING = 4;
     DevState *hring = nullptr;
     hipEvent_t ev_ring[STATE_RING] = {};
-    uint64_t ring_n[STATE_RING] = {};  // queries of the batch each copy follows
+    uint64_t ring_enq[STATE_RING] = {};  // enq_queries when each copy was enqueued
     uint64_t ring_head = 0;        // copies enqueued
     uint64_t ring_seen = 0;        // copies consumed (or dropped)
 
@@ -179,9 +185,12 @@ struct ServePlan {
 // Largest micro-batch that free device memory allows (at most 2^22).
 uint64_t serve_batch_limit(uint32_t inflight);
 // Replays the arrival schedule; launch(b, e) enqueues queries [b, e) on s.
-// Returns the number of micro-batches (their end indices in batch_end).
-uint64_t serve_loop(const double *arrival_us, uint64_t n, const ServePlan &plan, hipStream_t s,
-                    const std::function<void(uint64_t, uint64_t)> &launch, double *done_us, uint64_t *batch_end);
+// nb receives the number of micro-batches enqueued (their end indices in
+// batch_end); when launch throws, the micro-batches before it have been
+// waited for and stamped, nb counts them, and the error passes on.
+void serve_loop(const double *arrival_us, uint64_t n, const ServePlan &plan, hipStream_t s,
+                const std::function<void(uint64_t, uint64_t)> &launch, double *done_us, uint64_t *batch_end,
+                uint64_t &nb);
 
 // build.hip: level descriptor from sizes; level arrays from sorted keys
 IndexDesc make_desc(const Index &ix, const uint32_t *level_n, uint64_t *arena_entries);

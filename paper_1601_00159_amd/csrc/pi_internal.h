@@ -50,8 +50,21 @@ struct DevState {
     unsigned int b_new, b_deletes, b_revives, b_hits, b_invalid;
     unsigned int b_n;
     unsigned int b_pad;          // padding queries of a graph replay (not counted)
-    unsigned int errors;         // internal consistency failures (must stay 0)
+    unsigned int errors;         // ERR_* bits of internal consistency failures (must stay 0)
 };
+
+// DevState::errors bits
+constexpr unsigned int ERR_WALK = 1;      // a storage walk passed its bound (the list is malformed)
+constexpr unsigned int ERR_CAPACITY = 2;  // new nodes would have passed the storage capacity (none written)
+
+// Host message for DevState::errors (empty when 0).
+inline std::string device_error_text(unsigned int e) {
+    std::string m;
+    if (e & ERR_WALK) m += "internal error: storage walk exceeded its bound";
+    if (e & ERR_CAPACITY) m += std::string(m.empty() ? "" : "; ") +
+                               "internal error: new nodes would pass the storage capacity (not written)";
+    return m;
+}
 
 // ---------------------------------------------------------------------------
 // wave64 helpers

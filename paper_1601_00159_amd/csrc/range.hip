@@ -166,7 +166,7 @@ __global__ __launch_bounds__(WT) void k_range_walk(const uint32_t *__restrict__ 
         uint32_t cur = ra[i];
         for (uint64_t steps = 0;; steps++) {
             if (steps > limit) {
-                atomicAdd(&st->errors, 1u);
+                atomicOr(&st->errors, ERR_WALK);
                 break;
             }
             const uint64_t k = skey[cur];

@@ -60,8 +60,9 @@ uint64_t serve_batch_limit(uint32_t inflight) {
     return std::max<uint64_t>(1, std::min<uint64_t>(lim, 1u << 22));
 }
 
-uint64_t serve_loop(const double *arrival, uint64_t n, const ServePlan &plan, hipStream_t s,
-                    const std::function<void(uint64_t, uint64_t)> &launch, double *done_us, uint64_t *batch_end) {
+void serve_loop(const double *arrival, uint64_t n, const ServePlan &plan, hipStream_t s,
+                const std::function<void(uint64_t, uint64_t)> &launch, double *done_us, uint64_t *batch_end,
+                uint64_t &nb) {
     EventPool pool(plan.max_inflight + 1);
     hipEvent_t ev0 = pool.take();
     const auto clock0 = std::chrono::steady_clock::now();
@@ -91,7 +92,8 @@ uint64_t serve_loop(const double *arrival, uint64_t n, const ServePlan &plan, hi
             fl.pop_front();
         }
     };
-    uint64_t next = 0, nb = 0;
+    uint64_t next = 0;
+    nb = 0;
     while (next < n) {
         retire(false);
         const double t = now_us();
@@ -104,7 +106,17 @@ uint64_t serve_loop(const double *arrival, uint64_t n, const ServePlan &plan, hi
         const bool due = fl.empty() || t >= arrival[next] + plan.deadline_us;
         if (!full && !due) continue;                  // still collecting
         if (fl.size() >= plan.max_inflight) continue;  // no slot: keep admitting
-        launch(next, e);
+        try {
+            launch(next, e);
+        } catch (...) {
+            // the micro-batches before this one took effect: stamp them and
+            // report them (nb) before passing the error on
+            try {
+                while (!fl.empty()) retire(true);
+            } catch (...) {
+            }
+            throw;
+        }
         Flight f{pool.take(), next, e};
         PI_HIP(hipEventRecord(f.ev, s));
         fl.push_back(f);
@@ -112,7 +124,6 @@ uint64_t serve_loop(const double *arrival, uint64_t n, const ServePlan &plan, hi
         next = e;
     }
     while (!fl.empty()) retire(true);
-    return nb;
 }
 
 }  // namespace pi

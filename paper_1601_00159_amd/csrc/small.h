@@ -23,6 +23,7 @@ struct IndexView {
     uint32_t *snext;
     uint8_t *smeta;
     DevState *st;
+    uint64_t cap;  // storage capacity: new nodes never go past it
 };
 
 struct BatchView {
@@ -60,6 +61,7 @@ inline IndexView index_view(const Index &ix) {
     v.snext = ix.st.next.as<uint32_t>();
     v.smeta = ix.st.meta.as<uint8_t>();
     v.st = ix.dstate;
+    v.cap = ix.st.cap;
     return v;
 }
 
@@ -285,6 +287,10 @@ __device__ __forceinline__ void block_batch(const IndexView &v, const BatchView 
     uint32_t nnew = 0;
     uint32_t r = block_scan_u32(mynew, s_u, &nnew);
     const uint64_t base = v.st->nused;
+    // the host reserves room before the launch; should that ever fail, the
+    // new nodes are dropped rather than written past the capacity
+    const bool room = base + nnew <= v.cap;
+    if (!room) nnew = 0;
     if (nnew) {
 #pragma unroll
         for (int e = 0; e < SBI; e++) {
@@ -323,6 +329,7 @@ __device__ __forceinline__ void block_batch(const IndexView &v, const BatchView 
     __syncthreads();
     if (tid == 0) {
         DevState *st = v.st;
+        if (!room) st->errors |= ERR_CAPACITY;
         const unsigned int d = s_cnt[2], rv = s_cnt[3];
         st->nused += nnew;
         st->n_live = st->n_live + nnew + rv - d;

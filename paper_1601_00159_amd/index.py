@@ -217,6 +217,11 @@ class Index:
                                            _stream(stream)))
         return k[:got.value], d[:got.value]
 
+    def set_storage_bound(self, used_upper: int):
+        """Test hook (pi_debug_set_storage_bound): plants the host's bound on
+        the storage slots in use."""
+        self._check(self._L.pi_debug_set_storage_bound(self._h, used_upper))
+
     def sort(self, keys, stream=None):
         k = to_device_u64(keys, self.device)
         n = k.numel()

@@ -1,0 +1,86 @@
+"""Full-size parity of the write-heavy workload (Algorithm 4 with the
+threshold rebuild of Section 4.3.5 and the background index rebuild): 2^26
+loaded keys, eight batches of 2^22 queries, 40/50/10 SEARCH/INSERT/DELETE,
+SEARCH and DELETE keys Zipf 0.99 over the loaded keys, INSERT keys fresh.
+About 2.1M new nodes per batch take the index past the 15 % threshold near
+74M nodes.  Every answer of every batch and the final key/value set are
+compared bit-exactly with the single-threaded CPU oracle, which replays the
+same batches in arrival order in a thread of its own (the ctypes calls
+release the interpreter lock) while the GPU runs."""
+import concurrent.futures as cf
+
+import numpy as np
+import pytest
+import torch
+
+from oracle.skiplist import SkipList
+from paper_1601_00159_amd import workloads as W
+from paper_1601_00159_amd.index import Index, to_device_u64, to_device_u8, to_numpy_u64
+
+pytestmark = pytest.mark.gpu
+
+N_BATCHES = 8
+_STATE = {}
+
+
+@pytest.fixture(autouse=True)
+def _need_gpu(request):
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    print(f"\n[case] {request.node.name}", flush=True)
+
+
+def _workload():
+    if "w" not in _STATE:
+        _STATE["w"] = W.write_skew(load_log2=26, query_log2=22, n_batches=N_BATCHES)
+    return _STATE["w"]
+
+
+def _oracle_future():
+    """Answers of every batch and the final set, from the C oracle."""
+    if "fut" not in _STATE:
+        w = _workload()
+
+        def replay():
+            order = np.argsort(w.load_keys, kind="stable")
+            orc = SkipList()
+            orc.bulk_load_sorted(w.load_keys[order], w.load_vals[order])
+            answers = [orc.execute_batch(b.ops, b.keys, b.vals) for b in w.batches]
+            final = orc.export()
+            orc.close()
+            return answers, final
+
+        _STATE["pool"] = cf.ThreadPoolExecutor(1)
+        _STATE["fut"] = _STATE["pool"].submit(replay)
+    return _STATE["fut"]
+
+
+@pytest.mark.timeout(900)
+@pytest.mark.parametrize("policy", ["threshold", "background"])
+def test_write_skew_full_size(policy):
+    w = _workload()
+    fut = _oracle_future()
+    dev = torch.device("cuda", 0)
+    got = []
+    with Index(rebuild_policy=policy) as ix:
+        ix.bulk_load(w.load_keys, w.load_vals)
+        for i, b in enumerate(w.batches):
+            ov, os_ = ix.execute(to_device_u8(b.ops, dev), to_device_u64(b.keys, dev), to_device_u64(b.vals, dev))
+            torch.cuda.synchronize()
+            got.append((to_numpy_u64(ov), os_.cpu().numpy()))
+            print(f"  batch {i} done", flush=True)
+        ek, ev = ix.export()
+        ek, ev = to_numpy_u64(ek), to_numpy_u64(ev)
+        st = ix.stats()
+    print(f"  policy {policy}: repairs {st['repairs']}, index rebuilds {st['index_rebuilds']}, "
+          f"live {st['live_nodes']}, overflow {st['overflow_nodes']}", flush=True)
+    if policy == "threshold":
+        assert st["repairs"] >= 1
+    else:
+        assert st["index_rebuilds"] >= 1
+    answers, (ok, ov) = fut.result(timeout=800)
+    for i, ((gv, gs), (wv, ws)) in enumerate(zip(got, answers)):
+        bad = np.nonzero((gs != ws) | (gv != wv))[0]
+        assert bad.size == 0, f"batch {i}: {bad.size} mismatches, first at {int(bad[0])}"
+    assert np.array_equal(ek, ok) and np.array_equal(ev, ov)
+    assert st["live_nodes"] == ok.size

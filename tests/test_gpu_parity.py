@@ -518,14 +518,19 @@ def test_graph_replays_match_eager_batches():
     """Small batches replay a captured graph (padded to a power of two with
     invalid queries).  The same sequence of batches -- sizes across several
     classes, repeats of one class, a rebuild in between that forces a new
-    capture -- gives the eager path's answers and counters, replay after
-    replay, with host synchronisation between them."""
+    capture -- gives the oracle's answers and final set through both the
+    graph path and the eager path, replay after replay, with host
+    synchronisation between them, and the two paths keep equal counters."""
     rng = np.random.default_rng(77)
     lk = rng.integers(0, 1 << 63, size=100_000, dtype=np.uint64)
     lv = rng.integers(0, 1 << 64, size=100_000, dtype=np.uint64, endpoint=False)
     pool = np.concatenate([lk[:50_000], rng.integers(0, 1 << 63, size=50_000, dtype=np.uint64)])
     sizes = [1, 100, 4096, 4097, 5000, 5000, 5000, 70_000, 3000, 262_144, 9]
     batches = [_random_batch(rng, pool, n) for n in sizes]
+    orc = SkipList()
+    orc.bulk_load(lk, lv)
+    want = [orc.execute_batch(*b) for b in batches]
+    want_k, want_v = orc.export()
     res = {}
     for mode, glog in (("eager", 0), ("graph", 18)):
         with Index(rebuild_policy="never", graph_max_log2=glog) as ix:
@@ -536,10 +541,10 @@ def test_graph_replays_match_eager_batches():
                     ix.repair()  # new levels and storage: the graphs must be captured again
                 out.append(run_gpu(ix, ops, keys, vals))
             res[mode] = (out, export_np(ix), ix.stats())
-    for b in range(len(sizes)):
-        assert_same(*res["graph"][0][b], *res["eager"][0][b], f"batch {b} (n={sizes[b]})")
-    assert np.array_equal(res["graph"][1][0], res["eager"][1][0])
-    assert np.array_equal(res["graph"][1][1], res["eager"][1][1])
+    for mode in ("eager", "graph"):
+        for b in range(len(sizes)):
+            assert_same(*res[mode][0][b], *want[b], f"{mode} batch {b} (n={sizes[b]}) against the oracle")
+        assert np.array_equal(res[mode][1][0], want_k) and np.array_equal(res[mode][1][1], want_v), mode
     for k in ("queries", "hits", "invalid", "new_nodes", "deletes", "revives", "live_nodes"):
         assert res["graph"][2][k] == res["eager"][2][k], k
 

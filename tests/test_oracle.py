@@ -337,7 +337,7 @@ def _brute_range(pairs, lo, hi):
 
 
 def test_range_search_brute_force_and_special_cases():
-    """The range query of Section 4.3 (SEARCH only): the oracle and the numpy
+    """The range query of Section 3.2.5 (SEARCH only): the oracle and the numpy
     reference against a linear scan, after inserts and deletes, with empty,
     reversed, single-key, full-span and out-of-span ranges."""
     rng = random.Random(31)
@@ -373,3 +373,44 @@ def test_range_search_brute_force_and_special_cases():
     assert counts[-8] == n_all and counts[-7] == (1 if ref.keys[0] == 0 else 0)
     assert counts[-6] == 0 and counts[-5] == 1 and counts[-4] == 0 and counts[-3] == 0
     assert counts[-2] == n_all and counts[-1] == 0
+
+
+# ------------------------------------------------- self-check negative pins
+
+@pytest.mark.parametrize("kind,code", [(1, 1), (2, 2), (3, 3), (4, 4)])
+def test_self_check_rejects_planted_faults(kind, code):
+    """orc_check is pinned both ways: it accepts every well-formed list built
+    above, and it rejects each planted fault with that fault's code -- a level
+    out of order (1), a level-2 key missing on level 1 (2), a height that
+    differs from the rule (3), a size that differs from the level-1 count
+    (4) -- and accepts the list again once the fault is undone."""
+    rng = np.random.default_rng(50 + kind)
+    keys = np.unique(rng.integers(0, 1 << 63, size=5000, dtype=np.uint64))
+    s = SkipList()
+    s.bulk_load(keys, keys)
+    assert s.check() == 0
+    assert s.plant(kind) == 0
+    assert s.check() == code
+    s.restore()
+    assert s.check() == 0
+    s.close()
+
+
+def test_oracle_under_sanitizers(tmp_path):
+    """The oracle's self-test driver (every entry point against a brute-force
+    sorted array, planted faults included) built with AddressSanitizer and
+    UndefinedBehaviorSanitizer: no memory error, no undefined behaviour, no
+    leak, every answer right."""
+    import shutil
+    import subprocess
+
+    from oracle import build as ob
+
+    if shutil.which("gcc") is None:
+        pytest.skip("gcc not available")
+    exe = ob.build_selftest(str(tmp_path / "selftest"), sanitize=True)
+    env = dict(os.environ, ASAN_OPTIONS="detect_leaks=1:abort_on_error=0:verify_asan_link_order=0",
+               UBSAN_OPTIONS="print_stacktrace=1:halt_on_error=1")
+    r = subprocess.run([exe], capture_output=True, text=True, env=env, timeout=120)
+    assert r.returncode == 0, r.stdout + r.stderr
+    assert "selftest ok" in r.stdout
