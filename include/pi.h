@@ -175,6 +175,24 @@ pi_status pi_execute_batch(pi_index *idx, const uint8_t *d_ops, const uint64_t *
                            const uint64_t *d_values, uint64_t n, uint64_t *d_out_values,
                            uint8_t *d_out_status, pi_stream stream);
 
+/* pi_execute_batch for callers that cannot allocate device memory (code
+ * under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc).  Same arguments, answers and effect as pi_execute_batch, but
+ * the call never allocates or frees memory: every per-batch buffer of the hot
+ * path lives in one scratch array of 8 MiB that the library keeps per GPU for
+ * the life of the process (its address is taken when the first index is
+ * created on that GPU).  Limits: n <= 65536 (2^16) queries, else
+ * PI_ERR_INVALID_ARG; the storage is never grown, so a batch whose new nodes
+ * may not fit the free slots gets PI_ERR_CAPACITY with nothing enqueued; no
+ * index rebuild runs inside this call (one that is due runs at the next
+ * pi_execute_batch).  The scratch keeps the last call's contents and is
+ * shared by every index of the GPU: calls of this function that overlap on
+ * one GPU (other streams, other host threads) race and must be ordered by the
+ * caller.  n = 0 is a no-op. */
+pi_status pi_execute_batch_noalloc(pi_index *idx, const uint8_t *d_ops, const uint64_t *d_keys,
+                                   const uint64_t *d_values, uint64_t n, uint64_t *d_out_values,
+                                   uint8_t *d_out_status, pi_stream stream);
+
 /* Rebuilds the storage base region and every index level now, whatever the
  * policy (Section 4.1: rebuild from the storage layer, bottom-up, drop
  * deleted nodes).  Synchronises the stream. */

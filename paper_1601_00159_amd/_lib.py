@@ -54,7 +54,8 @@ class pi_stats(ctypes.Structure):
 EXPORTED = ["pi_config_default", "pi_create", "pi_destroy", "pi_bulk_load", "pi_execute_batch",
             "pi_repair", "pi_export", "pi_range_count", "pi_range_collect", "pi_serve_config_default", "pi_serve", "pi_group_config_default", "pi_group_create",
             "pi_group_destroy", "pi_group_execute", "pi_group_autotune", "pi_group_tuning", "pi_group_last_error", "pi_get_stats", "pi_get_profile", "pi_last_error", "pi_debug_interceptions",
-            "pi_debug_level", "pi_debug_sort", "pi_debug_set_storage_bound"]
+            "pi_debug_level", "pi_debug_sort", "pi_debug_set_storage_bound",
+            "pi_execute_batch_noalloc"]
 
 
 class pi_serve_config(ctypes.Structure):
@@ -109,6 +110,7 @@ def load(path: str = LIB_PATH):
         "pi_debug_level": ([vp, u32, vp, vp, u64, ctypes.POINTER(u64), vp], i32),
         "pi_debug_sort": ([vp, vp, u64, vp, vp, vp], i32),
         "pi_debug_set_storage_bound": ([vp, u64], i32),
+        "pi_execute_batch_noalloc": ([vp, vp, vp, vp, u64, vp, vp, vp], i32),
     }
     for name, (args, res) in sig.items():
         f = getattr(lib, name)

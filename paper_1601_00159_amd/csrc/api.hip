@@ -10,8 +10,20 @@
 
 namespace pi {
 
+thread_local Arena *t_arena = nullptr;
+
 void DevBuf::ensure(size_t need) {
     if (need <= bytes && p) return;
+    if (t_arena) {
+        // the caller's fixed range: no device allocation, nothing freed
+        const size_t off = (t_arena->used + 255) & ~size_t(255);
+        if (off + need > t_arena->cap)
+            throw Error{PI_ERR_INVALID_ARG, "scratch of " + std::to_string(t_arena->cap) + " bytes too small"};
+        p = reinterpret_cast<void *>(reinterpret_cast<uintptr_t>(t_arena->base) + off);
+        bytes = need;
+        t_arena->used = off + need;
+        return;
+    }
     // Buffers up to 16 MiB (batch workspaces, the storage of small indices)
     // take the next power of two, so sizes that vary from call to call
     // reallocate at most once per doubling; a larger buffer is allocated as
@@ -127,13 +139,14 @@ void release_all(pi::Index &ix) {
 // for only when STATE_RING batches are queued behind it, so the decision
 // lags the device by at most that many batches and the GPU queue never runs
 // dry because of it.
-void maybe_rebuild(pi::Index &ix, hipStream_t s) {
+void maybe_rebuild(pi::Index &ix, hipStream_t s, bool may_rebuild = true) {
     const uint32_t pol = ix.cfg.rebuild_policy;
     // only the threshold and background policies decide from the counters;
-    // the others read the copies that have landed (device errors, the
-    // storage bound) and never wait for one
-    const bool decides = pol == PI_REBUILD_THRESHOLD || pol == PI_REBUILD_BACKGROUND;
-    if (pol == PI_REBUILD_BACKGROUND) pi::bg_advance(ix);
+    // the others (and a call that may not allocate, which a rebuild does)
+    // read the copies that have landed (device errors, the storage bound)
+    // and never wait for one
+    const bool decides = may_rebuild && (pol == PI_REBUILD_THRESHOLD || pol == PI_REBUILD_BACKGROUND);
+    if (may_rebuild && pol == PI_REBUILD_BACKGROUND) pi::bg_advance(ix);
     bool have = false;
     pi::DevState latest{};
     uint64_t latest_enq = 0;
@@ -303,6 +316,7 @@ pi_status pi_create(const pi_config *cfg_in, pi_index **out) {
         std::memset(ix.hring, 0, pi::Index::STATE_RING * sizeof(pi::DevState));
         const uint64_t cap = std::max<uint64_t>(cfg.capacity_hint ? cfg.capacity_hint : (1u << 16), 4);
         ix.st.alloc(cap);
+        pi::noalloc_init(ix.device);
         pi::init_empty(ix, nullptr);
         PI_HIP(hipDeviceSynchronize());
     } catch (const pi::Error &e) {
@@ -376,6 +390,60 @@ pi_status pi_execute_batch(pi_index *h, const uint8_t *d_ops, const uint64_t *d_
         if (!d_ops || !d_keys || !d_values || !d_out_values || !d_out_status)
             return fail(ix, PI_ERR_INVALID_ARG, "NULL pointer");
         batch_step(ix, d_ops, d_keys, d_values, n, d_out_values, d_out_status, (hipStream_t)stream);
+        return PI_OK;
+    });
+}
+
+pi_status pi_execute_batch_noalloc(pi_index *h, const uint8_t *d_ops, const uint64_t *d_keys,
+                                   const uint64_t *d_values, uint64_t n, uint64_t *d_out_values,
+                                   uint8_t *d_out_status, pi_stream stream) {
+    return guarded(h, [&](pi::Index &ix) -> pi_status {
+        if (n == 0) return PI_OK;
+        if (n > pi::noalloc_max_batch()) return fail(ix, PI_ERR_INVALID_ARG, "n above the scratch limit (2^16)");
+        if (!d_ops || !d_keys || !d_values || !d_out_values || !d_out_status)
+            return fail(ix, PI_ERR_INVALID_ARG, "NULL pointer");
+        hipStream_t s = (hipStream_t)stream;
+        uint8_t *scr = pi::noalloc_scratch(ix.device);
+        // counters that have landed: device errors and the storage bound; no
+        // rebuild (it allocates): the next allocating call takes it up
+        maybe_rebuild(ix, s, false);
+        // room for the new nodes, never by growing the storage; the insert
+        // count goes to the first word of the scratch
+        if (ix.used_upper + n > ix.st.cap) {
+            pi::DevState cur;
+            pi::read_state(ix, s, &cur);
+            if (cur.nused + n > ix.st.cap) {
+                const uint64_t ins = pi::count_inserts(ix, d_ops, d_keys, n, s, reinterpret_cast<unsigned int *>(scr));
+                if (cur.nused + ins > ix.st.cap)
+                    return fail(ix, PI_ERR_CAPACITY, "no room for the batch's new nodes (this call never grows "
+                                                     "the storage)");
+            }
+        }
+        // every per-batch buffer from the scratch, sized before the first launch
+        constexpr size_t RESERVED = 256;  // the insert counter above
+        pi::Arena arena{scr + RESERVED, pi::noalloc_scratch_bytes() - RESERVED, 0};
+        pi::SortWorkspace sw;
+        pi::MsdWorkspace mw;
+        pi::ScanWorkspace cw;
+        pi::BatchWorkspace bw;
+        const bool prof = ix.prof.on;  // stage events are created on demand: off for this call
+        ix.prof.on = false;
+        try {
+            pi::ArenaScope scope(&arena);
+            sw.ensure(n);
+            mw.ensure(n);
+            cw.ensure(n);
+            bw.ensure(n);
+            pi::execute_batch(ix, pi::BatchBuffers{sw, mw, cw, bw}, d_ops, d_keys, d_values, n, d_out_values,
+                              d_out_status, s);
+        } catch (...) {
+            ix.prof.on = prof;
+            throw;
+        }
+        ix.prof.on = prof;
+        ix.used_upper = std::min<uint64_t>(ix.used_upper + n, ~0ull);
+        ix.enq_queries += n;
+        push_state(ix, s);
         return PI_OK;
     });
 }

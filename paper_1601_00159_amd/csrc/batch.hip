@@ -605,9 +605,12 @@ void BatchWorkspace::release() {
     n = 0;
 }
 
-uint64_t count_inserts(Index &ix, const uint8_t *ops, const uint64_t *keys, uint64_t n, hipStream_t s) {
-    ix.tmp[5].ensure(16);
-    unsigned int *cnt = ix.tmp[5].as<unsigned int>();
+uint64_t count_inserts(Index &ix, const uint8_t *ops, const uint64_t *keys, uint64_t n, hipStream_t s,
+                       unsigned int *cnt) {
+    if (!cnt) {
+        ix.tmp[5].ensure(16);
+        cnt = ix.tmp[5].as<unsigned int>();
+    }
     hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(64), 0, s, cnt);
     hipLaunchKernelGGL(k_count_inserts, dim3(blocks_for(n, 256)), dim3(256), 0, s, ops, keys, (uint32_t)n, cnt);
     PI_LAUNCH_CHECK();
@@ -620,7 +623,13 @@ uint64_t count_inserts(Index &ix, const uint8_t *ops, const uint64_t *keys, uint
 
 void execute_batch(Index &ix, const uint8_t *ops, const uint64_t *keys, const uint64_t *vals, uint64_t n,
                    uint64_t *out_vals, uint8_t *out_status, hipStream_t s) {
-    ix.bws.ensure(n);
+    execute_batch(ix, BatchBuffers{ix.sortws, ix.msdws, ix.scanws, ix.bws}, ops, keys, vals, n, out_vals,
+                  out_status, s);
+}
+
+void execute_batch(Index &ix, const BatchBuffers &buf, const uint8_t *ops, const uint64_t *keys,
+                   const uint64_t *vals, uint64_t n, uint64_t *out_vals, uint8_t *out_status, hipStream_t s) {
+    buf.bws.ensure(n);
     const uint64_t *sk = nullptr;
     const uint32_t *sidx = nullptr;
     DevState *st = ix.dstate;
@@ -635,10 +644,10 @@ void execute_batch(Index &ix, const uint8_t *ops, const uint64_t *keys, const ui
         hipLaunchKernelGGL(k_batch_begin, dim3(1), dim3(64), 0, s, st, (uint32_t)n);
         PI_LAUNCH_CHECK();
     }
-    sort_batch_by_range(ix.sortws, ix.msdws, keys, ops, n, st, s, &sk, &sidx);
+    sort_batch_by_range(buf.sort, buf.msd, keys, ops, n, st, s, &sk, &sidx);
     mark(1);
 
-    BatchWorkspace &w = ix.bws;
+    BatchWorkspace &w = buf.bws;
     launch_descend<0>(ix, s, sk, sidx, n, out_vals, out_status, w.res_val.as<uint64_t>(), w.res_flags.as<uint8_t>(),
                       w.loc.as<uint32_t>(), w.locnext.as<uint32_t>(), ops, vals, w.sop.as<uint8_t>(),
                       w.svin.as<uint64_t>());
@@ -656,7 +665,7 @@ void execute_batch(Index &ix, const uint8_t *ops, const uint64_t *keys, const ui
                        w.newflag.as<uint32_t>(), w.gw.as<int32_t>(), w.part.as<uint4>(), st);
     PI_LAUNCH_CHECK();
     mark(3);
-    exclusive_scan_u32(ix.scanws, w.newflag.as<uint32_t>(), w.newpos.as<uint32_t>(), n, &st->b_new,
+    exclusive_scan_u32(buf.scan, w.newflag.as<uint32_t>(), w.newpos.as<uint32_t>(), n, &st->b_new,
                        &st->b_writers, s);
     // grid-stride launches of at most 8 blocks per CU: batches without
     // updates leave at once, and a smaller grid dispatches faster

@@ -160,8 +160,18 @@ void read_state(Index &ix, hipStream_t s, DevState *out);  // synchronises s
 void grow_storage(Index &ix, uint64_t need_slots, hipStream_t s);
 
 // batch.hip
+// The per-batch buffers of the multi-kernel path (the index's own, or ones
+// taken from the no-allocation scratch).
+struct BatchBuffers {
+    SortWorkspace &sort;
+    MsdWorkspace &msd;
+    ScanWorkspace &scan;
+    BatchWorkspace &bws;
+};
 void execute_batch(Index &ix, const uint8_t *ops, const uint64_t *keys, const uint64_t *vals, uint64_t n,
                    uint64_t *out_vals, uint8_t *out_status, hipStream_t s);
+void execute_batch(Index &ix, const BatchBuffers &buf, const uint8_t *ops, const uint64_t *keys,
+                   const uint64_t *vals, uint64_t n, uint64_t *out_vals, uint8_t *out_status, hipStream_t s);
 // Same result through a captured graph of the hot path for the smallest
 // power-of-two class >= n (padding with invalid queries).
 void execute_batch_graph(Index &ix, const uint8_t *ops, const uint64_t *keys, const uint64_t *vals, uint64_t n,
@@ -174,7 +184,16 @@ void execute_batch_small(Index &ix, const uint8_t *ops, const uint64_t *keys, co
 uint32_t small_batch_lds_bytes();
 void debug_interceptions(Index &ix, const uint64_t *keys, uint64_t n, uint64_t *icpt_keys, uint8_t *is_head,
                          hipStream_t s);
-uint64_t count_inserts(Index &ix, const uint8_t *ops, const uint64_t *keys, uint64_t n, hipStream_t s);
+// Number of valid INSERT queries of a batch (synchronises s); the counter is
+// cnt (device, one word) when given, else index scratch.
+uint64_t count_inserts(Index &ix, const uint8_t *ops, const uint64_t *keys, uint64_t n, hipStream_t s,
+                       unsigned int *cnt = nullptr);
+
+// noalloc.hip: the scratch array of the call that allocates nothing
+void noalloc_init(int device);  // once per device, with that device current
+uint8_t *noalloc_scratch(int device);
+uint64_t noalloc_max_batch();
+size_t noalloc_scratch_bytes();
 
 // serve.hip
 struct ServePlan {

@@ -182,6 +182,22 @@ struct Error {
 
 #define PI_LAUNCH_CHECK() PI_HIP(hipGetLastError())
 
+// Memory a DevBuf takes its bytes from instead of hipMalloc while an
+// ArenaScope is active on the calling thread (the call that allocates
+// nothing): bump allocation from a fixed range, never freed.  With base
+// null it only counts the bytes asked for.
+struct Arena {
+    uint8_t *base;
+    size_t cap;
+    size_t used;
+};
+extern thread_local Arena *t_arena;
+struct ArenaScope {
+    Arena *prev;
+    explicit ArenaScope(Arena *a) : prev(t_arena) { t_arena = a; }
+    ~ArenaScope() { t_arena = prev; }
+};
+
 // A device buffer that only grows.
 struct DevBuf {
     void *p = nullptr;

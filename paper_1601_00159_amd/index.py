@@ -122,6 +122,12 @@ class Index:
         self._check(self._L.pi_execute_batch(self._h, _ptr(ops_t), _ptr(keys_t), _ptr(vals_t),
                                              keys_t.numel(), _ptr(out_v), _ptr(out_s), _stream(stream)))
 
+    def execute_noalloc(self, ops_t, keys_t, vals_t, out_v, out_s, stream=None):
+        """pi_execute_batch_noalloc: device tensors only; the call allocates
+        nothing (its buffers live in the library's per-GPU scratch)."""
+        self._check(self._L.pi_execute_batch_noalloc(self._h, _ptr(ops_t), _ptr(keys_t), _ptr(vals_t),
+                                                     keys_t.numel(), _ptr(out_v), _ptr(out_s), _stream(stream)))
+
     def repair(self, stream=None):
         self._check(self._L.pi_repair(self._h, _stream(stream)))
 
