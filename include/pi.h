@@ -70,7 +70,7 @@ enum {
     PI_REBUILD_THRESHOLD = 0, /* rebuild when changes >= fraction * live nodes */
     PI_REBUILD_NEVER = 1,     /* only pi_repair() rebuilds */
     PI_REBUILD_ALWAYS = 2,    /* rebuild after every batch that changed the structure */
-    PI_REBUILD_BACKGROUND = 3 /* when changes >= fraction * live nodes, rebuild the index layer over the
+    PI_REBUILD_BACKGROUND = 3, /* when changes >= fraction * live nodes, rebuild the index layer over the
                                  storage as it stands (new nodes included) on a second stream while
                                  batches go on, and switch to it at a batch boundary (Section 4.3.5);
                                  merge the storage itself (a full rebuild) only when the new and
@@ -80,6 +80,14 @@ enum {
                                  up to that merge point, and the buffers of the background rebuild
                                  (about 88 bytes per storage slot) are reserved when the storage is
                                  loaded, merged or grown */
+    PI_REBUILD_SLICES = 4     /* finer-grained repair (Section 7): the lower index levels are kept in
+                                 per-key-range segments (slices of 4096 base slots) with room to grow;
+                                 when changes >= fraction * live nodes, only the slices that received
+                                 new nodes since the last round are rewritten in place (their keys
+                                 merged with the new ones), and the small upper levels are rebuilt;
+                                 a segment that would overflow, or new and deleted nodes reaching
+                                 compact_percent of the base region, triggers a full rebuild that also
+                                 merges the storage.  Runs on the caller's stream between batches */
 };
 
 typedef struct {
@@ -107,6 +115,11 @@ typedef struct {
                                  keeps room for that many new nodes */
     uint64_t rebuild_min;     /* a threshold rebuild also needs at least this many changes (default 4096):
                                  an index of a few thousand keys is cheaper to walk than to rebuild */
+    uint32_t check_writers;   /* 1 = checked mode of the single-writer invariant (Section 3.2.4): every
+                                 storage write of a batch records its writer in a shadow word per node
+                                 (8 bytes per storage slot); a node written by two different writers in
+                                 one phase of a batch fails the handle with PI_ERR_DEVICE.  0 = off
+                                 (default).  Not available with pi_execute_batch_noalloc */
 } pi_config;
 
 /* Accumulated device time per stage of pi_execute_batch (profile = 1). */
@@ -138,6 +151,9 @@ typedef struct {
     uint32_t lds_from;        /* lowest level kept in LDS by the descent */
     uint64_t level_size[33];  /* keys on level l, l = 2..32 */
     uint64_t index_rebuilds;  /* background index-layer rebuilds switched in */
+    uint64_t slice_rounds;    /* slice repair rounds (PI_REBUILD_SLICES) */
+    uint64_t slices_repaired; /* slices rewritten over all rounds */
+    uint64_t slices;          /* slices of the current layout (0: not sliced) */
 } pi_stats;
 
 /* Fills *cfg with the defaults listed above. */
@@ -370,6 +386,14 @@ pi_status pi_debug_level(pi_index *idx, uint32_t level, uint64_t *d_keys, uint32
  * workspace. */
 pi_status pi_debug_sort(pi_index *idx, const uint64_t *d_keys, uint64_t n,
                         uint64_t *d_sorted_keys, uint32_t *d_perm, pi_stream stream);
+
+/* Self-test of the checked mode's detection (check_writers), on a private
+ * two-word shadow rather than the storage: *same_writer_err receives the error
+ * bits raised by one writer recording a node twice (must be 0), and
+ * *two_writer_err those raised by two writers of one node in one phase (must
+ * be nonzero).  Synchronises the stream.  Host pointers. */
+pi_status pi_debug_writer_selftest(pi_index *idx, uint32_t *same_writer_err, uint32_t *two_writer_err,
+                                   pi_stream stream);
 
 /* Test hook: sets the host's upper bound on the storage slots in use, the
  * bound that decides whether a batch needs room checked before it is

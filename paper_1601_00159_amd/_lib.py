@@ -17,7 +17,7 @@ PI_ERR_CAPACITY = -5
 
 PI_OP_SEARCH, PI_OP_INSERT, PI_OP_DELETE = 0, 1, 2
 PI_R_ABSENT, PI_R_PRESENT, PI_R_INVALID = 0, 1, 255
-PI_REBUILD_THRESHOLD, PI_REBUILD_NEVER, PI_REBUILD_ALWAYS, PI_REBUILD_BACKGROUND = 0, 1, 2, 3
+PI_REBUILD_THRESHOLD, PI_REBUILD_NEVER, PI_REBUILD_ALWAYS, PI_REBUILD_BACKGROUND, PI_REBUILD_SLICES = 0, 1, 2, 3, 4
 
 STATUS_NAMES = {PI_OK: "PI_OK", PI_ERR_INVALID_ARG: "PI_ERR_INVALID_ARG",
                 PI_ERR_OUT_OF_MEMORY: "PI_ERR_OUT_OF_MEMORY", PI_ERR_STATE: "PI_ERR_STATE",
@@ -33,7 +33,8 @@ class pi_config(ctypes.Structure):
                 ("queries_per_lane", ctypes.c_uint32), ("blocks_per_cu", ctypes.c_uint32),
                 ("lds_budget", ctypes.c_uint32), ("descent_block", ctypes.c_uint32),
                 ("graph_max_log2", ctypes.c_uint32), ("small_batch_log2", ctypes.c_uint32),
-                ("compact_percent", ctypes.c_uint32), ("rebuild_min", ctypes.c_uint64)]
+                ("compact_percent", ctypes.c_uint32), ("rebuild_min", ctypes.c_uint64),
+                ("check_writers", ctypes.c_uint32)]
 
 
 class pi_profile(ctypes.Structure):
@@ -48,13 +49,14 @@ class pi_stats(ctypes.Structure):
         "batches", "queries", "hits", "invalid", "new_nodes", "deletes", "revives", "changes",
         "repairs", "live_nodes", "base_nodes", "overflow_nodes", "capacity")] + [
         ("n_levels", ctypes.c_uint32), ("lds_from", ctypes.c_uint32),
-        ("level_size", ctypes.c_uint64 * 33), ("index_rebuilds", ctypes.c_uint64)]
+        ("level_size", ctypes.c_uint64 * 33), ("index_rebuilds", ctypes.c_uint64),
+        ("slice_rounds", ctypes.c_uint64), ("slices_repaired", ctypes.c_uint64), ("slices", ctypes.c_uint64)]
 
 
 EXPORTED = ["pi_config_default", "pi_create", "pi_destroy", "pi_bulk_load", "pi_execute_batch",
             "pi_repair", "pi_export", "pi_range_count", "pi_range_collect", "pi_serve_config_default", "pi_serve", "pi_group_config_default", "pi_group_create",
             "pi_group_destroy", "pi_group_execute", "pi_group_autotune", "pi_group_tuning", "pi_group_last_error", "pi_get_stats", "pi_get_profile", "pi_last_error", "pi_debug_interceptions",
-            "pi_debug_level", "pi_debug_sort", "pi_debug_set_storage_bound",
+            "pi_debug_level", "pi_debug_sort", "pi_debug_set_storage_bound", "pi_debug_writer_selftest",
             "pi_execute_batch_noalloc"]
 
 
@@ -110,6 +112,7 @@ def load(path: str = LIB_PATH):
         "pi_debug_level": ([vp, u32, vp, vp, u64, ctypes.POINTER(u64), vp], i32),
         "pi_debug_sort": ([vp, vp, u64, vp, vp, vp], i32),
         "pi_debug_set_storage_bound": ([vp, u64], i32),
+        "pi_debug_writer_selftest": ([vp, ctypes.POINTER(u32), ctypes.POINTER(u32), vp], i32),
         "pi_execute_batch_noalloc": ([vp, vp, vp, vp, u64, vp, vp, vp], i32),
     }
     for name, (args, res) in sig.items():

@@ -9,7 +9,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libpi.so")
 SOURCES = ["api.hip", "build.hip", "batch.hip", "sort.hip", "msd.hip", "scan.hip", "range.hip", "serve.hip", "small.hip", "group.hip", "bgrebuild.hip",
-           "noalloc.hip"]
+           "noalloc.hip", "slices.hip"]
 ARCH = os.environ.get("PI_OFFLOAD_ARCH", "gfx950")
 
 

@@ -120,6 +120,8 @@ void release_all(pi::Index &ix) {
     for (auto &b : ix.rng) b.release();
     pi::release_graphs(ix);
     pi::bg_release(ix);
+    pi::slice_release(ix);
+    ix.owner.release();
     if (ix.dstate) (void)hipFree(ix.dstate);
     if (ix.hstate) (void)hipHostFree(ix.hstate);
     if (ix.hcounts) (void)hipHostFree(ix.hcounts);
@@ -145,7 +147,8 @@ void maybe_rebuild(pi::Index &ix, hipStream_t s, bool may_rebuild = true) {
     // the others (and a call that may not allocate, which a rebuild does)
     // read the copies that have landed (device errors, the storage bound)
     // and never wait for one
-    const bool decides = may_rebuild && (pol == PI_REBUILD_THRESHOLD || pol == PI_REBUILD_BACKGROUND);
+    const bool decides = may_rebuild && (pol == PI_REBUILD_THRESHOLD || pol == PI_REBUILD_BACKGROUND ||
+                                         pol == PI_REBUILD_SLICES);
     if (may_rebuild && pol == PI_REBUILD_BACKGROUND) pi::bg_advance(ix);
     bool have = false;
     pi::DevState latest{};
@@ -182,8 +185,9 @@ void maybe_rebuild(pi::Index &ix, hipStream_t s, bool may_rebuild = true) {
         }
         return;
     }
-    // background: merge the storage when new and deleted nodes have piled up,
-    // else rebuild the index layer beside the batches
+    // background and slices: merge the storage when new and deleted nodes
+    // have piled up, else rebuild the index layer beside the batches, or
+    // repair the slices that changed
     const double compact = (ix.cfg.compact_percent ? ix.cfg.compact_percent : 100) / 100.0 *
                            (double)std::max<uint64_t>(ix.nbase, 1);
     if ((double)latest.changes >= std::max(compact, thr)) {
@@ -191,8 +195,16 @@ void maybe_rebuild(pi::Index &ix, hipStream_t s, bool may_rebuild = true) {
         ix.ring_seen = ix.ring_head;
         return;
     }
-    if (latest.changes >= ix.changes_base && (double)(latest.changes - ix.changes_base) >= thr)
-        pi::bg_start(ix, latest, s);
+    if (latest.changes >= ix.changes_base && (double)(latest.changes - ix.changes_base) >= thr) {
+        if (pol == PI_REBUILD_BACKGROUND) {
+            pi::bg_start(ix, latest, s);
+        } else if (pi::slice_round(ix, latest.nused, s)) {
+            ix.changes_base = latest.changes;
+        } else {  // a segment would overflow: rebuild everything
+            pi::rebuild(ix, s);
+            ix.ring_seen = ix.ring_head;
+        }
+    }
 }
 
 // Queues the copy of the counters after a batch.
@@ -278,7 +290,7 @@ pi_status pi_create(const pi_config *cfg_in, pi_index **out) {
         cfg = *cfg_in;
     }
     if (cfg.max_height < 2 || cfg.max_height > 32 || cfg.log2_inv_p < 1 || cfg.log2_inv_p > 8 ||
-        !(cfg.rebuild_fraction >= 0.0f) || cfg.rebuild_policy > PI_REBUILD_BACKGROUND ||
+        !(cfg.rebuild_fraction >= 0.0f) || cfg.rebuild_policy > PI_REBUILD_SLICES ||
         cfg.capacity_hint > (1ull << 32) - 64 ||
         (cfg.queries_per_lane != 0 && cfg.queries_per_lane != 1 && cfg.queries_per_lane != 2 &&
          cfg.queries_per_lane != 4) ||
@@ -286,7 +298,8 @@ pi_status pi_create(const pi_config *cfg_in, pi_index **out) {
         (cfg.descent_block != 0 && cfg.descent_block != 256 && cfg.descent_block != 512 &&
          cfg.descent_block != 1024) ||
         (cfg.graph_max_log2 != 0 && (cfg.graph_max_log2 < 12 || cfg.graph_max_log2 > 22)) ||
-        (cfg.small_batch_log2 > 12 && cfg.small_batch_log2 != 255) || cfg.compact_percent > 1000) {
+        (cfg.small_batch_log2 > 12 && cfg.small_batch_log2 != 255) || cfg.compact_percent > 1000 ||
+        cfg.check_writers > 1) {
         set_err("invalid pi_config field");
         return PI_ERR_INVALID_ARG;
     }
@@ -309,7 +322,7 @@ pi_status pi_create(const pi_config *cfg_in, pi_index **out) {
         ix.num_cus = prop.multiProcessorCount;
         PI_HIP(hipMalloc(&ix.dstate, sizeof(pi::DevState)));
         PI_HIP(hipHostMalloc(&ix.hstate, sizeof(pi::DevState), hipHostMallocDefault));
-        PI_HIP(hipHostMalloc(&ix.hcounts, 64 * sizeof(uint64_t), hipHostMallocDefault));
+        PI_HIP(hipHostMalloc(&ix.hcounts, 256 * sizeof(uint64_t), hipHostMallocDefault));
         PI_HIP(hipHostMalloc(&ix.hring, pi::Index::STATE_RING * sizeof(pi::DevState), hipHostMallocDefault));
         for (auto &e : ix.ev_ring) PI_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
         std::memset(ix.hstate, 0, sizeof(pi::DevState));
@@ -400,6 +413,7 @@ pi_status pi_execute_batch_noalloc(pi_index *h, const uint8_t *d_ops, const uint
     return guarded(h, [&](pi::Index &ix) -> pi_status {
         if (n == 0) return PI_OK;
         if (n > pi::noalloc_max_batch()) return fail(ix, PI_ERR_INVALID_ARG, "n above the scratch limit (2^16)");
+        if (ix.cfg.check_writers) return fail(ix, PI_ERR_INVALID_ARG, "the writer check allocates its shadow");
         if (!d_ops || !d_keys || !d_values || !d_out_values || !d_out_status)
             return fail(ix, PI_ERR_INVALID_ARG, "NULL pointer");
         hipStream_t s = (hipStream_t)stream;
@@ -557,8 +571,12 @@ pi_status pi_get_stats(pi_index *h, pi_stats *out) {
         out->capacity = ix.st.cap;
         out->n_levels = (uint32_t)ix.desc.top;
         out->lds_from = (uint32_t)ix.desc.lds_from;
-        for (int l = 2; l <= ix.desc.top && l < 33; l++) out->level_size[l] = ix.desc.n[l];
+        for (int l = 2; l <= ix.desc.top && l < 33; l++)
+            out->level_size[l] = ix.slc.on ? ix.slc.real_n[l] : ix.desc.n[l];
         out->index_rebuilds = ix.bg.done;
+        out->slice_rounds = ix.slc.rounds;
+        out->slices_repaired = ix.slc.repaired;
+        out->slices = ix.slc.on ? ix.slc.lay.S : 0;
         return PI_OK;
     });
 }
@@ -599,6 +617,14 @@ pi_status pi_debug_level(pi_index *h, uint32_t level, uint64_t *d_keys, uint32_t
         if (!n_out) return fail(ix, PI_ERR_INVALID_ARG, "n_out is NULL");
         if (level < 2 || level > ix.cfg.max_height) return fail(ix, PI_ERR_INVALID_ARG, "bad level");
         hipStream_t s = (hipStream_t)stream;
+        if (ix.slc.on) {
+            const uint64_t n = (int)level <= ix.desc.top ? ix.slc.real_n[level] : 0;
+            *n_out = n;
+            if (n > cap) return fail(ix, PI_ERR_CAPACITY, "level larger than cap");
+            if (n > 0 && (!d_keys || !d_down)) return fail(ix, PI_ERR_INVALID_ARG, "NULL output");
+            if (n > 0) pi::slice_export_level(ix, (int)level, d_keys, d_down, cap, s);
+            return PI_OK;
+        }
         const uint64_t n = (int)level <= ix.desc.top ? ix.desc.n[level] : 0;
         *n_out = n;
         if (n > cap) return fail(ix, PI_ERR_CAPACITY, "level larger than cap");
@@ -611,6 +637,15 @@ pi_status pi_debug_level(pi_index *h, uint32_t level, uint64_t *d_keys, uint32_t
         PI_HIP(hipStreamSynchronize(s));
         return PI_OK;
     });
+}
+
+pi_status pi_debug_writer_selftest(pi_index *h, uint32_t *same_writer_err, uint32_t *two_writer_err,
+                                   pi_stream stream) {
+    return guarded(h, [&](pi::Index &ix) -> pi_status {
+        if (!same_writer_err || !two_writer_err) return fail(ix, PI_ERR_INVALID_ARG, "NULL output");
+        pi::writer_selftest(ix, (hipStream_t)stream, same_writer_err, two_writer_err);
+        return PI_OK;
+    }, true);
 }
 
 pi_status pi_debug_set_storage_bound(pi_index *h, uint64_t used_upper) {

@@ -48,6 +48,7 @@ __global__ __launch_bounds__(DT) void k_descend(IndexDesc desc, const uint64_t *
                                                 const uint64_t *__restrict__ sval, const uint32_t *__restrict__ snext,
                                                 const uint8_t *__restrict__ smeta, const uint64_t *__restrict__ sk,
                                                 const uint32_t *__restrict__ sidx, uint32_t n, DevState *st,
+                                                uint2 *__restrict__ dpart,
                                                 uint64_t *__restrict__ out_vals, uint8_t *__restrict__ out_status,
                                                 uint64_t *__restrict__ res_val, uint8_t *__restrict__ res_flags,
                                                 uint32_t *__restrict__ loc, uint32_t *__restrict__ locnext,
@@ -120,11 +121,20 @@ __global__ __launch_bounds__(DT) void k_descend(IndexDesc desc, const uint64_t *
         }
     }
     if (MODE == 0) {
+        // the block's counts go to its own slot (summed at the batch's end),
+        // not to shared counters
+        __shared__ uint2 s_cnt[DT / 64];
         hits = wave_sum_u32(hits);
         invalid = wave_sum_u32(invalid);
-        if (lane_id() == 0) {
-            if (hits) atomicAdd(&st->b_hits, hits);
-            if (invalid) atomicAdd(&st->b_invalid, invalid);
+        if (lane_id() == 0) s_cnt[threadIdx.x >> 6] = make_uint2(hits, invalid);
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            uint2 c = make_uint2(0, 0);
+            for (int w = 0; w < DT / 64; w++) {
+                c.x += s_cnt[w].x;
+                c.y += s_cnt[w].y;
+            }
+            dpart[blockIdx.x] = c;
         }
     }
 }
@@ -236,11 +246,11 @@ __device__ __forceinline__ Seg run_element(const Run &r, uint32_t base, int e) {
     return x;
 }
 
-__global__ __launch_bounds__(OT) void k_own_reduce(const uint64_t *__restrict__ sk, const uint8_t *__restrict__ sop,
-                                                   uint32_t n, const DevState *st, Seg *__restrict__ agg) {
-    if (st->b_writers == 0) return;
-    __shared__ Seg s_w[ONW];
-    const uint32_t base = blockIdx.x * OTILE + threadIdx.x * OI;
+// tile t (OTILE sorted queries): aggregate of its segmented scan elements
+__device__ __forceinline__ void own_reduce_tile(uint32_t t, const uint64_t *__restrict__ sk,
+                                                const uint8_t *__restrict__ sop, uint32_t n, Seg *__restrict__ agg,
+                                                Seg *s_w) {
+    const uint32_t base = t * OTILE + threadIdx.x * OI;
     const Run r = load_run(sk, sop, n, base);
     Seg run{0, -1};
 #pragma unroll
@@ -248,13 +258,18 @@ __global__ __launch_bounds__(OT) void k_own_reduce(const uint64_t *__restrict__ 
         if (base + e < n) run = seg_op(run, run_element(r, base, e));
     Seg tot;
     block_excl_scan_seg(run, s_w, &tot);
-    if (threadIdx.x == 0) agg[blockIdx.x] = tot;
+    if (threadIdx.x == 0) agg[t] = tot;
 }
 
-// single block: exclusive scan of the tile aggregates (in place)
-__global__ __launch_bounds__(OT) void k_own_prefix(Seg *__restrict__ agg, uint32_t ntiles, const DevState *st) {
+__global__ __launch_bounds__(OT) void k_own_reduce(const uint64_t *__restrict__ sk, const uint8_t *__restrict__ sop,
+                                                   uint32_t n, const DevState *st, Seg *__restrict__ agg) {
     if (st->b_writers == 0) return;
     __shared__ Seg s_w[ONW];
+    own_reduce_tile(blockIdx.x, sk, sop, n, agg, s_w);
+}
+
+// one block: exclusive scan of the tile aggregates (in place)
+__device__ __forceinline__ void own_prefix_block(Seg *__restrict__ agg, uint32_t ntiles, Seg *s_w) {
     Seg carry{0, -1};
     for (uint32_t base = 0; base < ntiles; base += OT * 4) {
         Seg v[4];
@@ -275,7 +290,13 @@ __global__ __launch_bounds__(OT) void k_own_prefix(Seg *__restrict__ agg, uint32
     }
 }
 
-__global__ __launch_bounds__(OT) void k_own_apply(const uint64_t *__restrict__ sk, const uint32_t *__restrict__ sidx,
+__global__ __launch_bounds__(OT) void k_own_prefix(Seg *__restrict__ agg, uint32_t ntiles, const DevState *st) {
+    if (st->b_writers == 0) return;
+    __shared__ Seg s_w[ONW];
+    own_prefix_block(agg, ntiles, s_w);
+}
+
+__device__ __forceinline__ void own_apply_tile(uint32_t t, const uint64_t *__restrict__ sk, const uint32_t *__restrict__ sidx,
                                                   const uint8_t *__restrict__ sop, const uint64_t *__restrict__ svin,
                                                   uint32_t n, const Seg *__restrict__ carry_in,
                                                   const uint64_t *__restrict__ res_val,
@@ -284,10 +305,8 @@ __global__ __launch_bounds__(OT) void k_own_apply(const uint64_t *__restrict__ s
                                                   uint8_t *__restrict__ smeta, uint64_t *__restrict__ out_vals,
                                                   uint8_t *__restrict__ out_status, uint32_t *__restrict__ newflag,
                                                   int32_t *__restrict__ gw, uint4 *__restrict__ part,
-                                                  const DevState *st) {
-    if (st->b_writers == 0) return;
-    __shared__ Seg s_w[ONW];
-    const uint32_t base = blockIdx.x * OTILE + threadIdx.x * OI;
+                                                  DevState *st, WriterCheck wc, uint32_t *__restrict__ tilecnt, Seg *s_w) {
+    const uint32_t base = t * OTILE + threadIdx.x * OI;
     const Run r = load_run(sk, sop, n, base);
     const bool whole = base + OI <= n;
     Seg el[OI];
@@ -323,7 +342,7 @@ __global__ __launch_bounds__(OT) void k_own_apply(const uint64_t *__restrict__ s
         }
     }
     Seg tot;
-    Seg pre = seg_op(carry_in[blockIdx.x], block_excl_scan_seg(run, s_w, &tot));
+    Seg pre = seg_op(carry_in[t], block_excl_scan_seg(run, s_w, &tot));
     uint32_t hits = 0, dels = 0, revs = 0;
     uint32_t nf4[OI] = {0, 0, 0, 0};
 #pragma unroll
@@ -359,6 +378,7 @@ __global__ __launch_bounds__(OT) void k_own_apply(const uint64_t *__restrict__ s
             const bool exists = fl & 1, live = (fl & 2) != 0;
             if (sop[incl] == PI_OP_INSERT) {
                 if (exists) {
+                    wc.note(node, WriterCheck::APPLY, i, &st->errors);
                     sval[node] = svin[incl];
                     if (!live) {
                         smeta[node] = smeta[node] & (uint8_t)~META_DEL;
@@ -369,6 +389,7 @@ __global__ __launch_bounds__(OT) void k_own_apply(const uint64_t *__restrict__ s
                     gw[i] = incl;
                 }
             } else if (exists && live) {
+                wc.note(node, WriterCheck::APPLY, i, &st->errors);
                 smeta[node] = smeta[node] | META_DEL;
                 dels++;
             }
@@ -384,14 +405,17 @@ __global__ __launch_bounds__(OT) void k_own_apply(const uint64_t *__restrict__ s
     }
     // the tile's counts go to its own slot; the batch's end sums them (one
     // atomic per wave on three shared counters cost more than the apply)
+    uint32_t nnew = nf4[0] + nf4[1] + nf4[2] + nf4[3];
     hits = wave_sum_u32(hits);
     dels = wave_sum_u32(dels);
     revs = wave_sum_u32(revs);
-    __shared__ uint32_t s_c[3][ONW];
+    nnew = wave_sum_u32(nnew);
+    __shared__ uint32_t s_c[4][ONW];
     if (lane_id() == 0) {
         s_c[0][threadIdx.x >> 6] = hits;
         s_c[1][threadIdx.x >> 6] = dels;
         s_c[2][threadIdx.x >> 6] = revs;
+        s_c[3][threadIdx.x >> 6] = nnew;
     }
     __syncthreads();
     if (threadIdx.x == 0) {
@@ -400,9 +424,29 @@ __global__ __launch_bounds__(OT) void k_own_apply(const uint64_t *__restrict__ s
             c.x += s_c[0][w];
             c.y += s_c[1][w];
             c.z += s_c[2][w];
+            c.w += s_c[3][w];
         }
-        part[blockIdx.x] = c;
+        part[t] = c;
+        if (tilecnt) tilecnt[t] = c.w;
     }
+    __syncthreads();  // s_c is reused by the block's next tile
+}
+
+// tile counts (hits, deletes, revives, new nodes) go to part[tile]
+__global__ __launch_bounds__(OT) void k_own_apply(const uint64_t *__restrict__ sk, const uint32_t *__restrict__ sidx,
+                                                  const uint8_t *__restrict__ sop, const uint64_t *__restrict__ svin,
+                                                  uint32_t n, const Seg *__restrict__ carry_in,
+                                                  const uint64_t *__restrict__ res_val,
+                                                  const uint8_t *__restrict__ res_flags,
+                                                  const uint32_t *__restrict__ loc, uint64_t *__restrict__ sval,
+                                                  uint8_t *__restrict__ smeta, uint64_t *__restrict__ out_vals,
+                                                  uint8_t *__restrict__ out_status, uint32_t *__restrict__ newflag,
+                                                  int32_t *__restrict__ gw, uint4 *__restrict__ part,
+                                                  DevState *st, WriterCheck wc) {
+    if (st->b_writers == 0) return;
+    __shared__ Seg s_w[ONW];
+    own_apply_tile(blockIdx.x, sk, sidx, sop, svin, n, carry_in, res_val, res_flags, loc, sval, smeta, out_vals,
+                   out_status, newflag, gw, part, st, wc, nullptr, s_w);
 }
 
 // compacts the new nodes (key order) with their predecessor
@@ -423,43 +467,96 @@ __global__ void k_new_gather(const uint64_t *__restrict__ sk, const uint64_t *__
     }
 }
 
-// writes the new nodes and links them (Algorithm 4 insertNode).  The host
-// reserves room for every batch before it is enqueued; should that ever fail,
-// nothing is written past the capacity: the batch's new nodes are dropped
-// (k_batch_end flags ERR_CAPACITY, which fails the handle).
-__global__ void k_link(const uint64_t *__restrict__ nk, const uint64_t *__restrict__ nv,
-                       const uint32_t *__restrict__ npred, const uint32_t *__restrict__ npnext, DevState *st,
-                       uint64_t cap, uint64_t *__restrict__ skey, uint64_t *__restrict__ sval,
-                       uint32_t *__restrict__ snext, uint8_t *__restrict__ smeta) {
-    const uint32_t nnew = st->b_new;
-    if (nnew == 0) return;
-    if (st->nused + nnew > cap) return;
-    const uint32_t first = (uint32_t)st->nused;
-    for (uint32_t r = blockIdx.x * blockDim.x + threadIdx.x; r < nnew; r += gridDim.x * blockDim.x) {
+// writes new nodes r (grid-stride from r0 in steps of dr, r < nnew) to slots
+// first + r and links them (Algorithm 4 insertNode): a run of new nodes
+// sharing a predecessor is chained, and only its first node writes the
+// predecessor's successor.  Each node has one writer; no atomics.
+__device__ __forceinline__ void link_range(uint32_t r0, uint32_t dr, uint32_t first, uint32_t nnew,
+                                           const uint64_t *__restrict__ nk, const uint64_t *__restrict__ nv,
+                                           const uint32_t *__restrict__ npred, const uint32_t *__restrict__ npnext,
+                                           uint64_t *__restrict__ skey, uint64_t *__restrict__ sval,
+                                           uint32_t *__restrict__ snext, uint8_t *__restrict__ smeta,
+                                           const WriterCheck &wc, unsigned int *errors) {
+    for (uint32_t r = r0; r < nnew; r += dr) {
         const uint32_t slot = first + r;
         const uint32_t pr = npred[r];
+        wc.note(slot, WriterCheck::LINK, r, errors);
         skey[slot] = nk[r];
         sval[slot] = nv[r];
         smeta[slot] = META_LINK;
         snext[slot] = (r + 1 < nnew && npred[r + 1] == pr) ? slot + 1 : npnext[r];
         if (r == 0 || npred[r - 1] != pr) {
+            wc.note(pr, WriterCheck::LINK, r, errors);
             snext[pr] = slot;
             smeta[pr] = smeta[pr] | META_LINK;
         }
     }
 }
 
+// The host reserves room for every batch before it is enqueued; should that
+// ever fail, nothing is written past the capacity: the batch's new nodes are
+// dropped (k_batch_end flags ERR_CAPACITY, which fails the handle).
+__global__ void k_link(const uint64_t *__restrict__ nk, const uint64_t *__restrict__ nv,
+                       const uint32_t *__restrict__ npred, const uint32_t *__restrict__ npnext, DevState *st,
+                       uint64_t cap, uint64_t *__restrict__ skey, uint64_t *__restrict__ sval,
+                       uint32_t *__restrict__ snext, uint8_t *__restrict__ smeta, WriterCheck wc) {
+    const uint32_t nnew = st->b_new;
+    if (nnew == 0) return;
+    if (st->nused + nnew > cap) return;
+    link_range(blockIdx.x * blockDim.x + threadIdx.x, gridDim.x * blockDim.x, (uint32_t)st->nused, nnew, nk, nv,
+               npred, npnext, skey, sval, snext, smeta, wc, &st->errors);
+}
+
+// Self-test of the writer check's detection (no storage involved): on a
+// two-word shadow, one writer recording twice must pass and two writers of
+// one node under one tag must be caught.  out[0], out[1]: error bits of each.
+__global__ void k_writer_selftest(unsigned long long *shadow, unsigned int *out) {
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    shadow[0] = shadow[1] = 0;
+    out[0] = out[1] = 0;
+    const WriterCheck wc{shadow, 7};
+    wc.note(0, WriterCheck::APPLY, 5, &out[0]);
+    wc.note(0, WriterCheck::APPLY, 5, &out[0]);
+    wc.note(0, WriterCheck::LINK, 9, &out[0]);  // another phase: no conflict
+    wc.note(1, WriterCheck::APPLY, 5, &out[1]);
+    wc.note(1, WriterCheck::APPLY, 6, &out[1]);
+}
+
 __global__ void k_batch_begin(DevState *st, uint32_t n) {
     if (threadIdx.x != 0) return;
     st->b_writers = st->b_new = st->b_deletes = st->b_revives = st->b_hits = st->b_invalid = 0;
     st->b_n = n;
+    st->bar = 0;
 }
 
 // Sums the apply tiles' counts (batches with updates; one 256-thread block),
 // then folds the batch into the cumulative counters.
-__global__ __launch_bounds__(256) void k_batch_end(DevState *st, const uint4 *__restrict__ part, uint32_t ntiles,
-                                                   uint64_t cap) {
+__device__ __forceinline__ void batch_end_block(DevState *st, const uint4 *__restrict__ part, uint32_t ntiles,
+                                                uint64_t cap, const uint2 *__restrict__ dpart, uint32_t dgrid) {
     __shared__ uint32_t s_c[3][4];
+    __shared__ uint32_t s_d[2][4];
+    {
+        // the descent blocks' counts: hits of a batch without updates, and
+        // invalid queries
+        uint32_t h = 0, v = 0;
+        for (uint32_t b = threadIdx.x; b < dgrid; b += 256) {
+            const uint2 c = dpart[b];
+            h += c.x;
+            v += c.y;
+        }
+        h = wave_sum_u32(h);
+        v = wave_sum_u32(v);
+        if (lane_id() == 0) {
+            s_d[0][threadIdx.x >> 6] = h;
+            s_d[1][threadIdx.x >> 6] = v;
+        }
+        __syncthreads();
+        if (threadIdx.x == 0)
+            for (int w = 0; w < 4; w++) {
+                st->b_hits += s_d[0][w];
+                st->b_invalid += s_d[1][w];
+            }
+    }
     if (st->b_writers != 0) {
         uint32_t h = 0, d = 0, r = 0;
         for (uint32_t t = threadIdx.x; t < ntiles; t += 256) {
@@ -486,7 +583,7 @@ __global__ __launch_bounds__(256) void k_batch_end(DevState *st, const uint4 *__
     }
     if (threadIdx.x != 0) return;
     unsigned int nn = st->b_new;
-    if (st->nused + nn > cap) {  // k_link wrote nothing
+    if (st->nused + nn > cap) {  // the link step wrote nothing
         st->errors |= ERR_CAPACITY;
         nn = 0;
     }
@@ -505,12 +602,151 @@ __global__ __launch_bounds__(256) void k_batch_end(DevState *st, const uint4 *__
     st->revives += st->b_revives;
 }
 
+__global__ __launch_bounds__(256) void k_batch_end(DevState *st, const uint4 *__restrict__ part, uint32_t ntiles,
+                                                   uint64_t cap, const uint2 *__restrict__ dpart, uint32_t dgrid) {
+    batch_end_block(st, part, ntiles, cap, dpart, dgrid);
+}
+
+// ---------------------------------------------- the fused post-descent step --
+
+// Grid-wide barrier.  The launch is sized so that every block can be
+// resident at once (a quarter of what fits on each CU, and at most four such
+// launches run together), and nothing it waits for waits on it, so every
+// wait ends.  The spin is bounded anyway; running out flags ERR_BARRIER,
+// which fails the handle.
+__device__ __forceinline__ void grid_barrier(unsigned int *bar, unsigned int &round, unsigned int *errors) {
+    __syncthreads();
+    round++;
+    if (threadIdx.x == 0) {
+        __threadfence();  // this block's writes before the arrival
+        atomicAdd(bar, 1u);
+        const unsigned int target = round * gridDim.x;
+        for (uint32_t spins = 0;
+             __hip_atomic_load(bar, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target; spins++) {
+            if (spins > (1u << 24)) {
+                atomicOr(errors, ERR_BARRIER);
+                break;
+            }
+            __builtin_amdgcn_s_sleep(2);
+        }
+        __threadfence();  // the other blocks' writes after it
+    }
+    __syncthreads();
+}
+
+// The steps after the descent in one launch (grid-stride over tiles of
+// OTILE sorted queries, grid barriers between the steps): the segmented
+// last-writer scan (tile aggregates, their prefix), answers and in-place
+// updates with per-tile new-node counts, the prefix of those counts (slots
+// of the new nodes), the gather of new nodes in key order, their linking,
+// and the counters.  A batch without INSERT/DELETE only folds its counters.
+__global__ __launch_bounds__(OT) void k_post(const uint64_t *__restrict__ sk, const uint32_t *__restrict__ sidx,
+                                             const uint8_t *__restrict__ sop, const uint64_t *__restrict__ svin,
+                                             uint32_t n, const uint64_t *__restrict__ res_val,
+                                             const uint8_t *__restrict__ res_flags, const uint32_t *__restrict__ loc,
+                                             const uint32_t *__restrict__ locnext, uint64_t *__restrict__ skey,
+                                             uint64_t *__restrict__ sval, uint32_t *__restrict__ snext,
+                                             uint8_t *__restrict__ smeta, uint64_t cap,
+                                             uint64_t *__restrict__ out_vals, uint8_t *__restrict__ out_status,
+                                             Seg *__restrict__ agg, uint4 *__restrict__ part,
+                                             uint32_t *__restrict__ tilecnt, uint32_t *__restrict__ newflag,
+                                             int32_t *__restrict__ gw, uint64_t *__restrict__ nk,
+                                             uint64_t *__restrict__ nv, uint32_t *__restrict__ npred,
+                                             uint32_t *__restrict__ npnext, DevState *st, WriterCheck wc,
+                                             const uint2 *__restrict__ dpart, uint32_t dgrid) {
+    const uint32_t ntiles = (n + OTILE - 1) / OTILE;
+    if (st->b_writers == 0) {
+        if (blockIdx.x == 0) batch_end_block(st, part, 0, cap, dpart, dgrid);
+        return;
+    }
+    __shared__ Seg s_w[ONW];
+    __shared__ uint32_t s_u[ONW + 1];
+    unsigned int round = 0;
+    for (uint32_t t = blockIdx.x; t < ntiles; t += gridDim.x) own_reduce_tile(t, sk, sop, n, agg, s_w);
+    grid_barrier(&st->bar, round, &st->errors);
+    if (blockIdx.x == 0) own_prefix_block(agg, ntiles, s_w);
+    grid_barrier(&st->bar, round, &st->errors);
+    for (uint32_t t = blockIdx.x; t < ntiles; t += gridDim.x)
+        own_apply_tile(t, sk, sidx, sop, svin, n, agg, res_val, res_flags, loc, sval, smeta, out_vals, out_status,
+                       newflag, gw, part, st, wc, tilecnt, s_w);
+    grid_barrier(&st->bar, round, &st->errors);
+    if (blockIdx.x == 0) {
+        // slots of the new nodes: exclusive prefix of the tile counts
+        uint32_t carry = 0;
+        for (uint32_t b0 = 0; b0 < ntiles; b0 += OT * 4) {
+            uint32_t v[4], sum = 0;
+#pragma unroll
+            for (int k = 0; k < 4; k++) {
+                const uint32_t t = b0 + threadIdx.x * 4 + k;
+                v[k] = t < ntiles ? tilecnt[t] : 0u;
+                sum += v[k];
+            }
+            uint32_t tot;
+            uint32_t run = carry + block_excl_scan_u32<OT>(sum, s_u, &tot);
+#pragma unroll
+            for (int k = 0; k < 4; k++) {
+                const uint32_t t = b0 + threadIdx.x * 4 + k;
+                if (t < ntiles) tilecnt[t] = run;
+                run += v[k];
+            }
+            carry += tot;
+        }
+        if (threadIdx.x == 0) {
+            st->b_first = (uint32_t)st->nused;
+            st->b_new = st->nused + carry > cap ? 0u : carry;  // no room: nothing is linked (the end flags it)
+            if (st->nused + carry > cap) st->errors |= ERR_CAPACITY;
+        }
+    }
+    grid_barrier(&st->bar, round, &st->errors);
+    // new nodes in key order with their predecessors: tile offset plus the
+    // rank inside the tile
+    const uint32_t nnew = st->b_new;
+    if (nnew) {
+        for (uint32_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
+            const uint32_t base = t * OTILE + threadIdx.x * OI;
+            uint32_t f[OI], c = 0;
+#pragma unroll
+            for (int e = 0; e < OI; e++) {
+                f[e] = base + e < n ? newflag[base + e] : 0u;
+                c += f[e];
+            }
+            uint32_t tot;
+            uint32_t r = tilecnt[t] + block_excl_scan_u32<OT>(c, s_u, &tot);
+#pragma unroll
+            for (int e = 0; e < OI; e++) {
+                if (!f[e]) continue;
+                const uint32_t i = base + e;
+                nk[r] = sk[i];
+                nv[r] = svin[gw[i]];
+                npred[r] = loc[i];
+                npnext[r] = locnext[i];
+                r++;
+            }
+        }
+    }
+    grid_barrier(&st->bar, round, &st->errors);
+    link_range(blockIdx.x * OT + threadIdx.x, gridDim.x * OT, st->b_first, nnew, nk, nv, npred, npnext, skey, sval,
+               snext, smeta, wc, &st->errors);
+    // the counters: block 0, after its own share of the links (the others
+    // read only b_first and b_new, which the end does not change)
+    if (blockIdx.x == 0) {
+        __syncthreads();
+        batch_end_block(st, part, ntiles, cap, dpart, dgrid);
+    }
+}
+
 __global__ void k_count_inserts(const uint8_t *__restrict__ ops, const uint64_t *__restrict__ keys, uint32_t n,
                                 unsigned int *cnt) {
     const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
     uint32_t c = (i < n && ops[i] == PI_OP_INSERT && keys[i] != KEY_MAX) ? 1u : 0u;
+    __shared__ uint32_t s_c[4];  // 256-thread blocks: one atomic per block, not per wave
     c = wave_sum_u32(c);
-    if (lane_id() == 0 && c) atomicAdd(cnt, c);
+    if (lane_id() == 0) s_c[threadIdx.x >> 6] = c;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        const uint32_t t = s_c[0] + s_c[1] + s_c[2] + s_c[3];
+        if (t) atomicAdd(cnt, t);
+    }
 }
 
 __global__ void k_zero_u32(unsigned int *p) {
@@ -520,57 +756,57 @@ __global__ void k_zero_u32(unsigned int *p) {
 uint32_t blocks_for(uint64_t n, int t) { return (uint32_t)((n + t - 1) / t); }
 
 template <int MODE, int QPL, int DT>
-void launch_descend_q(Index &ix, hipStream_t s, const uint64_t *sk, const uint32_t *sidx, uint64_t n,
-                      uint64_t *out_vals, uint8_t *out_status, uint64_t *res_val, uint8_t *res_flags, uint32_t *loc,
-                      uint32_t *locnext, const uint8_t *ops, const uint64_t *vals, uint8_t *sop, uint64_t *svin) {
+uint32_t launch_descend_q(Index &ix, hipStream_t s, const uint64_t *sk, const uint32_t *sidx, uint64_t n,
+                          uint64_t *out_vals, uint8_t *out_status, uint64_t *res_val, uint8_t *res_flags, uint32_t *loc,
+                          uint32_t *locnext, const uint8_t *ops, const uint64_t *vals, uint8_t *sop, uint64_t *svin,
+                          uint2 *dpart) {
     const IndexDesc &d = ix.desc;
     const size_t lds = (size_t)d.lds_entries * 12;
     auto kern = k_descend<MODE, QPL, DT>;
     const uint32_t g = persistent_grid(ix, kern, DT, lds, blocks_for(n, DT * QPL));
     hipLaunchKernelGGL(kern, dim3(g), dim3(DT), lds, s, d, ix.arena_key.as<uint64_t>(), ix.arena_down.as<uint32_t>(),
                        ix.st.key.as<uint64_t>(), ix.st.val.as<uint64_t>(), ix.st.next.as<uint32_t>(),
-                       ix.st.meta.as<uint8_t>(), sk, sidx, (uint32_t)n, ix.dstate, out_vals, out_status, res_val,
-                       res_flags, loc, locnext, ops, vals, sop, svin);
+                       ix.st.meta.as<uint8_t>(), sk, sidx, (uint32_t)n, ix.dstate, dpart, out_vals, out_status,
+                       res_val, res_flags, loc, locnext, ops, vals, sop, svin);
     PI_LAUNCH_CHECK();
+    return g;
 }
 
 template <int MODE, int DT>
-void launch_descend_b(Index &ix, hipStream_t s, const uint64_t *sk, const uint32_t *sidx, uint64_t n,
-                      uint64_t *out_vals, uint8_t *out_status, uint64_t *res_val, uint8_t *res_flags, uint32_t *loc,
-                      uint32_t *locnext, const uint8_t *ops, const uint64_t *vals, uint8_t *sop, uint64_t *svin) {
+uint32_t launch_descend_b(Index &ix, hipStream_t s, const uint64_t *sk, const uint32_t *sidx, uint64_t n,
+                          uint64_t *out_vals, uint8_t *out_status, uint64_t *res_val, uint8_t *res_flags,
+                          uint32_t *loc, uint32_t *locnext, const uint8_t *ops, const uint64_t *vals, uint8_t *sop,
+                          uint64_t *svin, uint2 *dpart) {
     switch (ix.cfg.queries_per_lane) {
         case 2:
-            launch_descend_q<MODE, 2, DT>(ix, s, sk, sidx, n, out_vals, out_status, res_val, res_flags, loc, locnext,
-                ops, vals, sop, svin);
-            break;
+            return launch_descend_q<MODE, 2, DT>(ix, s, sk, sidx, n, out_vals, out_status, res_val, res_flags, loc,
+                                                 locnext, ops, vals, sop, svin, dpart);
         case 4:
-            launch_descend_q<MODE, 4, DT>(ix, s, sk, sidx, n, out_vals, out_status, res_val, res_flags, loc, locnext,
-                ops, vals, sop, svin);
-            break;
+            return launch_descend_q<MODE, 4, DT>(ix, s, sk, sidx, n, out_vals, out_status, res_val, res_flags, loc,
+                                                 locnext, ops, vals, sop, svin, dpart);
         default:
-            launch_descend_q<MODE, 1, DT>(ix, s, sk, sidx, n, out_vals, out_status, res_val, res_flags, loc, locnext,
-                ops, vals, sop, svin);
-            break;
+            return launch_descend_q<MODE, 1, DT>(ix, s, sk, sidx, n, out_vals, out_status, res_val, res_flags, loc,
+                                                 locnext, ops, vals, sop, svin, dpart);
     }
 }
 
+// Launches the descent; returns its grid (the number of per-block count
+// slots it writes in dpart).
 template <int MODE>
-void launch_descend(Index &ix, hipStream_t s, const uint64_t *sk, const uint32_t *sidx, uint64_t n,
-                    uint64_t *out_vals, uint8_t *out_status, uint64_t *res_val, uint8_t *res_flags, uint32_t *loc,
-                    uint32_t *locnext, const uint8_t *ops, const uint64_t *vals, uint8_t *sop, uint64_t *svin) {
+uint32_t launch_descend(Index &ix, hipStream_t s, const uint64_t *sk, const uint32_t *sidx, uint64_t n,
+                        uint64_t *out_vals, uint8_t *out_status, uint64_t *res_val, uint8_t *res_flags, uint32_t *loc,
+                        uint32_t *locnext, const uint8_t *ops, const uint64_t *vals, uint8_t *sop, uint64_t *svin,
+                        uint2 *dpart) {
     switch (ix.cfg.descent_block) {
         case 256:
-            launch_descend_b<MODE, 256>(ix, s, sk, sidx, n, out_vals, out_status, res_val, res_flags, loc, locnext,
-                ops, vals, sop, svin);
-            break;
+            return launch_descend_b<MODE, 256>(ix, s, sk, sidx, n, out_vals, out_status, res_val, res_flags, loc,
+                                               locnext, ops, vals, sop, svin, dpart);
         case 512:
-            launch_descend_b<MODE, 512>(ix, s, sk, sidx, n, out_vals, out_status, res_val, res_flags, loc, locnext,
-                ops, vals, sop, svin);
-            break;
+            return launch_descend_b<MODE, 512>(ix, s, sk, sidx, n, out_vals, out_status, res_val, res_flags, loc,
+                                               locnext, ops, vals, sop, svin, dpart);
         default:
-            launch_descend_b<MODE, 1024>(ix, s, sk, sidx, n, out_vals, out_status, res_val, res_flags, loc, locnext,
-                ops, vals, sop, svin);
-            break;
+            return launch_descend_b<MODE, 1024>(ix, s, sk, sidx, n, out_vals, out_status, res_val, res_flags, loc,
+                                                locnext, ops, vals, sop, svin, dpart);
     }
 }
 
@@ -589,6 +825,7 @@ void BatchWorkspace::ensure(uint64_t m) {
     const uint64_t nt = (c + OTILE - 1) / OTILE + 1;
     agg.ensure(nt * sizeof(Seg));
     part.ensure(nt * sizeof(uint4));
+    dpart.ensure(DPART * sizeof(uint2));
     sop.ensure(c);
     svin.ensure(c * 8);
     nk.ensure(c * 8);
@@ -600,7 +837,7 @@ void BatchWorkspace::ensure(uint64_t m) {
 
 void BatchWorkspace::release() {
     DevBuf *all[] = {&res_val, &res_flags, &loc, &locnext, &newflag, &newpos, &gw, &agg,
-                     &part, &nk, &nv, &npred, &npnext, &sop, &svin};
+                     &part, &dpart, &nk, &nv, &npred, &npnext, &sop, &svin};
     for (DevBuf *b : all) b->release();
     n = 0;
 }
@@ -648,38 +885,69 @@ void execute_batch(Index &ix, const BatchBuffers &buf, const uint8_t *ops, const
     mark(1);
 
     BatchWorkspace &w = buf.bws;
-    launch_descend<0>(ix, s, sk, sidx, n, out_vals, out_status, w.res_val.as<uint64_t>(), w.res_flags.as<uint8_t>(),
-                      w.loc.as<uint32_t>(), w.locnext.as<uint32_t>(), ops, vals, w.sop.as<uint8_t>(),
-                      w.svin.as<uint64_t>());
+    const WriterCheck wc = writer_check(ix, 1);
+    const uint32_t dgrid = launch_descend<0>(ix, s, sk, sidx, n, out_vals, out_status, w.res_val.as<uint64_t>(),
+                                             w.res_flags.as<uint8_t>(), w.loc.as<uint32_t>(), w.locnext.as<uint32_t>(),
+                                             ops, vals, w.sop.as<uint8_t>(), w.svin.as<uint64_t>(),
+                                             w.dpart.as<uint2>());
+    if (dgrid > BatchWorkspace::DPART) throw Error{PI_ERR_DEVICE, "internal error: descent grid above its count slots"};
     PI_LAUNCH_CHECK();
     mark(2);
 
     const uint32_t otiles = blocks_for(n, OTILE);
     Seg *agg = w.agg.as<Seg>();
-    hipLaunchKernelGGL(k_own_reduce, dim3(otiles), dim3(OT), 0, s, sk, w.sop.as<uint8_t>(), (uint32_t)n, st, agg);
-    hipLaunchKernelGGL(k_own_prefix, dim3(1), dim3(OT), 0, s, agg, otiles, st);
-    hipLaunchKernelGGL(k_own_apply, dim3(otiles), dim3(OT), 0, s, sk, sidx, w.sop.as<uint8_t>(),
-                       w.svin.as<uint64_t>(), (uint32_t)n, agg,
-                       w.res_val.as<uint64_t>(), w.res_flags.as<uint8_t>(), w.loc.as<uint32_t>(),
-                       ix.st.val.as<uint64_t>(), ix.st.meta.as<uint8_t>(), out_vals, out_status,
-                       w.newflag.as<uint32_t>(), w.gw.as<int32_t>(), w.part.as<uint4>(), st);
-    PI_LAUNCH_CHECK();
-    mark(3);
-    exclusive_scan_u32(buf.scan, w.newflag.as<uint32_t>(), w.newpos.as<uint32_t>(), n, &st->b_new,
-                       &st->b_writers, s);
-    // grid-stride launches of at most 8 blocks per CU: batches without
-    // updates leave at once, and a smaller grid dispatches faster
-    const uint32_t lgrid = std::min<uint32_t>(blocks_for(n, 256), (uint32_t)ix.num_cus * 8);
-    hipLaunchKernelGGL(k_new_gather, dim3(lgrid), dim3(256), 0, s, sk, w.svin.as<uint64_t>(),
-                       w.newflag.as<uint32_t>(), w.newpos.as<uint32_t>(), w.gw.as<int32_t>(), w.loc.as<uint32_t>(),
-                       w.locnext.as<uint32_t>(), (uint32_t)n, st, w.nk.as<uint64_t>(), w.nv.as<uint64_t>(),
-                       w.npred.as<uint32_t>(), w.npnext.as<uint32_t>());
-    hipLaunchKernelGGL(k_link, dim3(lgrid), dim3(256), 0, s, w.nk.as<uint64_t>(), w.nv.as<uint64_t>(),
-                       w.npred.as<uint32_t>(), w.npnext.as<uint32_t>(), st, ix.st.cap, ix.st.key.as<uint64_t>(),
-                       ix.st.val.as<uint64_t>(), ix.st.next.as<uint32_t>(), ix.st.meta.as<uint8_t>());
-    hipLaunchKernelGGL(k_batch_end, dim3(1), dim3(256), 0, s, st, (const uint4 *)w.part.as<uint4>(), otiles,
-                       ix.st.cap);
-    PI_LAUNCH_CHECK();
+    // The steps after the descent in one launch with grid barriers; under
+    // graph capture as separate kernels (a replay gives no say over which
+    // other kernels share the device).
+    hipStreamCaptureStatus cap_status = hipStreamCaptureStatusNone;
+    PI_HIP(hipStreamIsCapturing(s, &cap_status));
+    if (cap_status == hipStreamCaptureStatusNone) {
+        static int occ = 0;
+        if (!occ) {
+            PI_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, k_post, OT, 0));
+            if (occ < 1) throw Error{PI_ERR_DEVICE, "fused post-descent step cannot be resident"};
+        }
+        // a quarter of the resident blocks: up to four of these launches run
+        // at once (the lane streams of a group call), and each must be able
+        // to become resident while the others hold theirs
+        const uint32_t per_cu = (uint32_t)std::max(1, occ / 4);
+        const uint32_t grid = std::max<uint32_t>(1, std::min<uint32_t>(otiles, (uint32_t)ix.num_cus * per_cu));
+        hipLaunchKernelGGL(k_post, dim3(grid), dim3(OT), 0, s, sk, sidx, w.sop.as<uint8_t>(), w.svin.as<uint64_t>(),
+                           (uint32_t)n, w.res_val.as<uint64_t>(), w.res_flags.as<uint8_t>(), w.loc.as<uint32_t>(),
+                           w.locnext.as<uint32_t>(), ix.st.key.as<uint64_t>(), ix.st.val.as<uint64_t>(),
+                           ix.st.next.as<uint32_t>(), ix.st.meta.as<uint8_t>(), ix.st.cap, out_vals, out_status, agg,
+                           w.part.as<uint4>(), w.newpos.as<uint32_t>() /* per-tile new-node counts, then their prefix */,
+                           w.newflag.as<uint32_t>(), w.gw.as<int32_t>(), w.nk.as<uint64_t>(), w.nv.as<uint64_t>(),
+                           w.npred.as<uint32_t>(), w.npnext.as<uint32_t>(), st, wc, (const uint2 *)w.dpart.as<uint2>(),
+                           dgrid);
+        PI_LAUNCH_CHECK();
+        mark(3);  // the fused step counts as the ownership stage
+    } else {
+        hipLaunchKernelGGL(k_own_reduce, dim3(otiles), dim3(OT), 0, s, sk, w.sop.as<uint8_t>(), (uint32_t)n, st, agg);
+        hipLaunchKernelGGL(k_own_prefix, dim3(1), dim3(OT), 0, s, agg, otiles, st);
+        hipLaunchKernelGGL(k_own_apply, dim3(otiles), dim3(OT), 0, s, sk, sidx, w.sop.as<uint8_t>(),
+                           w.svin.as<uint64_t>(), (uint32_t)n, agg,
+                           w.res_val.as<uint64_t>(), w.res_flags.as<uint8_t>(), w.loc.as<uint32_t>(),
+                           ix.st.val.as<uint64_t>(), ix.st.meta.as<uint8_t>(), out_vals, out_status,
+                           w.newflag.as<uint32_t>(), w.gw.as<int32_t>(), w.part.as<uint4>(), st, wc);
+        PI_LAUNCH_CHECK();
+        mark(3);
+        exclusive_scan_u32(buf.scan, w.newflag.as<uint32_t>(), w.newpos.as<uint32_t>(), n, &st->b_new,
+                           &st->b_writers, s);
+        // grid-stride launches of at most 8 blocks per CU: batches without
+        // updates leave at once, and a smaller grid dispatches faster
+        const uint32_t lgrid = std::min<uint32_t>(blocks_for(n, 256), (uint32_t)ix.num_cus * 8);
+        hipLaunchKernelGGL(k_new_gather, dim3(lgrid), dim3(256), 0, s, sk, w.svin.as<uint64_t>(),
+                           w.newflag.as<uint32_t>(), w.newpos.as<uint32_t>(), w.gw.as<int32_t>(), w.loc.as<uint32_t>(),
+                           w.locnext.as<uint32_t>(), (uint32_t)n, st, w.nk.as<uint64_t>(), w.nv.as<uint64_t>(),
+                           w.npred.as<uint32_t>(), w.npnext.as<uint32_t>());
+        hipLaunchKernelGGL(k_link, dim3(lgrid), dim3(256), 0, s, w.nk.as<uint64_t>(), w.nv.as<uint64_t>(),
+                           w.npred.as<uint32_t>(), w.npnext.as<uint32_t>(), st, ix.st.cap, ix.st.key.as<uint64_t>(),
+                           ix.st.val.as<uint64_t>(), ix.st.next.as<uint32_t>(), ix.st.meta.as<uint8_t>(), wc);
+        hipLaunchKernelGGL(k_batch_end, dim3(1), dim3(256), 0, s, st, (const uint4 *)w.part.as<uint4>(), otiles,
+                           ix.st.cap, (const uint2 *)w.dpart.as<uint2>(), dgrid);
+        PI_LAUNCH_CHECK();
+    }
     mark(4);
     if (ix.prof.on) {
         rec.n = 5;
@@ -780,7 +1048,8 @@ std::vector<uint64_t> fingerprint(const Index &ix) {
     add(ix.scanws.tiles);
     const BatchWorkspace &w = ix.bws;
     add(w.res_val), add(w.res_flags), add(w.loc), add(w.locnext), add(w.newflag), add(w.newpos), add(w.gw);
-    add(w.agg), add(w.part), add(w.nk), add(w.nv), add(w.npred), add(w.npnext), add(w.sop), add(w.svin);
+    add(w.agg), add(w.part), add(w.dpart), add(w.nk), add(w.nv), add(w.npred), add(w.npnext), add(w.sop),
+        add(w.svin);
     for (const DevBuf &b : ix.stage) add(b);
     f.push_back((uint64_t)(uintptr_t)ix.dstate);
     const uint64_t *d = reinterpret_cast<const uint64_t *>(&ix.desc);
@@ -853,10 +1122,42 @@ void execute_batch_graph(Index &ix, const uint8_t *ops, const uint64_t *keys, co
     PI_LAUNCH_CHECK();
 }
 
+WriterCheck writer_check(Index &ix, uint32_t units) {
+    WriterCheck wc{nullptr, 0};
+    if (!ix.cfg.check_writers) return wc;
+    const size_t need = (size_t)(ix.st.cap + STORAGE_SLACK) * sizeof(unsigned long long);
+    if (ix.owner.bytes < need || !ix.owner.p) {
+        ix.owner.ensure(need);
+        PI_HIP(hipMemset(ix.owner.p, 0, ix.owner.bytes));  // tag 0: no writer yet
+    }
+    wc.owner = ix.owner.as<unsigned long long>();
+    if (ix.writer_unit + units >= (1u << 30)) {  // units wrap: forget every recorded writer
+        ix.writer_unit = 0;
+        PI_HIP(hipMemset(ix.owner.p, 0, ix.owner.bytes));
+    }
+    wc.unit = ix.writer_unit + 1;
+    ix.writer_unit += units;
+    return wc;
+}
+
+bool writer_selftest(Index &ix, hipStream_t s, uint32_t *same_writer_err, uint32_t *two_writer_err) {
+    ix.tmp[6].ensure(64);
+    unsigned long long *shadow = ix.tmp[6].as<unsigned long long>();
+    unsigned int *out = reinterpret_cast<unsigned int *>(shadow + 2);
+    hipLaunchKernelGGL(k_writer_selftest, dim3(1), dim3(64), 0, s, shadow, out);
+    PI_LAUNCH_CHECK();
+    PI_HIP(hipMemcpyAsync(ix.hcounts, out, 8, hipMemcpyDeviceToHost, s));
+    PI_HIP(hipStreamSynchronize(s));
+    const uint32_t *h = reinterpret_cast<const uint32_t *>(ix.hcounts);
+    *same_writer_err = h[0];
+    *two_writer_err = h[1];
+    return true;
+}
+
 void debug_interceptions(Index &ix, const uint64_t *keys, uint64_t n, uint64_t *icpt_keys, uint8_t *is_head,
                          hipStream_t s) {
     launch_descend<1>(ix, s, keys, nullptr, n, icpt_keys, is_head, nullptr, nullptr, nullptr, nullptr, nullptr,
-                      nullptr, nullptr, nullptr);
+                      nullptr, nullptr, nullptr, nullptr);
 }
 
 }  // namespace pi

@@ -58,7 +58,7 @@ __global__ __launch_bounds__(BT) void k_level_scatter(const uint64_t *__restrict
                                                       uint64_t seed, uint32_t l2p, uint32_t maxh,
                                                       const uint32_t *__restrict__ tileoff, uint32_t ntiles,
                                                       IndexDesc desc, uint64_t *__restrict__ lkey,
-                                                      uint32_t *__restrict__ ldown) {
+                                                      uint32_t *__restrict__ ldown, uint32_t first_level) {
     __shared__ uint32_t s_cnt[BNW][MAX_LEVELS];
     __shared__ uint32_t s_toff[MAX_LEVELS];
     const int tid = threadIdx.x;
@@ -85,7 +85,7 @@ __global__ __launch_bounds__(BT) void k_level_scatter(const uint64_t *__restrict
     // keys of this wave per level
 #pragma unroll
     for (int r = 0; r < BI; r++) {
-        for (uint32_t l = 2;; l++) {
+        for (uint32_t l = first_level;; l++) {
             const uint64_t m = ballot64(h[r] >= l);
             if (!m) break;
             if (lane == 0) s_cnt[w][l] += (uint32_t)__popcll(m);
@@ -104,8 +104,10 @@ __global__ __launch_bounds__(BT) void k_level_scatter(const uint64_t *__restrict
 #pragma unroll
     for (int r = 0; r < BI; r++) {
         const uint32_t b = wbase + r * 64 + lane;
-        uint32_t prev = slots ? (b < nbase ? slots[b] : 0u) : 1 + b;  // storage slot: down pointer of level 2
-        for (uint32_t l = 2;; l++) {
+        // down pointer on first_level: the storage slot (level 2) or the
+        // position one level below
+        uint32_t prev = slots ? (b < nbase ? slots[b] : 0u) : 1 + b;
+        for (uint32_t l = first_level;; l++) {
             const bool in = h[r] >= l;
             const uint64_t m = ballot64(in);
             if (!m) break;
@@ -343,8 +345,8 @@ void select_lds_levels(const Index &ix, IndexDesc &d) {
 // pointers from slots, or 1 + position when slots is null) into the arena.
 // Asynchronous on s; cnt is per-tile scratch.
 void scatter_levels(const Index &ix, const uint64_t *keys, const uint32_t *slots, uint64_t n, const IndexDesc &d,
-                    DevBuf &cnt, DevBuf &tot, DevBuf &akey, DevBuf &adown, hipStream_t s) {
-    if (n == 0 || d.top < 2) return;
+                    DevBuf &cnt, DevBuf &tot, DevBuf &akey, DevBuf &adown, hipStream_t s, uint32_t first_level) {
+    if (n == 0 || d.top < (int)first_level) return;
     const uint32_t ntiles = blocks_for(n, BTILE);
     cnt.ensure((size_t)MAX_LEVELS * ntiles * sizeof(uint32_t));
     tot.ensure(MAX_LEVELS * sizeof(uint32_t));
@@ -354,14 +356,41 @@ void scatter_levels(const Index &ix, const uint64_t *keys, const uint32_t *slots
     column_scan(cnt.as<uint32_t>(), MAX_LEVELS, ntiles, tot.as<uint32_t>(), s);
     hipLaunchKernelGGL(k_level_scatter, dim3(ntiles), dim3(BT), 0, s, keys, slots, (uint32_t)n, ix.cfg.height_seed,
                        ix.cfg.log2_inv_p, ix.cfg.max_height, cnt.as<uint32_t>(), ntiles, d, akey.as<uint64_t>(),
-                       adown.as<uint32_t>());
+                       adown.as<uint32_t>(), first_level);
     hipLaunchKernelGGL(k_level_pad, dim3(MAX_LEVELS), dim3(64), 0, s, d, akey.as<uint64_t>(), adown.as<uint32_t>());
+    PI_LAUNCH_CHECK();
+}
+
+void level_totals(Index &ix, const uint64_t *keys, uint64_t n, DevBuf &cnt, DevBuf &tot, uint32_t *level_n,
+                  hipStream_t s) {
+    for (int l = 0; l < MAX_LEVELS; l++) level_n[l] = 0;
+    if (n == 0) return;
+    const uint32_t ntiles = blocks_for(n, BTILE);
+    cnt.ensure((size_t)MAX_LEVELS * ntiles * sizeof(uint32_t));
+    tot.ensure(MAX_LEVELS * sizeof(uint32_t));
+    hipLaunchKernelGGL(k_height_count, dim3(ntiles), dim3(BT), 0, s, keys, (uint32_t)n, ix.cfg.height_seed,
+                       ix.cfg.log2_inv_p, ix.cfg.max_height, cnt.as<uint32_t>(), ntiles);
+    PI_LAUNCH_CHECK();
+    column_scan(cnt.as<uint32_t>(), MAX_LEVELS, ntiles, tot.as<uint32_t>(), s);
+    uint32_t *h = reinterpret_cast<uint32_t *>(ix.hcounts);
+    PI_HIP(hipMemcpyAsync(h, tot.p, MAX_LEVELS * sizeof(uint32_t), hipMemcpyDeviceToHost, s));
+    PI_HIP(hipStreamSynchronize(s));
+    for (int l = 0; l < MAX_LEVELS; l++) level_n[l] = h[l];
+}
+
+void pad_levels(Index &ix, const IndexDesc &d, hipStream_t s) {
+    hipLaunchKernelGGL(k_level_pad, dim3(MAX_LEVELS), dim3(64), 0, s, d, ix.arena_key.as<uint64_t>(),
+                       ix.arena_down.as<uint32_t>());
     PI_LAUNCH_CHECK();
 }
 
 // Builds every index level from base slots 1..nbase.  Waits for the level
 // sizes.
 static void build_levels(Index &ix, hipStream_t s) {
+    if (ix.cfg.rebuild_policy == PI_REBUILD_SLICES) {
+        slice_build(ix, s);
+        return;
+    }
     const uint64_t nb = ix.nbase;
     uint32_t level_n[MAX_LEVELS] = {};
     if (nb > 0) {
@@ -395,7 +424,7 @@ static void build_levels(Index &ix, hipStream_t s) {
         hipLaunchKernelGGL(k_level_scatter, dim3(ntiles), dim3(BT), 0, s, ix.st.key.as<uint64_t>() + 1, nullptr,
                            (uint32_t)nb, ix.cfg.height_seed, ix.cfg.log2_inv_p, ix.cfg.max_height,
                            ix.tmp[8].as<uint32_t>(), ntiles, d, ix.arena_key.as<uint64_t>(),
-                           ix.arena_down.as<uint32_t>());
+                           ix.arena_down.as<uint32_t>(), 2u);
         hipLaunchKernelGGL(k_level_pad, dim3(MAX_LEVELS), dim3(64), 0, s, d, ix.arena_key.as<uint64_t>(),
                            ix.arena_down.as<uint32_t>());
         PI_LAUNCH_CHECK();

@@ -51,6 +51,7 @@ __global__ __launch_bounds__(SBT) void k_group_batches(const GroupItem *__restri
             b.out_vals += c;
             b.out_status += c;
             b.n = n - c < SB_MAX ? n - c : SB_MAX;
+            b.unit = g.b.unit + c / SB_MAX;  // each chunk is a batch of its own for the writer check
             block_batch(g.v, b, s_raw);
         }
     }
@@ -131,15 +132,22 @@ void settle_previous(pi_group *g, hipStream_t s) {
         const uint32_t pol = ix.cfg.rebuild_policy;
         if (pol == PI_REBUILD_NEVER) continue;
         const double thr = rebuild_threshold(ix);
-        if (pol == PI_REBUILD_BACKGROUND) {
-            bg_advance(ix);
+        if (pol == PI_REBUILD_BACKGROUND || pol == PI_REBUILD_SLICES) {
+            if (pol == PI_REBUILD_BACKGROUND) bg_advance(ix);
             const double compact = (ix.cfg.compact_percent ? ix.cfg.compact_percent : 100) / 100.0 *
                                    (double)std::max<uint64_t>(ix.nbase, 1);
             if ((double)st.changes >= std::max(compact, thr)) {
                 rebuild(ix, s);
                 ix.ring_seen = ix.ring_head;
             } else if (st.changes >= ix.changes_base && (double)(st.changes - ix.changes_base) >= thr) {
-                bg_start(ix, st, s);
+                if (pol == PI_REBUILD_BACKGROUND) {
+                    bg_start(ix, st, s);
+                } else if (slice_round(ix, st.nused, s)) {
+                    ix.changes_base = st.changes;
+                } else {
+                    rebuild(ix, s);
+                    ix.ring_seen = ix.ring_head;
+                }
             }
             continue;
         }
@@ -197,9 +205,12 @@ void run_group(pi_group *g, pi_index *const *indices, const pi_batch *batches, u
         for (uint32_t k = 0; k < nf; k++) {
             const pi_batch &b = batches[fused[k]];
             GroupItem &it = g->h_items[k];
-            it.v = index_view(indices[fused[k]]->ix);
+            Index &fx = indices[fused[k]]->ix;
+            const WriterCheck wc = writer_check(fx, (uint32_t)((b.n + SB_MAX - 1) / SB_MAX));
+            it.v = index_view(fx);
+            it.v.owner = wc.owner;
             it.b = BatchView{ops_override ? ops_override : b.d_ops, b.d_keys, b.d_values, (uint32_t)b.n,
-                             b.d_out_values, b.d_out_status};
+                             b.d_out_values, b.d_out_status, wc.unit};
         }
         g->d_items.ensure((size_t)g->cap_items * sizeof(GroupItem));
         g->d_counter.ensure(64);

@@ -25,7 +25,9 @@ struct Storage {
 
 struct BatchWorkspace {
     DevBuf res_val, res_flags, loc, locnext, newflag, newpos, gw, agg;
-    DevBuf part;       // per apply tile: hits, deletes, revives (summed at the batch's end)
+    DevBuf part;       // per apply tile: hits, deletes, revives, new nodes (summed at the batch's end)
+    DevBuf dpart;      // per descent block: hits, invalid queries (summed at the batch's end)
+    static constexpr uint32_t DPART = 8192;  // count slots of the descent (its grid is at most this)
     DevBuf nk, nv, npred, npnext;
     DevBuf sop, svin;  // op and inserted value of each sorted query (batches with updates)
     uint64_t n = 0;
@@ -46,6 +48,17 @@ struct Profiler {
     hipEvent_t take();
     void drain(bool wait);  // folds completed records into acc
     void release();
+};
+
+// Sliced layout of the lower index levels (rebuild policy SLICES): slices of
+// SL_B consecutive base slots; on levels 2..ls slice j owns entries
+// [1 + j*cap[l], 1 + (j+1)*cap[l]) of the level (its keys, then a gap).
+constexpr uint32_t SL_LOG = 12;
+constexpr uint32_t SL_B = 1u << SL_LOG;
+struct SliceLayout {
+    uint32_t S;                  // slices
+    int32_t ls;                  // highest sliced level
+    uint32_t cap[MAX_LEVELS];    // entries per segment on level l <= ls
 };
 
 struct Index {
@@ -127,8 +140,25 @@ struct Index {
         uint64_t done = 0;
     } bg;
     uint32_t base_level_n[MAX_LEVELS] = {};  // level sizes of the base region alone
+    // slice repair (rebuild policy SLICES)
+    struct Slices {
+        bool on = false;
+        SliceLayout lay{};
+        DevBuf cnt;      // u32 [MAX_LEVELS][S]: keys of each segment
+        DevBuf first;    // u64 [S]: first key of each slice (slice 0: 0)
+        DevBuf dirty;    // u32 [S]: rewritten by the last round
+        DevBuf offs, offs2, misc, ukey, upos, okeys, tcnt, ttot;
+        SortWorkspace sortws;
+        MsdWorkspace msdws;
+        uint64_t round_first = 0;  // new nodes from this slot on are not indexed yet
+        uint64_t rounds = 0, repaired = 0;
+        uint64_t arena_used = 0;
+        uint64_t real_n[MAX_LEVELS] = {};  // keys per level (without gaps)
+    } slc;
     uint64_t changes_base = 0;     // DevState::changes when the index layer was last rebuilt
     DevBuf stage[5];               // graph inputs/outputs: ops, keys, values, answer values, answer status
+    DevBuf owner;                  // writer-check shadow: u64 per storage slot (check_writers)
+    uint32_t writer_unit = 0;      // writer-check units handed out
     hipStream_t cap_stream = nullptr;
     uint64_t *hcounts = nullptr;   // pinned: level totals etc.
     int num_cus = 256;
@@ -178,6 +208,13 @@ void execute_batch_graph(Index &ix, const uint8_t *ops, const uint64_t *keys, co
                          uint64_t *out_vals, uint8_t *out_status, hipStream_t s);
 void release_graphs(Index &ix);
 
+// The writer check of the next `units` batch units (an off check when
+// check_writers is 0); sizes and clears the shadow when the storage grew.
+WriterCheck writer_check(Index &ix, uint32_t units);
+// Runs the check's detection on a private two-word shadow: error bits of one
+// writer recording twice, and of two writers of one node (synchronises s).
+bool writer_selftest(Index &ix, hipStream_t s, uint32_t *same_writer_err, uint32_t *two_writer_err);
+
 // small.hip: the whole batch (n <= 4096) in one workgroup, one launch
 void execute_batch_small(Index &ix, const uint8_t *ops, const uint64_t *keys, const uint64_t *vals, uint64_t n,
                          uint64_t *out_vals, uint8_t *out_status, hipStream_t s);
@@ -214,8 +251,21 @@ void serve_loop(const double *arrival_us, uint64_t n, const ServePlan &plan, hip
 // build.hip: level descriptor from sizes; level arrays from sorted keys
 IndexDesc make_desc(const Index &ix, const uint32_t *level_n, uint64_t *arena_entries);
 void select_lds_levels(const Index &ix, IndexDesc &d);
+// Writes keys[0 .. n) into the levels first_level.. their towers reach; the
+// down pointer on first_level is slots[i] (or 1 + i when slots is null).
 void scatter_levels(const Index &ix, const uint64_t *keys, const uint32_t *slots, uint64_t n, const IndexDesc &d,
-                    DevBuf &cnt, DevBuf &tot, DevBuf &akey, DevBuf &adown, hipStream_t s);
+                    DevBuf &cnt, DevBuf &tot, DevBuf &akey, DevBuf &adown, hipStream_t s, uint32_t first_level = 2);
+// Keys per level (height >= l) of keys[0 .. n) into level_n (synchronises).
+void level_totals(Index &ix, const uint64_t *keys, uint64_t n, DevBuf &cnt, DevBuf &tot, uint32_t *level_n,
+                  hipStream_t s);
+// Head entries and +infinity pads of every level of d.
+void pad_levels(Index &ix, const IndexDesc &d, hipStream_t s);
+
+// slices.hip: slice repair (rebuild policy SLICES)
+void slice_build(Index &ix, hipStream_t s);                 // full build of the sliced layout (synchronises)
+bool slice_round(Index &ix, uint64_t snap, hipStream_t s);  // repair round; false: a segment would overflow
+uint64_t slice_export_level(Index &ix, int l, uint64_t *okey, uint32_t *odown, uint64_t cap, hipStream_t s);
+void slice_release(Index &ix);
 
 // bgrebuild.hip: background index rebuild (rebuild policy BACKGROUND)
 void bg_start(Index &ix, const DevState &latest, hipStream_t s);  // enqueues the counting step

@@ -130,6 +130,7 @@ __global__ __launch_bounds__(MT) void k_make_map(const uint64_t *__restrict__ pa
         if (st) {
             st->b_writers = st->b_new = st->b_deletes = st->b_revives = st->b_hits = st->b_invalid = 0;
             st->b_n = n;
+            st->bar = 0;
         }
     }
 }

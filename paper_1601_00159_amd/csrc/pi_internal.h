@@ -51,11 +51,15 @@ struct DevState {
     unsigned int b_n;
     unsigned int b_pad;          // padding queries of a graph replay (not counted)
     unsigned int errors;         // ERR_* bits of internal consistency failures (must stay 0)
+    unsigned int bar;            // grid barrier of the fused post-descent step (cleared per batch)
+    unsigned int b_first;        // first storage slot of the batch's new nodes (fused step)
 };
 
 // DevState::errors bits
 constexpr unsigned int ERR_WALK = 1;      // a storage walk passed its bound (the list is malformed)
 constexpr unsigned int ERR_CAPACITY = 2;  // new nodes would have passed the storage capacity (none written)
+constexpr unsigned int ERR_WRITERS = 4;   // a storage node had two writers in one phase of a batch (checked mode)
+constexpr unsigned int ERR_BARRIER = 8;   // a grid barrier outwaited its bound (blocks not co-resident)
 
 // Host message for DevState::errors (empty when 0).
 inline std::string device_error_text(unsigned int e) {
@@ -63,8 +67,42 @@ inline std::string device_error_text(unsigned int e) {
     if (e & ERR_WALK) m += "internal error: storage walk exceeded its bound";
     if (e & ERR_CAPACITY) m += std::string(m.empty() ? "" : "; ") +
                                "internal error: new nodes would pass the storage capacity (not written)";
+    if (e & ERR_WRITERS) m += std::string(m.empty() ? "" : "; ") +
+                              "internal error: a storage node had two writers in one phase of a batch";
+    if (e & ERR_BARRIER) m += std::string(m.empty() ? "" : "; ") +
+                              "internal error: a grid barrier did not complete";
     return m;
 }
+
+// Checked mode of the single-writer invariant (Section 3.2.4: after the
+// hand-over every storage node that changes has exactly one writer).  Every
+// storage write of a batch also records its writer in a shadow word per node:
+// tag = (unit << 2) | phase, writer = the owning query's sorted position (the
+// apply phase) or the new node's rank (the link phase).  A second, different
+// writer of one node under one tag sets ERR_WRITERS.  The phases of a batch
+// run one after the other (separate kernels, or separated by a workgroup
+// barrier), so only writers within one phase could race.
+struct WriterCheck {
+    unsigned long long *owner;  // u64 per storage slot, null when the check is off
+    uint32_t unit;              // batch (or workgroup chunk) number, < 2^30
+    enum : uint32_t { APPLY = 1, LINK = 2 };
+    __device__ __forceinline__ void note(uint32_t node, uint32_t phase, uint32_t who, unsigned int *errors) const {
+        if (!owner) return;
+        const uint32_t tag = (unit << 2) | phase;
+        const unsigned long long want = ((unsigned long long)tag << 32) | who;
+        unsigned long long old = owner[node];
+        for (int i = 0; i < 64; i++) {  // a legal pattern needs one or two rounds
+            if ((uint32_t)(old >> 32) == tag) {
+                if ((uint32_t)old != who) atomicOr(errors, ERR_WRITERS);
+                return;
+            }
+            const unsigned long long prev = atomicCAS(&owner[node], old, want);
+            if (prev == old) return;
+            old = prev;
+        }
+        atomicOr(errors, ERR_WRITERS);
+    }
+};
 
 // ---------------------------------------------------------------------------
 // wave64 helpers

@@ -24,6 +24,7 @@ struct IndexView {
     uint8_t *smeta;
     DevState *st;
     uint64_t cap;  // storage capacity: new nodes never go past it
+    unsigned long long *owner;  // writer-check shadow (null: check off)
 };
 
 struct BatchView {
@@ -33,6 +34,7 @@ struct BatchView {
     uint32_t n;
     uint64_t *out_vals;
     uint8_t *out_status;
+    uint32_t unit;  // writer-check unit of the first workgroup chunk
 };
 
 // Index entries of the upper levels a workgroup stages in LDS next to its
@@ -62,6 +64,7 @@ inline IndexView index_view(const Index &ix) {
     v.smeta = ix.st.meta.as<uint8_t>();
     v.st = ix.dstate;
     v.cap = ix.st.cap;
+    v.owner = nullptr;
     return v;
 }
 
@@ -145,6 +148,7 @@ __device__ __forceinline__ void block_batch(const IndexView &v, const BatchView 
     unsigned int *s_cnt = reinterpret_cast<unsigned int *>(lds + SmallLds::misc_off + 512);  // counters
     const uint32_t n = b.n;
     const uint32_t tid = threadIdx.x;
+    const WriterCheck wc{v.owner, b.unit};
 
     // ---- order: bitonic sort of (key, position) over the next power of two
     uint32_t m = 64;
@@ -264,6 +268,7 @@ __device__ __forceinline__ void block_batch(const IndexView &v, const BatchView 
             const uint32_t node = f[e].node;
             if (b.ops[jd] == PI_OP_INSERT) {
                 if (f[e].exists) {
+                    wc.note(node, WriterCheck::APPLY, i, &v.st->errors);
                     v.sval[node] = b.vals[jd];
                     if (!f[e].live) {
                         v.smeta[node] = v.smeta[node] & (uint8_t)~META_DEL;
@@ -274,6 +279,7 @@ __device__ __forceinline__ void block_batch(const IndexView &v, const BatchView 
                     newv[e] = b.vals[jd];
                 }
             } else if (f[e].exists && f[e].live) {
+                wc.note(node, WriterCheck::APPLY, i, &v.st->errors);
                 v.smeta[node] = v.smeta[node] | META_DEL;
                 dels++;
             }
@@ -296,6 +302,7 @@ __device__ __forceinline__ void block_batch(const IndexView &v, const BatchView 
         for (int e = 0; e < SBI; e++) {
             if (!newf[e]) continue;
             const uint64_t slot = base + r;
+            wc.note((uint32_t)slot, WriterCheck::LINK, r, &v.st->errors);
             v.skey[slot] = q[e];
             v.sval[slot] = newv[e];
             v.smeta[slot] = META_LINK;
@@ -310,6 +317,7 @@ __device__ __forceinline__ void block_batch(const IndexView &v, const BatchView 
         const uint32_t pr = s_pred[k];
         v.snext[slot] = (k + 1 < nnew && s_pred[k + 1] == pr) ? slot + 1 : s_pnext[k];
         if (k == 0 || s_pred[k - 1] != pr) {
+            wc.note(pr, WriterCheck::LINK, k, &v.st->errors);
             v.snext[pr] = slot;
             v.smeta[pr] = v.smeta[pr] | META_LINK;
         }

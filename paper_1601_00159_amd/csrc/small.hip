@@ -41,8 +41,10 @@ __global__ __launch_bounds__(SBT) void k_batch_block(IndexView v, BatchView b) {
 
 void execute_batch_small(Index &ix, const uint8_t *ops, const uint64_t *keys, const uint64_t *vals, uint64_t n,
                          uint64_t *out_vals, uint8_t *out_status, hipStream_t s) {
-    const IndexView v = index_view(ix);
-    BatchView b{ops, keys, vals, (uint32_t)n, out_vals, out_status};
+    IndexView v = index_view(ix);
+    const WriterCheck wc = writer_check(ix, 1);
+    v.owner = wc.owner;
+    BatchView b{ops, keys, vals, (uint32_t)n, out_vals, out_status, wc.unit};
     const uint32_t lds = SmallLds::bytes();
     static bool attr = false;
     if (!attr) {

@@ -9,7 +9,8 @@ from . import _lib
 from ._lib import check
 
 _POLICY = {"threshold": _lib.PI_REBUILD_THRESHOLD, "never": _lib.PI_REBUILD_NEVER,
-           "always": _lib.PI_REBUILD_ALWAYS, "background": _lib.PI_REBUILD_BACKGROUND}
+           "always": _lib.PI_REBUILD_ALWAYS, "background": _lib.PI_REBUILD_BACKGROUND,
+           "slices": _lib.PI_REBUILD_SLICES}
 
 
 def _ptr(t):
@@ -47,7 +48,7 @@ class Index:
                  rebuild_policy: str = "threshold", capacity_hint: int = 0, lds_levels: int = 0,
                  profile: int = 0, queries_per_lane: int = 0, blocks_per_cu: int = 0, lds_budget: int = 0,
                  descent_block: int = 0, graph_max_log2: int = 0, small_batch_log2: int = 0,
-                 rebuild_min: int = 4096, compact_percent: int = 0):
+                 rebuild_min: int = 4096, compact_percent: int = 0, check_writers: int = 0):
         self._L = _lib.lib()
         cfg = _lib.pi_config()
         check(self._L.pi_config_default(ctypes.byref(cfg)))
@@ -68,6 +69,7 @@ class Index:
         cfg.small_batch_log2 = small_batch_log2
         cfg.rebuild_min = rebuild_min
         cfg.compact_percent = compact_percent
+        cfg.check_writers = check_writers
         h = ctypes.c_void_p()
         check(self._L.pi_create(ctypes.byref(cfg), ctypes.byref(h)))
         self._h = h
@@ -222,6 +224,13 @@ class Index:
         self._check(self._L.pi_debug_level(self._h, level, _ptr(k), _ptr(d), n, ctypes.byref(got),
                                            _stream(stream)))
         return k[:got.value], d[:got.value]
+
+    def writer_selftest(self, stream=None):
+        """(error bits of one writer recording twice, of two writers of one
+        node) from the checked mode's detection on a private shadow."""
+        a, b = ctypes.c_uint32(), ctypes.c_uint32()
+        self._check(self._L.pi_debug_writer_selftest(self._h, ctypes.byref(a), ctypes.byref(b), _stream(stream)))
+        return a.value, b.value
 
     def set_storage_bound(self, used_upper: int):
         """Test hook (pi_debug_set_storage_bound): plants the host's bound on
