@@ -390,56 +390,139 @@ def run_write(args):
         "cpu_baseline": None if args.no_cpu_baseline else write_cpu_baseline(w)}), flush=True)
 
 
+def serve_cpu_baseline(w, budget_s=8.0):
+    """The CPU oracle on the serving stream: the full index, the stream's
+    queries in arrival order, in chunks until budget_s seconds, one pinned
+    core."""
+    import numpy as np
+
+    from oracle.skiplist import SkipList
+    from paper_1601_00159_amd.workloads import Batch
+
+    order = np.argsort(w.load_keys, kind="stable")
+    orc = SkipList()
+    orc.bulk_load_sorted(w.load_keys[order], w.load_vals[order])
+    m = min(w.keys.size, 1 << 22)
+    with OneCore() as pin:
+        done, elapsed = oracle_rate(orc, Batch(w.ops[:m], w.keys[:m], w.vals[:m]), m, budget_s, 1 << 16)
+    orc.close()
+    return {"value": round(done / elapsed / 1e6, 4), "unit": "Mqueries/s", "cores": 1, "kind": "oracle",
+            "sample": f"the first {done} queries of the stream (90/5/5 S/I/D, Zipf 0.8) against the full "
+                      f"{w.load_keys.size}-key index (single-threaded Pugh skip list pinned to core {pin.core}, "
+                      f"{elapsed:.1f}s timed inside the oracle; host CPU {cpu_model()})"}
+
+
+def serve_bytes(w, lds_from):
+    """Algorithmic bytes of the whole stream: the whole-batch model of the
+    read path on a sample of up to 2^22 of its queries (index as loaded),
+    scaled to the stream, plus the inserted values read (8 B per query),
+    per insert a new node and its predecessor's link (26 B), per delete a
+    flag write (1 B)."""
+    import numpy as np
+
+    from paper_1601_00159_amd import bytemodel
+
+    m = min(w.keys.size, 1 << 22)
+    bm = bytemodel.descent_bytes(np.sort(w.load_keys), np.sort(w.keys[:m]), lds_from=lds_from)
+    per_q = bytemodel.batch_bytes(bm, m) / m + 8
+    return per_q * w.keys.size + int((w.ops == 1).sum()) * 26 + int((w.ops == 2).sum())
+
+
 def run_serve(args):
     """Serving loop (--workload serve): 2^25 loaded keys, open-loop Poisson
     arrivals at each rate of --rates for --serve-ms of arrivals, 90/5/5
     S/I/D with Zipf 0.8 keys.  Continuous batching (100 us deadline) with 1,
     2 and 4 micro-batches in flight, each after a warm-up of SEARCH
-    batches.  One JSON line per rate and mode."""
+    batches.  The rate "sat" is saturation: --sat-queries queries that have
+    all arrived at time 0, served in micro-batches of up to 2^22 back to back
+    (the serving form's ceiling, beside the plain launch of 2^22-query
+    batches of the same stream).  One JSON line per rate and mode."""
     import numpy as np
     import torch
 
     from paper_1601_00159_amd import workloads as W
-    from paper_1601_00159_amd.index import Index
+    from paper_1601_00159_amd.index import Index, to_device_u64, to_device_u8
 
-    for rate in [float(x) for x in args.rates.split(",")]:
-        n = int(rate * args.serve_ms / 1e3)
+    for rate_s in args.rates.split(","):
+        sat = rate_s == "sat"
+        rate = 1e9 if sat else float(rate_s)
+        n = args.sat_queries if sat else int(rate * args.serve_ms / 1e3)
         t0 = time.perf_counter()
         w = W.serving(args.load_log2 if args.load_log2 != 26 else 25, rate, n)
+        if sat:
+            w.arrival_us = np.zeros(n, dtype=np.float64)
+            w.name = f"serve-2^{25 if args.load_log2 == 26 else args.load_log2}-saturation"
         log(f"workload {w.name}: {w.note}; generated in {time.perf_counter() - t0:.1f}s")
-        for mode, deadline, inflight in (("continuous", 100.0, 1), ("continuous", 100.0, 2),
-                                         ("continuous", 100.0, 4)):
-            with Index(device=0) as ix:
+        if sat:
+            # the plain launch of the same stream in 2^22-query batches
+            with Index(device=0, lds_budget=args.lds_budget) as ix:
+                ix.bulk_load(w.load_keys, w.load_vals)
+                m = 1 << 22
+                for b in range(0, min(n, 2 * m), m):  # warm-up on SEARCH batches
+                    ix.execute(np.zeros(min(m, n - b), dtype=np.uint8), w.keys[b:b + m], w.vals[b:b + m])
+                dev_b = [(to_device_u8(w.ops[b:b + m]), to_device_u64(w.keys[b:b + m]), to_device_u64(w.vals[b:b + m]),
+                          torch.empty(min(m, n - b), dtype=torch.int64, device="cuda"),
+                          torch.empty(min(m, n - b), dtype=torch.uint8, device="cuda")) for b in range(0, n, m)]
+                torch.cuda.synchronize()
+                t1 = time.perf_counter()
+                for o, k, v, ov, os_ in dev_b:
+                    ix.execute_raw(o, k, v, ov, os_)
+                torch.cuda.synchronize()
+                plain_s = time.perf_counter() - t1
+            log(f"plain launch of the same stream: {n / plain_s / 1e6:.1f} Mq/s ({len(dev_b)} batches)")
+        cpu = None if args.no_cpu_baseline else serve_cpu_baseline(w)
+        sbytes = None
+        modes = (("continuous", 0.0, 1), ("continuous", 0.0, 2), ("continuous", 0.0, 4)) if sat else \
+            (("continuous", 100.0, 1), ("continuous", 100.0, 2), ("continuous", 100.0, 4))
+        for mode, deadline, inflight in modes:
+            with Index(device=0, lds_budget=args.lds_budget) as ix:
                 ix.bulk_load(w.load_keys, w.load_vals)
                 # warm-up outside the measurement: SEARCH batches of every
                 # size class load the kernels and size the workspaces
                 for m in (1 << 10, 1 << 16, 1 << 22):
                     m = min(m, n)
                     ix.execute(np.zeros(m, dtype=np.uint8), w.keys[:m], w.vals[:m])
+                if inflight > 1:
+                    # the buffer sets of overlapped micro-batches, as a server
+                    # that has been running has them
+                    m = min(n, 2 << 22)
+                    ix.serve(np.zeros(m), np.zeros(m, dtype=np.uint8), w.keys[:m], w.vals[:m], deadline_us=0.0,
+                             max_batch=1 << 22, max_inflight=inflight)
                 torch.cuda.synchronize()
                 gv, gs, done, ends = ix.serve(w.arrival_us, w.ops, w.keys, w.vals, deadline_us=deadline,
                                               max_inflight=inflight)
                 torch.cuda.synchronize()
                 st = ix.stats()
+            if sbytes is None and not args.no_bytemodel:
+                sbytes = serve_bytes(w, st["lds_from"])
             lat = done - w.arrival_us
             starts = np.concatenate([[0], ends[:-1]])
             blat = done[ends - 1] - w.arrival_us[starts]
             span_s = (done.max() - w.arrival_us[0]) / 1e6
+            roof = None
+            if sbytes is not None:
+                ach = sbytes / span_s / 1e9
+                roof = {"bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                        "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": None,
+                        "scope": "whole stream over the served span (first arrival to last answer)",
+                        "algorithmic_bytes": int(sbytes), "bytes_per_query": round(sbytes / n, 2),
+                        "note": "descent lines counted on the index as loaded"}
             print(json.dumps({
                 "metric": "Mqueries/s served (open-loop arrivals) at p99 latency", "value": round(n / span_s / 1e6, 2),
                 "unit": "Mqueries/s", "n_gpus": 1, "steps": int(ends.size), "warmup": 0,
                 "ms_per_step": round(span_s * 1e3 / max(ends.size, 1), 4), "higher_is_better": True,
                 "scaling": "weak", "vs_baseline": None, "dtype": "u64", "data": "synthetic",
                 "config": {"workload": w.name, "loaded_keys": int(w.load_keys.size), "queries": n,
-                           "offered_Mqps": rate / 1e6, "op_mix": "90/5/5 S/I/D", "key_distribution": "zipf 0.8",
-                           "mode": mode, "deadline_us": deadline, "max_inflight": inflight,
-                           "parallelism": "single GPU"},
+                           "offered_Mqps": "saturation" if sat else rate / 1e6, "op_mix": "90/5/5 S/I/D",
+                           "key_distribution": "zipf 0.8", "mode": mode, "deadline_us": deadline,
+                           "max_inflight": inflight, "lds_budget": args.lds_budget, "parallelism": "single GPU"},
                 "latency_us": {"query_p50": round(float(np.percentile(lat, 50)), 1),
                                "query_p99": round(float(np.percentile(lat, 99)), 1),
                                "batch_p50": round(float(np.percentile(blat, 50)), 1),
                                "batch_p99": round(float(np.percentile(blat, 99)), 1)},
                 "micro_batches": int(ends.size), "mean_batch": round(n / max(ends.size, 1), 1),
-                "rebuilds": st["repairs"], "roofline": None, "cpu_baseline": None}), flush=True)
+                "plain_launch_Mqps": round(n / plain_s / 1e6, 2) if sat else None,
+                "rebuilds": st["repairs"], "roofline": roof, "cpu_baseline": cpu}), flush=True)
 
 
 def run_many(args):
@@ -548,6 +631,7 @@ def main():
                     help="rebuild policy (--workload write)")
     ap.add_argument("--rates", default="50e6,200e6,500e6", help="offered queries/s (--workload serve)")
     ap.add_argument("--serve-ms", type=float, default=20.0, help="ms of arrivals per rate (--workload serve)")
+    ap.add_argument("--sat-queries", type=int, default=1 << 25, help="queries of the saturation run (--workload serve)")
     ap.add_argument("--ranges", type=int, default=8192, help="range queries per batch (--workload range)")
     ap.add_argument("--granularity", default="1,10,100,1000", help="mean keys per range (--workload range)")
     args = ap.parse_args()

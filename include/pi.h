@@ -120,6 +120,12 @@ typedef struct {
                                  (8 bytes per storage slot); a node written by two different writers in
                                  one phase of a batch fails the handle with PI_ERR_DEVICE.  0 = off
                                  (default).  Not available with pi_execute_batch_noalloc */
+    uint32_t post_form;       /* form of the steps after the descent (ownership hand-off of Algorithm 3's
+                                 purpose, the updates of Algorithm 4): 0 = chosen per batch from the
+                                 index's latest counters that reached the host (one launch after a batch
+                                 without INSERT/DELETE, separate kernels after one with them; default),
+                                 1 = always one launch, 2 = always separate kernels.  Results are the same
+                                 in every form; under graph capture the kernels are always separate */
 } pi_config;
 
 /* Accumulated device time per stage of pi_execute_batch (profile = 1). */

@@ -119,6 +119,7 @@ void release_all(pi::Index &ix) {
     for (auto &b : ix.tmp) b.release();
     for (auto &b : ix.rng) b.release();
     pi::release_graphs(ix);
+    pi::pipe_release(ix);
     pi::bg_release(ix);
     pi::slice_release(ix);
     ix.owner.release();
@@ -170,6 +171,7 @@ void maybe_rebuild(pi::Index &ix, hipStream_t s, bool may_rebuild = true) {
         latest_enq = ix.ring_enq[slot];
         have = true;
         ix.ring_seen++;
+        ix.recent_writers = latest.b_writers != 0;
         if (latest.errors) throw pi::Error{PI_ERR_DEVICE, pi::device_error_text(latest.errors)};
     }
     if (!have) return;
@@ -299,7 +301,7 @@ pi_status pi_create(const pi_config *cfg_in, pi_index **out) {
          cfg.descent_block != 1024) ||
         (cfg.graph_max_log2 != 0 && (cfg.graph_max_log2 < 12 || cfg.graph_max_log2 > 22)) ||
         (cfg.small_batch_log2 > 12 && cfg.small_batch_log2 != 255) || cfg.compact_percent > 1000 ||
-        cfg.check_writers > 1) {
+        cfg.check_writers > 1 || cfg.post_form > 2) {
         set_err("invalid pi_config field");
         return PI_ERR_INVALID_ARG;
     }
@@ -393,6 +395,40 @@ void batch_step(pi::Index &ix, const uint8_t *d_ops, const uint64_t *d_keys, con
         pi::read_state(ix, s, &cur);
         if (cur.changes > 0) pi::rebuild(ix, s);
     }
+}
+
+// One micro-batch of the serving loop with the ordering on the side stream
+// (pi::pipe_open done): the same steps, bookkeeping and results as
+// batch_step.  Batches that take the one-workgroup path have no separate
+// ordering and run as there.
+void serve_step(pi::Index &ix, const uint8_t *d_ops, const uint64_t *d_keys, const uint64_t *d_values, uint64_t n,
+                uint64_t *d_out_values, uint8_t *d_out_status, hipStream_t s) {
+    const uint32_t slog = ix.cfg.small_batch_log2 ? ix.cfg.small_batch_log2 : 10;
+    if (ix.prof.on || ix.cfg.graph_max_log2 != 0 || (slog != 255 && n <= (1ull << slog)) ||
+        ix.cfg.rebuild_policy == PI_REBUILD_ALWAYS) {
+        batch_step(ix, d_ops, d_keys, d_values, n, d_out_values, d_out_status, s);
+        return;
+    }
+    maybe_rebuild(ix, s);
+    ensure_capacity(ix, d_ops, d_keys, n, s);
+    pi::Index::ServePipe &p = ix.pipe;
+    auto &set = p.set[p.next];
+    p.next ^= 1;
+    const pi::BatchBuffers buf{set.sort, set.msd, set.scan, set.bws};
+    // this set's previous batch is done with its buffers before they are
+    // ordered into again
+    if (set.used) PI_HIP(hipStreamWaitEvent(p.side, set.done, 0));
+    const uint64_t *sk = nullptr;
+    const uint32_t *sidx = nullptr;
+    pi::order_batch(buf, d_ops, d_keys, n, p.side, &sk, &sidx);
+    PI_HIP(hipEventRecord(set.ordered, p.side));
+    PI_HIP(hipStreamWaitEvent(s, set.ordered, 0));
+    pi::finish_batch(ix, buf, sk, sidx, d_ops, d_values, n, d_out_values, d_out_status, s, nullptr);
+    PI_HIP(hipEventRecord(set.done, s));
+    set.used = true;
+    ix.used_upper = std::min<uint64_t>(ix.used_upper + n, ~0ull);
+    ix.enq_queries += n;
+    push_state(ix, s);
 }
 
 pi_status pi_execute_batch(pi_index *h, const uint8_t *d_ops, const uint64_t *d_keys, const uint64_t *d_values,
@@ -496,10 +532,18 @@ pi_status pi_serve(pi_index *h, const pi_serve_config *cfg, const double *h_arri
         plan.deadline_us = cfg->deadline_us;
         plan.max_inflight = cfg->max_inflight ? cfg->max_inflight : 1;
         plan.max_batch = cfg->max_batch ? cfg->max_batch : pi::serve_batch_limit(plan.max_inflight);
+        // more than one micro-batch in flight: the next one's ordering runs
+        // beside the current one's descent
+        const bool overlap = plan.max_inflight > 1;
+        if (overlap) pi::pipe_open(ix, s);
         pi::serve_loop(
             h_arrival_us, n, plan, s,
             [&](uint64_t b, uint64_t e) {
-                batch_step(ix, d_ops + b, d_keys + b, d_values + b, e - b, d_out_values + b, d_out_status + b, s);
+                if (overlap)
+                    serve_step(ix, d_ops + b, d_keys + b, d_values + b, e - b, d_out_values + b, d_out_status + b, s);
+                else
+                    batch_step(ix, d_ops + b, d_keys + b, d_values + b, e - b, d_out_values + b, d_out_status + b,
+                               s);
             },
             h_done_us, h_batch_end, *n_batches);
         return PI_OK;
@@ -664,7 +708,7 @@ pi_status pi_debug_sort(pi_index *h, const uint64_t *d_keys, uint64_t n, uint64_
         hipStream_t s = (hipStream_t)stream;
         const uint64_t *sk = nullptr;
         const uint32_t *si = nullptr;
-        pi::sort_batch_by_range(ix.sortws, ix.msdws, d_keys, nullptr, n, nullptr, s, &sk, &si);
+        pi::sort_batch_by_range(ix.sortws, ix.msdws, d_keys, nullptr, n, false, s, &sk, &si);
         PI_HIP(hipMemcpyAsync(d_sorted_keys, sk, n * 8, hipMemcpyDeviceToDevice, s));
         PI_HIP(hipMemcpyAsync(d_perm, si, n * 4, hipMemcpyDeviceToDevice, s));
         return PI_OK;

@@ -48,7 +48,7 @@ __global__ __launch_bounds__(DT) void k_descend(IndexDesc desc, const uint64_t *
                                                 const uint64_t *__restrict__ sval, const uint32_t *__restrict__ snext,
                                                 const uint8_t *__restrict__ smeta, const uint64_t *__restrict__ sk,
                                                 const uint32_t *__restrict__ sidx, uint32_t n, DevState *st,
-                                                uint2 *__restrict__ dpart,
+                                                uint2 *__restrict__ dpart, const unsigned int *__restrict__ wflag,
                                                 uint64_t *__restrict__ out_vals, uint8_t *__restrict__ out_status,
                                                 uint64_t *__restrict__ res_val, uint8_t *__restrict__ res_flags,
                                                 uint32_t *__restrict__ loc, uint32_t *__restrict__ locnext,
@@ -59,7 +59,17 @@ __global__ __launch_bounds__(DT) void k_descend(IndexDesc desc, const uint64_t *
     uint32_t *s_d = reinterpret_cast<uint32_t *>(s_dyn + desc.lds_entries);
     stage_levels(desc, lkey, ldown, s_k, s_d);
 
-    const bool mixed = MODE == 0 && st->b_writers != 0;
+    // the batch's counters start here (the ordering before this kernel
+    // touches nothing of the index): the later steps read and add to them
+    const unsigned int writers = MODE == 0 && n ? *wflag : 0u;  // an empty batch has no ordering step
+    if (MODE == 0 && blockIdx.x == 0 && threadIdx.x == 0) {
+        st->b_writers = writers;
+        st->b_new = st->b_deletes = st->b_revives = st->b_hits = st->b_invalid = 0;
+        st->b_n = n;
+        st->bar = st->join = 0;
+        st->parts = st->tile_next = 0;
+    }
+    const bool mixed = writers != 0;
     const bool links = MODE == 0 && st->has_links != 0;
     const bool dead = MODE == 0 && st->has_dead != 0;
 
@@ -526,7 +536,7 @@ __global__ void k_batch_begin(DevState *st, uint32_t n) {
     if (threadIdx.x != 0) return;
     st->b_writers = st->b_new = st->b_deletes = st->b_revives = st->b_hits = st->b_invalid = 0;
     st->b_n = n;
-    st->bar = 0;
+    st->bar = st->join = st->parts = st->tile_next = 0;
 }
 
 // Sums the apply tiles' counts (batches with updates; one 256-thread block),
@@ -609,18 +619,56 @@ __global__ __launch_bounds__(256) void k_batch_end(DevState *st, const uint4 *__
 
 // ---------------------------------------------- the fused post-descent step --
 
-// Grid-wide barrier.  The launch is sized so that every block can be
-// resident at once (a quarter of what fits on each CU, and at most four such
-// launches run together), and nothing it waits for waits on it, so every
-// wait ends.  The spin is bounded anyway; running out flags ERR_BARRIER,
-// which fails the handle.
-__device__ __forceinline__ void grid_barrier(unsigned int *bar, unsigned int &round, unsigned int *errors) {
+// Blocks of the fused step.  A block takes part if it starts before the
+// first block reaches the first grid barrier: it joins by adding one to the
+// join word, and the first arrival at that barrier closes the word (a bit
+// set by atomicOr), which fixes the number of blocks taking part; that
+// block publishes the number for the others.  Every block taking part is
+// running by then, so every barrier completes whatever else shares the
+// device; a block that starts later sees the closed bit and leaves at once.
+// One atomic per block to join and one to close: no retry loop, whose cost
+// grows with the square of the blocks starting together.  The first phase
+// hands its tiles out by a counter, so the blocks that take part cover all
+// of them; the later phases split the tiles by rank.
+constexpr unsigned int JOIN_CLOSED = 1u << 31;
+constexpr unsigned int PART_SET = 1u << 31;
+
+// thread 0: this block's rank among the blocks taking part, or ~0u
+__device__ __forceinline__ uint32_t grid_join(unsigned int *join) {
+    const unsigned int c = atomicAdd(join, 1u);
+    return (c & JOIN_CLOSED) ? ~0u : c;
+}
+
+// thread 0: the number of blocks taking part (closing the window if open)
+__device__ uint32_t grid_close(unsigned int *join, unsigned int *parts, unsigned int *errors) {
+    const unsigned int c = atomicOr(join, JOIN_CLOSED);
+    if (!(c & JOIN_CLOSED)) {
+        __hip_atomic_store(parts, PART_SET | c, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        return c;
+    }
+    // closed by another block, which publishes the count right after
+    unsigned int p = __hip_atomic_load(parts, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    for (uint32_t spins = 0; !(p & PART_SET); spins++) {
+        if (spins > (1u << 24)) {
+            atomicOr(errors, ERR_BARRIER);
+            return 1;
+        }
+        __builtin_amdgcn_s_sleep(1);
+        p = __hip_atomic_load(parts, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+    return p & ~PART_SET;
+}
+
+// Barrier of the P blocks taking part.  The spin is bounded anyway; running
+// out flags ERR_BARRIER, which fails the handle.
+__device__ __forceinline__ void grid_barrier(unsigned int *bar, unsigned int &round, uint32_t P,
+                                             unsigned int *errors) {
     __syncthreads();
     round++;
     if (threadIdx.x == 0) {
         __threadfence();  // this block's writes before the arrival
         atomicAdd(bar, 1u);
-        const unsigned int target = round * gridDim.x;
+        const unsigned int target = round * P;
         for (uint32_t spins = 0;
              __hip_atomic_load(bar, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target; spins++) {
             if (spins > (1u << 24)) {
@@ -634,8 +682,16 @@ __device__ __forceinline__ void grid_barrier(unsigned int *bar, unsigned int &ro
     __syncthreads();
 }
 
-// The steps after the descent in one launch (grid-stride over tiles of
-// OTILE sorted queries, grid barriers between the steps): the segmented
+// next tile of a phase for the whole block
+__device__ __forceinline__ uint32_t next_tile(unsigned int *ctr, uint32_t *s_t) {
+    __syncthreads();  // the block is done with the previous value
+    if (threadIdx.x == 0) *s_t = atomicAdd(ctr, 1u);
+    __syncthreads();
+    return *s_t;
+}
+
+// The steps after the descent in one launch (tiles of OTILE sorted queries
+// handed out by counters, grid barriers between the steps): the segmented
 // last-writer scan (tile aggregates, their prefix), answers and in-place
 // updates with per-tile new-node counts, the prefix of those counts (slots
 // of the new nodes), the gather of new nodes in key order, their linking,
@@ -661,16 +717,26 @@ __global__ __launch_bounds__(OT) void k_post(const uint64_t *__restrict__ sk, co
     }
     __shared__ Seg s_w[ONW];
     __shared__ uint32_t s_u[ONW + 1];
+    __shared__ uint32_t s_t;
+    if (threadIdx.x == 0) s_t = grid_join(&st->join);
+    __syncthreads();
+    const uint32_t rank = s_t;
+    if (rank == ~0u) return;  // started after the window closed
     unsigned int round = 0;
-    for (uint32_t t = blockIdx.x; t < ntiles; t += gridDim.x) own_reduce_tile(t, sk, sop, n, agg, s_w);
-    grid_barrier(&st->bar, round, &st->errors);
-    if (blockIdx.x == 0) own_prefix_block(agg, ntiles, s_w);
-    grid_barrier(&st->bar, round, &st->errors);
-    for (uint32_t t = blockIdx.x; t < ntiles; t += gridDim.x)
+    for (uint32_t t = next_tile(&st->tile_next, &s_t); t < ntiles; t = next_tile(&st->tile_next, &s_t))
+        own_reduce_tile(t, sk, sop, n, agg, s_w);
+    __syncthreads();
+    if (threadIdx.x == 0) s_t = grid_close(&st->join, &st->parts, &st->errors);
+    __syncthreads();
+    const uint32_t P = s_t;
+    grid_barrier(&st->bar, round, P, &st->errors);
+    if (rank == 0) own_prefix_block(agg, ntiles, s_w);
+    grid_barrier(&st->bar, round, P, &st->errors);
+    for (uint32_t t = rank; t < ntiles; t += P)
         own_apply_tile(t, sk, sidx, sop, svin, n, agg, res_val, res_flags, loc, sval, smeta, out_vals, out_status,
                        newflag, gw, part, st, wc, tilecnt, s_w);
-    grid_barrier(&st->bar, round, &st->errors);
-    if (blockIdx.x == 0) {
+    grid_barrier(&st->bar, round, P, &st->errors);
+    if (rank == 0) {
         // slots of the new nodes: exclusive prefix of the tile counts
         uint32_t carry = 0;
         for (uint32_t b0 = 0; b0 < ntiles; b0 += OT * 4) {
@@ -697,12 +763,12 @@ __global__ __launch_bounds__(OT) void k_post(const uint64_t *__restrict__ sk, co
             if (st->nused + carry > cap) st->errors |= ERR_CAPACITY;
         }
     }
-    grid_barrier(&st->bar, round, &st->errors);
+    grid_barrier(&st->bar, round, P, &st->errors);
     // new nodes in key order with their predecessors: tile offset plus the
     // rank inside the tile
     const uint32_t nnew = st->b_new;
     if (nnew) {
-        for (uint32_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
+        for (uint32_t t = rank; t < ntiles; t += P) {
             const uint32_t base = t * OTILE + threadIdx.x * OI;
             uint32_t f[OI], c = 0;
 #pragma unroll
@@ -724,12 +790,12 @@ __global__ __launch_bounds__(OT) void k_post(const uint64_t *__restrict__ sk, co
             }
         }
     }
-    grid_barrier(&st->bar, round, &st->errors);
-    link_range(blockIdx.x * OT + threadIdx.x, gridDim.x * OT, st->b_first, nnew, nk, nv, npred, npnext, skey, sval,
-               snext, smeta, wc, &st->errors);
-    // the counters: block 0, after its own share of the links (the others
+    grid_barrier(&st->bar, round, P, &st->errors);
+    link_range(rank * OT + threadIdx.x, P * OT, st->b_first, nnew, nk, nv, npred, npnext, skey, sval, snext, smeta,
+               wc, &st->errors);
+    // the counters: rank 0, after its own share of the links (the others
     // read only b_first and b_new, which the end does not change)
-    if (blockIdx.x == 0) {
+    if (rank == 0) {
         __syncthreads();
         batch_end_block(st, part, ntiles, cap, dpart, dgrid);
     }
@@ -759,15 +825,15 @@ template <int MODE, int QPL, int DT>
 uint32_t launch_descend_q(Index &ix, hipStream_t s, const uint64_t *sk, const uint32_t *sidx, uint64_t n,
                           uint64_t *out_vals, uint8_t *out_status, uint64_t *res_val, uint8_t *res_flags, uint32_t *loc,
                           uint32_t *locnext, const uint8_t *ops, const uint64_t *vals, uint8_t *sop, uint64_t *svin,
-                          uint2 *dpart) {
+                          uint2 *dpart, const unsigned int *wflag) {
     const IndexDesc &d = ix.desc;
     const size_t lds = (size_t)d.lds_entries * 12;
     auto kern = k_descend<MODE, QPL, DT>;
     const uint32_t g = persistent_grid(ix, kern, DT, lds, blocks_for(n, DT * QPL));
     hipLaunchKernelGGL(kern, dim3(g), dim3(DT), lds, s, d, ix.arena_key.as<uint64_t>(), ix.arena_down.as<uint32_t>(),
                        ix.st.key.as<uint64_t>(), ix.st.val.as<uint64_t>(), ix.st.next.as<uint32_t>(),
-                       ix.st.meta.as<uint8_t>(), sk, sidx, (uint32_t)n, ix.dstate, dpart, out_vals, out_status,
-                       res_val, res_flags, loc, locnext, ops, vals, sop, svin);
+                       ix.st.meta.as<uint8_t>(), sk, sidx, (uint32_t)n, ix.dstate, dpart, wflag, out_vals,
+                       out_status, res_val, res_flags, loc, locnext, ops, vals, sop, svin);
     PI_LAUNCH_CHECK();
     return g;
 }
@@ -776,17 +842,17 @@ template <int MODE, int DT>
 uint32_t launch_descend_b(Index &ix, hipStream_t s, const uint64_t *sk, const uint32_t *sidx, uint64_t n,
                           uint64_t *out_vals, uint8_t *out_status, uint64_t *res_val, uint8_t *res_flags,
                           uint32_t *loc, uint32_t *locnext, const uint8_t *ops, const uint64_t *vals, uint8_t *sop,
-                          uint64_t *svin, uint2 *dpart) {
+                          uint64_t *svin, uint2 *dpart, const unsigned int *wflag) {
     switch (ix.cfg.queries_per_lane) {
         case 2:
             return launch_descend_q<MODE, 2, DT>(ix, s, sk, sidx, n, out_vals, out_status, res_val, res_flags, loc,
-                                                 locnext, ops, vals, sop, svin, dpart);
+                                                 locnext, ops, vals, sop, svin, dpart, wflag);
         case 4:
             return launch_descend_q<MODE, 4, DT>(ix, s, sk, sidx, n, out_vals, out_status, res_val, res_flags, loc,
-                                                 locnext, ops, vals, sop, svin, dpart);
+                                                 locnext, ops, vals, sop, svin, dpart, wflag);
         default:
             return launch_descend_q<MODE, 1, DT>(ix, s, sk, sidx, n, out_vals, out_status, res_val, res_flags, loc,
-                                                 locnext, ops, vals, sop, svin, dpart);
+                                                 locnext, ops, vals, sop, svin, dpart, wflag);
     }
 }
 
@@ -796,17 +862,17 @@ template <int MODE>
 uint32_t launch_descend(Index &ix, hipStream_t s, const uint64_t *sk, const uint32_t *sidx, uint64_t n,
                         uint64_t *out_vals, uint8_t *out_status, uint64_t *res_val, uint8_t *res_flags, uint32_t *loc,
                         uint32_t *locnext, const uint8_t *ops, const uint64_t *vals, uint8_t *sop, uint64_t *svin,
-                        uint2 *dpart) {
+                        uint2 *dpart, const unsigned int *wflag) {
     switch (ix.cfg.descent_block) {
         case 256:
             return launch_descend_b<MODE, 256>(ix, s, sk, sidx, n, out_vals, out_status, res_val, res_flags, loc,
-                                               locnext, ops, vals, sop, svin, dpart);
+                                               locnext, ops, vals, sop, svin, dpart, wflag);
         case 512:
             return launch_descend_b<MODE, 512>(ix, s, sk, sidx, n, out_vals, out_status, res_val, res_flags, loc,
-                                               locnext, ops, vals, sop, svin, dpart);
+                                               locnext, ops, vals, sop, svin, dpart, wflag);
         default:
             return launch_descend_b<MODE, 1024>(ix, s, sk, sidx, n, out_vals, out_status, res_val, res_flags, loc,
-                                                locnext, ops, vals, sop, svin, dpart);
+                                                locnext, ops, vals, sop, svin, dpart, wflag);
     }
 }
 
@@ -866,10 +932,6 @@ void execute_batch(Index &ix, const uint8_t *ops, const uint64_t *keys, const ui
 
 void execute_batch(Index &ix, const BatchBuffers &buf, const uint8_t *ops, const uint64_t *keys,
                    const uint64_t *vals, uint64_t n, uint64_t *out_vals, uint8_t *out_status, hipStream_t s) {
-    buf.bws.ensure(n);
-    const uint64_t *sk = nullptr;
-    const uint32_t *sidx = nullptr;
-    DevState *st = ix.dstate;
     Profiler::Rec rec{};
     auto mark = [&](int k) {
         if (!ix.prof.on) return;
@@ -877,41 +939,67 @@ void execute_batch(Index &ix, const BatchBuffers &buf, const uint8_t *ops, const
         PI_HIP(hipEventRecord(rec.e[k], s));
     };
     mark(0);
-    if (n == 0) {  // (otherwise the ordering step clears the per-batch counters)
+    const uint64_t *sk = nullptr;
+    const uint32_t *sidx = nullptr;
+    order_batch(buf, ops, keys, n, s, &sk, &sidx);
+    mark(1);
+    finish_batch(ix, buf, sk, sidx, ops, vals, n, out_vals, out_status, s, ix.prof.on ? &rec : nullptr);
+}
+
+void order_batch(const BatchBuffers &buf, const uint8_t *ops, const uint64_t *keys, uint64_t n, hipStream_t so,
+                 const uint64_t **sk, const uint32_t **sidx) {
+    sort_batch_by_range(buf.sort, buf.msd, keys, ops, n, true, so, sk, sidx);
+}
+
+void finish_batch(Index &ix, const BatchBuffers &buf, const uint64_t *sk, const uint32_t *sidx, const uint8_t *ops,
+                  const uint64_t *vals, uint64_t n, uint64_t *out_vals, uint8_t *out_status, hipStream_t s,
+                  Profiler::Rec *prec) {
+    buf.bws.ensure(n);
+    DevState *st = ix.dstate;
+    auto mark = [&](int k) {
+        if (!prec) return;
+        prec->e[k] = ix.prof.take();
+        PI_HIP(hipEventRecord(prec->e[k], s));
+    };
+    if (n == 0) {  // (otherwise the descent starts the per-batch counters)
         hipLaunchKernelGGL(k_batch_begin, dim3(1), dim3(64), 0, s, st, (uint32_t)n);
         PI_LAUNCH_CHECK();
     }
-    sort_batch_by_range(buf.sort, buf.msd, keys, ops, n, st, s, &sk, &sidx);
-    mark(1);
 
     BatchWorkspace &w = buf.bws;
     const WriterCheck wc = writer_check(ix, 1);
     const uint32_t dgrid = launch_descend<0>(ix, s, sk, sidx, n, out_vals, out_status, w.res_val.as<uint64_t>(),
                                              w.res_flags.as<uint8_t>(), w.loc.as<uint32_t>(), w.locnext.as<uint32_t>(),
                                              ops, vals, w.sop.as<uint8_t>(), w.svin.as<uint64_t>(),
-                                             w.dpart.as<uint2>());
+                                             w.dpart.as<uint2>(), buf.msd.wflag.as<unsigned int>());
     if (dgrid > BatchWorkspace::DPART) throw Error{PI_ERR_DEVICE, "internal error: descent grid above its count slots"};
     PI_LAUNCH_CHECK();
     mark(2);
 
     const uint32_t otiles = blocks_for(n, OTILE);
     Seg *agg = w.agg.as<Seg>();
-    // The steps after the descent in one launch with grid barriers; under
-    // graph capture as separate kernels (a replay gives no say over which
-    // other kernels share the device).
+    // The steps after the descent in one launch with grid barriers, or as
+    // separate kernels.  The one launch saves ~9 dispatches on a batch
+    // without INSERT/DELETE (it only folds the counters), but its barriers
+    // and its blocks that take part cost more than the separate kernels on
+    // a batch with updates; the host cannot see which kind this batch is,
+    // so it goes by the latest counters that reached it.  Under graph
+    // capture always separate (a replay gives no say over which other
+    // kernels share the device).
     hipStreamCaptureStatus cap_status = hipStreamCaptureStatusNone;
     PI_HIP(hipStreamIsCapturing(s, &cap_status));
-    if (cap_status == hipStreamCaptureStatusNone) {
+    const uint32_t form = ix.cfg.post_form;
+    const bool fused = cap_status == hipStreamCaptureStatusNone && (form == 1 || (form == 0 && !ix.recent_writers));
+    if (fused) {
         static int occ = 0;
         if (!occ) {
             PI_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, k_post, OT, 0));
             if (occ < 1) throw Error{PI_ERR_DEVICE, "fused post-descent step cannot be resident"};
         }
-        // a quarter of the resident blocks: up to four of these launches run
-        // at once (the lane streams of a group call), and each must be able
-        // to become resident while the others hold theirs
-        const uint32_t per_cu = (uint32_t)std::max(1, occ / 4);
-        const uint32_t grid = std::max<uint32_t>(1, std::min<uint32_t>(otiles, (uint32_t)ix.num_cus * per_cu));
+        // two blocks per CU: every block that takes part costs same-address
+        // atomics (joining, each barrier), slow with five blocks per CU
+        const uint32_t grid =
+            std::max<uint32_t>(1, std::min<uint32_t>(otiles, (uint32_t)ix.num_cus * std::min(occ, 2)));
         hipLaunchKernelGGL(k_post, dim3(grid), dim3(OT), 0, s, sk, sidx, w.sop.as<uint8_t>(), w.svin.as<uint64_t>(),
                            (uint32_t)n, w.res_val.as<uint64_t>(), w.res_flags.as<uint8_t>(), w.loc.as<uint32_t>(),
                            w.locnext.as<uint32_t>(), ix.st.key.as<uint64_t>(), ix.st.val.as<uint64_t>(),
@@ -949,9 +1037,9 @@ void execute_batch(Index &ix, const BatchBuffers &buf, const uint8_t *ops, const
         PI_LAUNCH_CHECK();
     }
     mark(4);
-    if (ix.prof.on) {
-        rec.n = 5;
-        ix.prof.pending.push_back(rec);
+    if (prec) {
+        prec->n = 5;
+        ix.prof.pending.push_back(*prec);
         if (ix.prof.pending.size() > 4096) ix.prof.drain(false);
     }
 }
@@ -1157,7 +1245,7 @@ bool writer_selftest(Index &ix, hipStream_t s, uint32_t *same_writer_err, uint32
 void debug_interceptions(Index &ix, const uint64_t *keys, uint64_t n, uint64_t *icpt_keys, uint8_t *is_head,
                          hipStream_t s) {
     launch_descend<1>(ix, s, keys, nullptr, n, icpt_keys, is_head, nullptr, nullptr, nullptr, nullptr, nullptr,
-                      nullptr, nullptr, nullptr, nullptr);
+                      nullptr, nullptr, nullptr, nullptr, nullptr);
 }
 
 }  // namespace pi

@@ -202,7 +202,8 @@ void bg_start(Index &ix, const DevState &latest, hipStream_t s) {
     hipLaunchKernelGGL(k_bg_gather, dim3(grid_of(novf, GT)), dim3(GT), 0, b.side, ix.st.key.as<uint64_t>(),
                        ix.st.meta.as<uint8_t>(), b.first, novf, b.okeys.as<uint64_t>());
     PI_LAUNCH_CHECK();
-    sort_batch_by_range(b.sortws, b.msdws, b.okeys.as<uint64_t>(), nullptr, novf, nullptr, b.side, &b.sk, &b.si);
+    sort_batch_by_range(b.sortws, b.msdws, b.okeys.as<uint64_t>(), nullptr, novf, false, b.side,
+                        &b.sk, &b.si);
     hipLaunchKernelGGL(k_bg_zero, dim3(1), dim3(64), 0, b.side, b.cnt.as<uint32_t>(), 64u);
     hipLaunchKernelGGL(k_bg_count, dim3(std::min<uint32_t>(grid_of(novf, GT), 1024)), dim3(GT), 0, b.side, b.sk,
                        novf, ix.cfg.height_seed, ix.cfg.log2_inv_p, ix.cfg.max_height, b.cnt.as<uint32_t>());

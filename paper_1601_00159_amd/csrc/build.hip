@@ -548,7 +548,7 @@ static uint64_t merge_live(Index &ix, uint64_t *okey, uint64_t *oval, uint8_t *o
         // the overflow region holds distinct keys: the batch ordering (range
         // groups + in-group fix-up) sorts them fully; the payload is the
         // position in the region, so the slot is first + payload
-        sort_batch_by_range(ix.sortws, ix.msdws, ix.st.key.as<uint64_t>() + first, nullptr, novf, nullptr, s, &osk,
+        sort_batch_by_range(ix.sortws, ix.msdws, ix.st.key.as<uint64_t>() + first, nullptr, novf, false, s, &osk,
                             &opos_in);
         hipLaunchKernelGGL(k_ovf_place, dim3(blocks_for(novf, 256)), dim3(256), 0, s, osk, opos_in, (uint32_t)first,
                            novf, ix.st.key.as<uint64_t>(), ix.st.meta.as<uint8_t>(), nb, olive.as<uint32_t>(),

@@ -129,6 +129,7 @@ void settle_previous(pi_group *g, hipStream_t s) {
         // nused in the copy plus every query enqueued on the index since the
         // copy (group or single calls) bounds the storage in use now
         ix.used_upper = std::min<uint64_t>(ix.used_upper, st.nused + (ix.enq_queries - g->last_enq[k]));
+        ix.recent_writers = st.b_writers != 0;  // the form of the next large batch's post-descent steps
         const uint32_t pol = ix.cfg.rebuild_policy;
         if (pol == PI_REBUILD_NEVER) continue;
         const double thr = rebuild_threshold(ix);

@@ -94,12 +94,31 @@ struct Index {
     hipEvent_t ev_ring[STATE_RING] = {};
     uint64_t ring_enq[STATE_RING] = {};  // enq_queries when each copy was enqueued
     uint64_t ring_head = 0;        // copies enqueued
+    bool recent_writers = false;   // the newest copy consumed was of a batch with INSERT/DELETE
     uint64_t ring_seen = 0;        // copies consumed (or dropped)
 
     SortWorkspace sortws;
     MsdWorkspace msdws;
     ScanWorkspace scanws;
     BatchWorkspace bws;
+    // Serving with micro-batches in flight: the ordering of a micro-batch
+    // runs on a side stream, beside the descent and updates of the one
+    // before it on the caller's stream.  Two sets of batch buffers take
+    // turns; `ordered` hands a set from the side stream to the caller's
+    // stream, `done` hands it back.  Made on first use, kept until destroy.
+    struct ServePipe {
+        hipStream_t side = nullptr;
+        hipEvent_t inputs = nullptr;  // the caller's stream at the start of a serve call
+        struct Set {
+            SortWorkspace sort;
+            MsdWorkspace msd;
+            ScanWorkspace scan;
+            BatchWorkspace bws;
+            hipEvent_t ordered = nullptr, done = nullptr;
+            bool used = false;
+        } set[2];
+        int next = 0;
+    } pipe;
     DevBuf tmp[10];                // rebuild / export scratch
     DevBuf rng[4];                 // range search: first node, end slot, counts, scan tiles
     // Bumped by every call that may change the storage or reuse the ordering
@@ -202,6 +221,15 @@ void execute_batch(Index &ix, const uint8_t *ops, const uint64_t *keys, const ui
                    uint64_t *out_vals, uint8_t *out_status, hipStream_t s);
 void execute_batch(Index &ix, const BatchBuffers &buf, const uint8_t *ops, const uint64_t *keys,
                    const uint64_t *vals, uint64_t n, uint64_t *out_vals, uint8_t *out_status, hipStream_t s);
+// The two halves of execute_batch.  The ordering reads only the batch and
+// writes only buf.sort / buf.msd, so it may run on another stream beside the
+// steps of an earlier batch; finish_batch (the descent and everything after
+// it, on s) must come after it.  prec: profiler record to complete, or null.
+void order_batch(const BatchBuffers &buf, const uint8_t *ops, const uint64_t *keys, uint64_t n, hipStream_t so,
+                 const uint64_t **sk, const uint32_t **sidx);
+void finish_batch(Index &ix, const BatchBuffers &buf, const uint64_t *sk, const uint32_t *sidx, const uint8_t *ops,
+                  const uint64_t *vals, uint64_t n, uint64_t *out_vals, uint8_t *out_status, hipStream_t s,
+                  Profiler::Rec *prec);
 // Same result through a captured graph of the hot path for the smallest
 // power-of-two class >= n (padding with invalid queries).
 void execute_batch_graph(Index &ix, const uint8_t *ops, const uint64_t *keys, const uint64_t *vals, uint64_t n,
@@ -247,6 +275,10 @@ uint64_t serve_batch_limit(uint32_t inflight);
 void serve_loop(const double *arrival_us, uint64_t n, const ServePlan &plan, hipStream_t s,
                 const std::function<void(uint64_t, uint64_t)> &launch, double *done_us, uint64_t *batch_end,
                 uint64_t &nb);
+// The side stream and events of Index::pipe (default priority), made once;
+// the side stream then waits for what the caller's stream s holds so far.
+void pipe_open(Index &ix, hipStream_t s);
+void pipe_release(Index &ix);
 
 // build.hip: level descriptor from sizes; level arrays from sorted keys
 IndexDesc make_desc(const Index &ix, const uint32_t *level_n, uint64_t *arena_entries);

@@ -37,11 +37,6 @@ constexpr int BIG_GRID = 128;
 
 // ---- 1. key span --------------------------------------------------------
 
-__device__ __forceinline__ uint64_t shfl_xor_u64(uint64_t x, int m) {
-    const uint32_t lo = __shfl_xor((uint32_t)x, m, 64), hi = __shfl_xor((uint32_t)(x >> 32), m, 64);
-    return ((uint64_t)hi << 32) | lo;
-}
-
 // keys equal to +infinity (invalid queries) do not widen the span
 __global__ __launch_bounds__(MT) void k_minmax(const uint64_t *__restrict__ keys, uint32_t n,
                                                uint64_t *__restrict__ partials) {
@@ -90,10 +85,11 @@ __global__ __launch_bounds__(MT) void k_minmax(const uint64_t *__restrict__ keys
     }
 }
 
-// Also clears the big-window count and, for a query batch (st given), the
-// per-batch counters (the first kernels to touch them run after this one).
+// The range map from the min/max partials.  Also clears the big-window count
+// and the writers flag (when given): the first kernels to touch them run
+// after this one.
 __global__ __launch_bounds__(MT) void k_make_map(const uint64_t *__restrict__ partials, uint32_t nparts,
-                                                 RangeMap *map, unsigned int *nbig, DevState *st, uint32_t n) {
+                                                 RangeMap *map, unsigned int *nbig, unsigned int *writers) {
     __shared__ uint64_t s_red[MNW * 2];
     uint64_t lo = ~0ull, hi = 0;
     for (uint32_t i = threadIdx.x; i < nparts; i += MT) {
@@ -117,21 +113,9 @@ __global__ __launch_bounds__(MT) void k_make_map(const uint64_t *__restrict__ pa
             lo = s_red[i] < lo ? s_red[i] : lo;
             hi = s_red[MNW + i] > hi ? s_red[MNW + i] : hi;
         }
-        if (lo > hi) lo = hi = 0;  // no valid key
-        const uint64_t span = hi - lo;
-        uint32_t sbits = 0;
-        while (sbits < 64 && (span >> sbits) != 0) sbits++;
-        RangeMap m;
-        m.lo = lo;
-        m.shift = sbits > RANGE_BITS ? sbits - RANGE_BITS : 0;
-        m.pad_ = 0;
-        *map = m;
+        *map = span_map(lo, hi);
         *nbig = 0;
-        if (st) {
-            st->b_writers = st->b_new = st->b_deletes = st->b_revives = st->b_hits = st->b_invalid = 0;
-            st->b_n = n;
-            st->bar = 0;
-        }
+        if (writers) *writers = 0;
     }
 }
 
@@ -250,22 +234,24 @@ __device__ __forceinline__ void window_bounds(const uint64_t *__restrict__ k, ui
     e = e0 < n ? (range_pos(k[e0 - 1], map) == range_pos(k[e0], map) ? group_end(k, n, map, e0 - 1) : e0) : n;
 }
 
-// A batch without INSERT/DELETE (st->b_writers == 0) needs the order only for
+// A batch without INSERT/DELETE (writers flag 0) needs the order only for
 // locality -- no node gets a writer and no answer depends on the order of
-// different keys -- so it stops at the grouping by u; st == nullptr always
-// orders fully.
+// different keys -- so it stops at the grouping by u; writers == nullptr
+// always orders fully.
 __global__ __launch_bounds__(WT) void k_fixup(uint64_t *__restrict__ kk, uint32_t *__restrict__ vv, uint32_t n,
                                               const RangeMap *__restrict__ mapp, uint32_t *__restrict__ big,
-                                              unsigned int *nbig, unsigned int *dirty, const DevState *st) {
+                                              unsigned int *nbig, unsigned int *dirty,
+                                              const unsigned int *writers) {
     __shared__ uint64_t s_k[WMAX];
     __shared__ uint32_t s_v[WMAX];
     __shared__ uint32_t s_h[WMAX + 1];  // group heads, in order
+    __shared__ uint8_t s_gd[WMAX];      // per group: some entry has a smaller key than the one before it
     __shared__ uint32_t s_b[2];
     __shared__ uint32_t s_tmp[WNW + 1];
     __shared__ unsigned int s_gmax;
     const RangeMap map = *mapp;
     if (blockIdx.x * WNOM >= n) return;
-    if (st && st->b_writers == 0) return;
+    if (writers && *writers == 0) return;
     if (threadIdx.x < 64) {
         uint32_t s, e;
         window_bounds(kk, n, map, blockIdx.x, s, e);
@@ -318,18 +304,37 @@ __global__ __launch_bounds__(WT) void k_fixup(uint64_t *__restrict__ kk, uint32_
         nheads -= 1;
     }
     if (threadIdx.x == 0) s_h[nheads] = m;
+    for (uint32_t g = threadIdx.x; g < nheads; g += WT) s_gd[g] = 0;
     __syncthreads();
+    // The radix passes are stable, so a group is in (key, input position)
+    // order unless some entry has a smaller key than the one before it:
+    // groups of one key repeated (hot keys) need nothing.  Only the groups
+    // with such a descent are ordered.
+    bool desc = false;
+#pragma unroll
+    for (int r = 0; r < WE; r++) {
+        const uint32_t x = t0 + r;
+        if (x == 0 || x >= m || (hmask & (1u << r)) || s_k[x] >= s_k[x - 1]) continue;
+        desc = true;
+        uint32_t lo = 0, hi = nheads;  // the group holding x: last head <= x
+        while (hi - lo > 1) {
+            const uint32_t mid = (lo + hi) >> 1;
+            if (s_h[mid] <= x) lo = mid; else hi = mid;
+        }
+        s_gd[lo] = 1;
+    }
+    if (!__syncthreads_or(desc)) return;  // every group is in order already
     uint32_t gmax = 1;
-    for (uint32_t g = threadIdx.x; g < nheads; g += WT) gmax = max(gmax, s_h[g + 1] - s_h[g]);
+    for (uint32_t g = threadIdx.x; g < nheads; g += WT)
+        if (s_gd[g]) gmax = max(gmax, s_h[g + 1] - s_h[g]);
     if (gmax > 1) atomicMax(&s_gmax, gmax);
     __syncthreads();
     const uint32_t G = s_gmax;
-    if (G == 1) return;  // every group is a single entry: already in order
     if (G <= 32) {
-        // insertion sort of each group by (key, input position)
+        // insertion sort of each such group by (key, input position)
         for (uint32_t g = threadIdx.x; g < nheads; g += WT) {
             const uint32_t a = s_h[g], z = s_h[g + 1];
-            if (z - a < 2) continue;
+            if (!s_gd[g]) continue;
             for (uint32_t x = a + 1; x < z; x++) {
                 const uint64_t ck = s_k[x];
                 const uint32_t cv = s_v[x];
@@ -373,9 +378,11 @@ __global__ __launch_bounds__(WT) void k_fixup(uint64_t *__restrict__ kk, uint32_
     }
 }
 
-// Marks a large window dirty when it holds more than one key.  All blocks
-// share the work: the windows' sizes are prefix-summed in LDS and the blocks
-// stride over fixed-size chunks of the concatenated windows.
+// Marks a large window dirty when some entry has a smaller key than the one
+// before it (otherwise the stable passes left it in (key, input position)
+// order: one key repeated, or keys that arrived in order).  All blocks share
+// the work: the windows' sizes are prefix-summed in LDS and the blocks stride
+// over fixed-size chunks of the concatenated windows.
 constexpr uint32_t CHECK_CHUNK = 4096;
 constexpr uint32_t CHECK_LIST = 4096;
 
@@ -388,10 +395,9 @@ __global__ __launch_bounds__(WT) void k_big_check(const uint64_t *__restrict__ k
     if (nb > CHECK_LIST) {  // too many to list: one window per block
         for (unsigned int j = blockIdx.x; j < nb; j += gridDim.x) {
             const uint32_t s = big[2 * j], m = big[2 * j + 1];
-            const uint64_t K = kk[s];
-            bool diff = false;
-            for (uint32_t x = threadIdx.x; x < m; x += WT) diff |= kk[s + x] != K;
-            if (__syncthreads_or(diff) && threadIdx.x == 0) dirty[j] = 1;
+            bool desc = false;
+            for (uint32_t x = threadIdx.x + 1; x < m; x += WT) desc |= kk[s + x] < kk[s + x - 1];
+            if (__syncthreads_or(desc) && threadIdx.x == 0) dirty[j] = 1;
         }
         return;
     }
@@ -418,10 +424,10 @@ __global__ __launch_bounds__(WT) void k_big_check(const uint64_t *__restrict__ k
         const uint32_t s = big[2 * j], m = big[2 * j + 1];
         const uint32_t off = (c - s_pre[j]) * CHECK_CHUNK;
         const uint32_t len = m - off < CHECK_CHUNK ? m - off : CHECK_CHUNK;
-        const uint64_t K = kk[s];
-        bool diff = false;
-        for (uint32_t x = threadIdx.x; x < len; x += WT) diff |= kk[s + off + x] != K;
-        if (__syncthreads_or(diff) && threadIdx.x == 0) dirty[j] = 1;
+        bool desc = false;
+        for (uint32_t x = threadIdx.x + (off == 0 ? 1u : 0u); x < len; x += WT)
+            desc |= kk[s + off + x] < kk[s + off + x - 1];
+        if (__syncthreads_or(desc) && threadIdx.x == 0) dirty[j] = 1;
     }
 }
 
@@ -690,6 +696,7 @@ void MsdWorkspace::ensure(uint64_t n) {
     big.ensure(2 * nw * sizeof(uint32_t));
     dirty.ensure(nw * sizeof(uint32_t));
     nbig.ensure(64);
+    wflag.ensure(64);
 }
 
 void MsdWorkspace::release() {
@@ -698,10 +705,11 @@ void MsdWorkspace::release() {
     big.release();
     dirty.release();
     nbig.release();
+    wflag.release();
 }
 
 void sort_batch_by_range(SortWorkspace &ws, MsdWorkspace &mw, const uint64_t *keys, const uint8_t *ops, uint64_t n,
-                         DevState *st, hipStream_t s, const uint64_t **out_keys, const uint32_t **out_idx) {
+                         bool batch, hipStream_t s, const uint64_t **out_keys, const uint32_t **out_idx) {
     ws.ensure(n);
     mw.ensure(n);
     uint64_t *ka = ws.keys[0].as<uint64_t>(), *kb = ws.keys[1].as<uint64_t>();
@@ -713,16 +721,17 @@ void sort_batch_by_range(SortWorkspace &ws, MsdWorkspace &mw, const uint64_t *ke
     RangeMap *map = mw.map.as<RangeMap>();
     const uint32_t parts = std::max<uint32_t>(1, std::min<uint32_t>(MM_BLOCKS, (nn + MT * 16 - 1) / (MT * 16)));
     hipLaunchKernelGGL(k_minmax, dim3(parts), dim3(MT), 0, s, keys, nn, mw.partials.as<uint64_t>());
+    unsigned int *wf = batch ? mw.wflag.as<unsigned int>() : nullptr;
     hipLaunchKernelGGL(k_make_map, dim3(1), dim3(MT), 0, s, mw.partials.as<uint64_t>(), parts, map,
-                       mw.nbig.as<unsigned int>(), st, nn);
+                       mw.nbig.as<unsigned int>(), wf);
     PI_LAUNCH_CHECK();
     // group by the 24-bit position inside the span, one byte per pass
-    radix_pass(ws, keys, nullptr, ops, nn, 0, map, st, ka, ia, s);
+    radix_pass(ws, keys, nullptr, ops, nn, 0, map, wf, ka, ia, s);
     radix_pass(ws, ka, ia, nullptr, nn, 8, map, nullptr, kb, ib, s);
     radix_pass(ws, kb, ib, nullptr, nn, 16, map, nullptr, ka, ia, s);
     const uint32_t nwin = (nn + WNOM - 1) / WNOM;
     hipLaunchKernelGGL(k_fixup, dim3(nwin), dim3(WT), 0, s, ka, ia, nn, map, mw.big.as<uint32_t>(),
-                       mw.nbig.as<unsigned int>(), mw.dirty.as<unsigned int>(), (const DevState *)st);
+                       mw.nbig.as<unsigned int>(), mw.dirty.as<unsigned int>(), (const unsigned int *)wf);
     hipLaunchKernelGGL(k_big_check, dim3(1024), dim3(WT), 0, s, ka, mw.big.as<uint32_t>(), mw.nbig.as<unsigned int>(),
                        mw.dirty.as<unsigned int>());
     hipLaunchKernelGGL(k_big_fixup, dim3(BIG_GRID), dim3(WT), 0, s, ka, ia, kb, ib, mw.big.as<uint32_t>(),

@@ -53,6 +53,10 @@ struct DevState {
     unsigned int errors;         // ERR_* bits of internal consistency failures (must stay 0)
     unsigned int bar;            // grid barrier of the fused post-descent step (cleared per batch)
     unsigned int b_first;        // first storage slot of the batch's new nodes (fused step)
+    // fused post-descent step, cleared per batch: blocks that joined (bit 31
+    // once the window closed), their number once fixed (bit 31 = set), next
+    // tile of the first phase
+    unsigned int join, parts, tile_next;
 };
 
 // DevState::errors bits
@@ -197,6 +201,25 @@ struct RangeMap {
     uint32_t pad_;
 };
 
+__device__ __forceinline__ uint64_t shfl_xor_u64(uint64_t x, int m) {
+    const uint32_t lo = __shfl_xor((uint32_t)x, m, 64), hi = __shfl_xor((uint32_t)(x >> 32), m, 64);
+    return ((uint64_t)hi << 32) | lo;
+}
+
+// Map of the span [lo, hi] of a batch's valid keys (lo > hi: no valid key)
+// onto RANGE_BITS-bit positions.
+__device__ __forceinline__ RangeMap span_map(uint64_t lo, uint64_t hi) {
+    if (lo > hi) lo = hi = 0;
+    const uint64_t span = hi - lo;
+    uint32_t sbits = 0;
+    while (sbits < 64 && (span >> sbits) != 0) sbits++;
+    RangeMap m;
+    m.lo = lo;
+    m.shift = sbits > RANGE_BITS ? sbits - RANGE_BITS : 0;
+    m.pad_ = 0;
+    return m;
+}
+
 __device__ __forceinline__ uint32_t range_pos(uint64_t k, const RangeMap &m) {
     if (k <= m.lo) return 0;
     const uint64_t r = (k - m.lo) >> m.shift;
@@ -252,34 +275,38 @@ struct SortWorkspace {
     void release();
 };
 // Stable LSD radix sort of keys (payload = input position).  When ops is not
-// null, keys whose op is > 2 sort as KEY_MAX, and b_writers of st is set
-// (nonzero) when there is a valid INSERT/DELETE query.  Returns pointers into
-// the workspace.
+// null, keys whose op is > 2 sort as KEY_MAX, and *writers (when not null) is
+// set nonzero when there is a valid INSERT/DELETE query.  Returns pointers
+// into the workspace.
 void sort_keys_with_index(SortWorkspace &ws, const uint64_t *keys, const uint8_t *ops, uint64_t n,
-                          DevState *st, hipStream_t s, const uint64_t **out_keys,
+                          unsigned int *writers, hipStream_t s, const uint64_t **out_keys,
                           const uint32_t **out_idx);
 // Same, with an explicit u32 payload.
 void sort_pairs(SortWorkspace &ws, const uint64_t *keys, const uint32_t *payload, uint64_t n,
                 hipStream_t s, const uint64_t **out_keys, const uint32_t **out_payload);
 
-// Ordering of a query batch: partition by key range, then LDS sort of each
-// range (msd.hip).  Same contract as sort_keys_with_index; with st given it
-// also clears st's per-batch counters (b_pad excepted) for a non-empty batch.
+// Ordering of a query batch: partition by key range, then order inside each
+// range (msd.hip).  Same contract as sort_keys_with_index.  With batch set,
+// the workspace's writers flag (MsdWorkspace::wflag) is cleared and then set
+// when there is a valid INSERT/DELETE query, and a batch without any stops at
+// the grouping by range position (its order only serves locality).  Touches
+// nothing of the index, so that it may run beside another batch's steps.
 struct MsdWorkspace {
-    DevBuf partials, map, big, nbig, dirty;
+    DevBuf partials, map, big, nbig, dirty, wflag;
     void ensure(uint64_t n);
     void release();
 };
 void sort_batch_by_range(SortWorkspace &ws, MsdWorkspace &mw, const uint64_t *keys, const uint8_t *ops, uint64_t n,
-                         DevState *st, hipStream_t s, const uint64_t **out_keys, const uint32_t **out_idx);
+                         bool batch, hipStream_t s, const uint64_t **out_keys, const uint32_t **out_idx);
 
 // One stable 8-bit LSD pass (hist, column scan, scatter).  The digit is
 // (key >> shift) & 255, or, when map is not null, (range_pos(key) >> shift)
 // & 255.  idx_in null = input positions; ops not null = keys whose op is
-// invalid count as KEY_MAX, and st->b_writers is set when there is an
-// INSERT/DELETE query.
+// invalid count as KEY_MAX, and *writers (when not null) is set when there is
+// an INSERT/DELETE query.
 void radix_pass(SortWorkspace &ws, const uint64_t *kin, const uint32_t *iin, const uint8_t *ops, uint32_t n,
-                uint32_t shift, const RangeMap *map, DevState *st, uint64_t *kout, uint32_t *iout, hipStream_t s);
+                uint32_t shift, const RangeMap *map, unsigned int *writers, uint64_t *kout, uint32_t *iout,
+                hipStream_t s);
 
 // Exclusive scan of each of ncols columns of length len stored back to back
 // (column c at cols + c*len); totals[c] receives the column sum.

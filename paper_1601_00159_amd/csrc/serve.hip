@@ -49,6 +49,40 @@ struct Flight {
 
 }  // namespace
 
+void pipe_open(Index &ix, hipStream_t s) {
+    Index::ServePipe &p = ix.pipe;
+    if (!p.side) {
+        PI_HIP(hipStreamCreateWithFlags(&p.side, hipStreamNonBlocking));
+        PI_HIP(hipEventCreateWithFlags(&p.inputs, hipEventDisableTiming));
+        for (auto &b : p.set) {
+            PI_HIP(hipEventCreateWithFlags(&b.ordered, hipEventDisableTiming));
+            PI_HIP(hipEventCreateWithFlags(&b.done, hipEventDisableTiming));
+        }
+    }
+    // the batch arrays the caller filled on s before this call
+    PI_HIP(hipEventRecord(p.inputs, s));
+    PI_HIP(hipStreamWaitEvent(p.side, p.inputs, 0));
+}
+
+void pipe_release(Index &ix) {
+    Index::ServePipe &p = ix.pipe;
+    if (p.side) (void)hipStreamSynchronize(p.side);
+    for (auto &b : p.set) {
+        b.sort.release();
+        b.msd.release();
+        b.scan.release();
+        b.bws.release();
+        if (b.ordered) (void)hipEventDestroy(b.ordered);
+        if (b.done) (void)hipEventDestroy(b.done);
+        b.ordered = b.done = nullptr;
+        b.used = false;
+    }
+    if (p.inputs) (void)hipEventDestroy(p.inputs);
+    if (p.side) (void)hipStreamDestroy(p.side);
+    p.inputs = nullptr;
+    p.side = nullptr;
+}
+
 uint64_t serve_batch_limit(uint32_t inflight) {
     size_t freeb = 0, total = 0;
     PI_HIP(hipMemGetInfo(&freeb, &total));
@@ -71,6 +105,17 @@ void serve_loop(const double *arrival, uint64_t n, const ServePlan &plan, hipStr
         return std::chrono::duration<double, std::micro>(std::chrono::steady_clock::now() - clock0).count();
     };
     std::deque<Flight> fl;
+    // completion time of each retired micro-batch; the per-query times are
+    // written after the loop, so that a large micro-batch's stamping (8 B
+    // per query) never delays the next launch
+    std::vector<std::pair<uint64_t, double>> stamps;  // (end, time)
+    auto fill = [&] {
+        uint64_t b = 0;
+        for (const auto &st : stamps) {
+            std::fill(done_us + b, done_us + st.first, st.second);
+            b = st.first;
+        }
+    };
     auto retire = [&](bool wait) {
         while (!fl.empty()) {
             Flight &f = fl.front();
@@ -86,8 +131,7 @@ void serve_loop(const double *arrival, uint64_t n, const ServePlan &plan, hipStr
             }
             float ms = 0.f;
             PI_HIP(hipEventElapsedTime(&ms, ev0, f.ev));
-            const double t = (double)ms * 1000.0;
-            for (uint64_t i = f.b; i < f.e; i++) done_us[i] = t;
+            stamps.emplace_back(f.e, (double)ms * 1000.0);
             pool.give(f.ev);
             fl.pop_front();
         }
@@ -113,6 +157,7 @@ void serve_loop(const double *arrival, uint64_t n, const ServePlan &plan, hipStr
             // report them (nb) before passing the error on
             try {
                 while (!fl.empty()) retire(true);
+                fill();
             } catch (...) {
             }
             throw;
@@ -124,6 +169,7 @@ void serve_loop(const double *arrival, uint64_t n, const ServePlan &plan, hipStr
         next = e;
     }
     while (!fl.empty()) retire(true);
+    fill();
 }
 
 }  // namespace pi

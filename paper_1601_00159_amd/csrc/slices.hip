@@ -527,7 +527,7 @@ bool slice_round(Index &ix, uint64_t snap, hipStream_t s) {
     PI_LAUNCH_CHECK();
     const uint64_t *sk = nullptr;
     const uint32_t *si = nullptr;
-    sort_batch_by_range(z.sortws, z.msdws, z.okeys.as<uint64_t>(), nullptr, m, nullptr, s, &sk, &si);
+    sort_batch_by_range(z.sortws, z.msdws, z.okeys.as<uint64_t>(), nullptr, m, false, s, &sk, &si);
     uint32_t *misc = z.misc.as<uint32_t>();
     unsigned int *flag = misc + 200;
     unsigned int *nrep = misc + 201;

@@ -48,7 +48,8 @@ __device__ __forceinline__ Digit make_digit(uint32_t shift, const RangeMap *map)
 
 __global__ __launch_bounds__(ST) void k_hist(const uint64_t *__restrict__ keys, const uint8_t *__restrict__ ops,
                                              uint32_t n, uint32_t shift, const RangeMap *map,
-                                             uint32_t *__restrict__ tile_hist, uint32_t ntiles, DevState *st) {
+                                             uint32_t *__restrict__ tile_hist, uint32_t ntiles,
+                                             unsigned int *writers_flag) {
     __shared__ uint32_t h[R];
     const Digit dg = make_digit(shift, map);
     const int tid = threadIdx.x;
@@ -71,11 +72,11 @@ __global__ __launch_bounds__(ST) void k_hist(const uint64_t *__restrict__ keys, 
             atomicAdd(&h[dg(k)], 1u);
         }
     }
-    // b_writers is a flag (nonzero: the batch has INSERT/DELETE queries): one
+    // the writers flag (nonzero: the batch has INSERT/DELETE queries): one
     // plain store per tile that has any, not an atomic per wave on one word
     const int any = __syncthreads_or(writers != 0);
     if (tid < R) tile_hist[(size_t)tid * ntiles + blockIdx.x] = h[tid];
-    if (st && any && tid == 0) st->b_writers = 1;
+    if (writers_flag && any && tid == 0) *writers_flag = 1;
 }
 
 __global__ __launch_bounds__(CT) void k_colscan(uint32_t *__restrict__ tile_hist, uint32_t ntiles,
@@ -205,7 +206,7 @@ __global__ __launch_bounds__(ST) void k_scatter(const uint64_t *__restrict__ key
 }
 
 void sort_impl(SortWorkspace &ws, const uint64_t *keys, const uint32_t *payload, const uint8_t *ops,
-               uint64_t n, DevState *st, hipStream_t s, const uint64_t **out_keys,
+               uint64_t n, unsigned int *writers, hipStream_t s, const uint64_t **out_keys,
                const uint32_t **out_idx) {
     ws.ensure(n);
     if (n == 0) {
@@ -225,7 +226,7 @@ void sort_impl(SortWorkspace &ws, const uint64_t *keys, const uint32_t *payload,
         uint64_t *kout = ws.keys[pass & 1].as<uint64_t>();
         uint32_t *iout = ws.idx[pass & 1].as<uint32_t>();
         hipLaunchKernelGGL(k_hist, dim3(ntiles), dim3(ST), 0, s, kin, opin, nn, shift, (const RangeMap *)nullptr,
-                           hist, ntiles, pass == 0 ? st : nullptr);
+                           hist, ntiles, pass == 0 ? writers : nullptr);
         hipLaunchKernelGGL(k_colscan, dim3(R), dim3(CT), 0, s, hist, ntiles, tot);
         hipLaunchKernelGGL(k_scatter, dim3(ntiles), dim3(ST), 0, s, kin, iin, opin, nn, shift,
                            (const RangeMap *)nullptr, hist, ntiles, tot, kout, iout);
@@ -261,12 +262,13 @@ void SortWorkspace::release() {
 }
 
 void radix_pass(SortWorkspace &ws, const uint64_t *kin, const uint32_t *iin, const uint8_t *ops, uint32_t n,
-                uint32_t shift, const RangeMap *map, DevState *st, uint64_t *kout, uint32_t *iout, hipStream_t s) {
+                uint32_t shift, const RangeMap *map, unsigned int *writers, uint64_t *kout, uint32_t *iout,
+                hipStream_t s) {
     if (n == 0) return;
     const uint32_t ntiles = (n + STILE - 1) / STILE;
     uint32_t *hist = ws.tile_hist.as<uint32_t>();
     uint32_t *tot = ws.digit_tot.as<uint32_t>();
-    hipLaunchKernelGGL(k_hist, dim3(ntiles), dim3(ST), 0, s, kin, ops, n, shift, map, hist, ntiles, st);
+    hipLaunchKernelGGL(k_hist, dim3(ntiles), dim3(ST), 0, s, kin, ops, n, shift, map, hist, ntiles, writers);
     hipLaunchKernelGGL(k_colscan, dim3(R), dim3(CT), 0, s, hist, ntiles, tot);
     hipLaunchKernelGGL(k_scatter, dim3(ntiles), dim3(ST), 0, s, kin, iin, ops, n, shift, map, hist, ntiles, tot,
                        kout, iout);
@@ -280,8 +282,9 @@ void column_scan(uint32_t *cols, uint32_t ncols, uint32_t len, uint32_t *totals,
 }
 
 void sort_keys_with_index(SortWorkspace &ws, const uint64_t *keys, const uint8_t *ops, uint64_t n,
-                          DevState *st, hipStream_t s, const uint64_t **out_keys, const uint32_t **out_idx) {
-    sort_impl(ws, keys, nullptr, ops, n, st, s, out_keys, out_idx);
+                          unsigned int *writers, hipStream_t s, const uint64_t **out_keys,
+                          const uint32_t **out_idx) {
+    sort_impl(ws, keys, nullptr, ops, n, writers, s, out_keys, out_idx);
 }
 
 void sort_pairs(SortWorkspace &ws, const uint64_t *keys, const uint32_t *payload, uint64_t n, hipStream_t s,

@@ -48,7 +48,7 @@ class Index:
                  rebuild_policy: str = "threshold", capacity_hint: int = 0, lds_levels: int = 0,
                  profile: int = 0, queries_per_lane: int = 0, blocks_per_cu: int = 0, lds_budget: int = 0,
                  descent_block: int = 0, graph_max_log2: int = 0, small_batch_log2: int = 0,
-                 rebuild_min: int = 4096, compact_percent: int = 0, check_writers: int = 0):
+                 rebuild_min: int = 4096, compact_percent: int = 0, check_writers: int = 0, post_form: int = 0):
         self._L = _lib.lib()
         cfg = _lib.pi_config()
         check(self._L.pi_config_default(ctypes.byref(cfg)))
@@ -70,6 +70,7 @@ class Index:
         cfg.rebuild_min = rebuild_min
         cfg.compact_percent = compact_percent
         cfg.check_writers = check_writers
+        cfg.post_form = post_form
         h = ctypes.c_void_p()
         check(self._L.pi_create(ctypes.byref(cfg), ctypes.byref(h)))
         self._h = h

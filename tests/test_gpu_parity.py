@@ -82,7 +82,8 @@ def _sort_case(kind, n, rng):
     return keys
 
 
-@pytest.mark.parametrize("kind,n", [("uniform+dups", m) for m in (1, 2, 63, 64, 4095, 4096, 4097, 100_003, 1 << 20)]
+@pytest.mark.parametrize("kind,n", [("uniform+dups", m) for m in (1, 2, 63, 64, 4095, 4096, 4097, 100_003, 1 << 20,
+                                                                   4096 * 67 + 5, (1 << 22) + 3)]
                          + [("clustered", 70_001), ("hot-in-cluster", 150_001), ("two-hot", 200_003)])
 def test_sort_is_stable_key_order(kind, n):
     rng = np.random.default_rng(n)
@@ -178,21 +179,27 @@ def _random_batch(rng, pool, n, p_invalid=0.01):
     return ops, keys, vals
 
 
-@pytest.mark.parametrize("policy", ["never", "always", "threshold"])
-def test_mixed_batches_vs_oracle(policy):
-    rng = np.random.default_rng({"never": 1, "always": 2, "threshold": 3}[policy])
+@pytest.mark.parametrize("policy,form", [("never", 0), ("always", 0), ("threshold", 0), ("never", 1),
+                                         ("threshold", 2)])
+def test_mixed_batches_vs_oracle(policy, form):
+    """Mixed and SEARCH-only batches in turn (so that the default form of the
+    post-descent steps switches between its one launch and the separate
+    kernels), and each form forced."""
+    rng = np.random.default_rng({"never": 1, "always": 2, "threshold": 3}[policy] + 10 * form)
     lk = rng.integers(0, 1 << 63, size=50_000, dtype=np.uint64)
     lv = rng.integers(0, 1 << 64, size=50_000, dtype=np.uint64, endpoint=False)
     pool = np.concatenate([lk[:20_000], rng.integers(0, 1 << 63, size=20_000, dtype=np.uint64),
                            np.array([0, (1 << 64) - 2], dtype=np.uint64)])
     orc = SkipList()
     orc.bulk_load(lk, lv)
-    with Index(rebuild_policy=policy, rebuild_fraction=0.05, rebuild_min=1) as ix:
+    with Index(rebuild_policy=policy, rebuild_fraction=0.05, rebuild_min=1, post_form=form) as ix:
         ix.bulk_load(lk, lv)
         tot = {"queries": 0, "hits": 0, "invalid": 0}
-        for b in range(6):
-            n = [40_000, 1, 4097, 65_536, 12_345, 40_000][b]
+        for b in range(9):
+            n = [40_000, 1, 4097, 65_536, 12_345, 40_000, 30_000, 30_000, 20_000][b]
             ops, keys, vals = _random_batch(rng, pool, n)
+            if b in (3, 6, 7):
+                ops = np.where(ops <= 2, 0, ops).astype(np.uint8)  # SEARCH-only (invalid ops stay)
             say(f"batch {b} n={n}")
             wv, ws = orc.execute_batch(ops, keys, vals)
             gv, gs = run_gpu(ix, ops, keys, vals)

@@ -54,12 +54,17 @@ def _stress_batches(rng, lk, n):
     return [b1, b2, b3, b4]
 
 
-@pytest.mark.parametrize("path", ["multi-kernel", "one-workgroup"])
+@pytest.mark.parametrize("path", ["multi-kernel one launch", "multi-kernel separate", "one-workgroup"])
 def test_single_writer_holds_on_stress_batches(path):
-    rng = np.random.default_rng({"multi-kernel": 1, "one-workgroup": 2}[path])
+    """The multi-kernel path in both forms of its post-descent steps (one
+    launch with grid barriers; separate kernels), and the one-workgroup
+    path."""
+    rng = np.random.default_rng({"multi-kernel one launch": 1, "multi-kernel separate": 4, "one-workgroup": 2}[path])
     lk = (np.unique(rng.integers(0, 1 << 40, size=40_000, dtype=np.uint64)) << np.uint64(10)).astype(np.uint64)
-    n = 120_000 if path == "multi-kernel" else 4096
-    kw = {"small_batch_log2": 255} if path == "multi-kernel" else {"small_batch_log2": 12}
+    n = 120_000 if path.startswith("multi") else 4096
+    kw = {"small_batch_log2": 255} if path.startswith("multi") else {"small_batch_log2": 12}
+    if path.startswith("multi"):
+        kw["post_form"] = 1 if path.endswith("one launch") else 2
     orc = SkipList()
     orc.bulk_load(lk, lk)
     with Index(check_writers=1, rebuild_policy="never", **kw) as ix:
