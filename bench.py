@@ -550,7 +550,7 @@ def run_many(args):
                             torch.empty(len(b), dtype=torch.uint8, device=dev)) for b in batches])
     q_per_round = [sum(len(b) for b in batches) for batches in w.rounds]
     for mode in ("per-index", "group"):
-        ixs = [Index(device=0) for _ in w.loads]
+        ixs = [Index(device=0, rebuild_policy=args.many_policy) for _ in w.loads]
         for ix, (k, v) in zip(ixs, w.loads):
             ix.bulk_load(k, v)
         torch.cuda.synchronize()
@@ -595,7 +595,7 @@ def run_many(args):
             "scaling": "weak", "vs_baseline": None, "dtype": "u64", "data": "synthetic",
             "config": {"workload": w.name, "indices": args.indices, "total_keys": int(total_keys),
                        "queries_per_round": int(np.mean(q_per_round)), "op_mix": "90/5/5 S/I/D", "mode": mode,
-                       "fused_max": fused,
+                       "fused_max": fused, "rebuild_policy": args.many_policy,
                        "descent_shape": shape,
                        "parallelism": "single GPU"},
             "latency_ms": {"round_p50": round(float(np.percentile(lat, 50)) * 1e3, 3),
@@ -627,6 +627,8 @@ def main():
                          "write: write-heavy Zipf batches; serve: continuous batching of Poisson arrivals; "
                          "many: one batch on each of many indices per round")
     ap.add_argument("--indices", type=int, default=512, help="indices (--workload many)")
+    ap.add_argument("--many-policy", default="threshold", choices=["threshold", "never", "slices"],
+                    help="rebuild policy of the indices (--workload many)")
     ap.add_argument("--rebuild-policy", default="background", choices=["threshold", "background", "never"],
                     help="rebuild policy (--workload write)")
     ap.add_argument("--rates", default="50e6,200e6,500e6", help="offered queries/s (--workload serve)")

@@ -925,13 +925,14 @@ uint64_t count_inserts(Index &ix, const uint8_t *ops, const uint64_t *keys, uint
 }
 
 void execute_batch(Index &ix, const uint8_t *ops, const uint64_t *keys, const uint64_t *vals, uint64_t n,
-                   uint64_t *out_vals, uint8_t *out_status, hipStream_t s) {
+                   uint64_t *out_vals, uint8_t *out_status, hipStream_t s, bool one_launch) {
     execute_batch(ix, BatchBuffers{ix.sortws, ix.msdws, ix.scanws, ix.bws}, ops, keys, vals, n, out_vals,
-                  out_status, s);
+                  out_status, s, one_launch);
 }
 
 void execute_batch(Index &ix, const BatchBuffers &buf, const uint8_t *ops, const uint64_t *keys,
-                   const uint64_t *vals, uint64_t n, uint64_t *out_vals, uint8_t *out_status, hipStream_t s) {
+                   const uint64_t *vals, uint64_t n, uint64_t *out_vals, uint8_t *out_status, hipStream_t s,
+                   bool one_launch) {
     Profiler::Rec rec{};
     auto mark = [&](int k) {
         if (!ix.prof.on) return;
@@ -943,7 +944,7 @@ void execute_batch(Index &ix, const BatchBuffers &buf, const uint8_t *ops, const
     const uint32_t *sidx = nullptr;
     order_batch(buf, ops, keys, n, s, &sk, &sidx);
     mark(1);
-    finish_batch(ix, buf, sk, sidx, ops, vals, n, out_vals, out_status, s, ix.prof.on ? &rec : nullptr);
+    finish_batch(ix, buf, sk, sidx, ops, vals, n, out_vals, out_status, s, ix.prof.on ? &rec : nullptr, one_launch);
 }
 
 void order_batch(const BatchBuffers &buf, const uint8_t *ops, const uint64_t *keys, uint64_t n, hipStream_t so,
@@ -953,7 +954,7 @@ void order_batch(const BatchBuffers &buf, const uint8_t *ops, const uint64_t *ke
 
 void finish_batch(Index &ix, const BatchBuffers &buf, const uint64_t *sk, const uint32_t *sidx, const uint8_t *ops,
                   const uint64_t *vals, uint64_t n, uint64_t *out_vals, uint8_t *out_status, hipStream_t s,
-                  Profiler::Rec *prec) {
+                  Profiler::Rec *prec, bool one_launch) {
     buf.bws.ensure(n);
     DevState *st = ix.dstate;
     auto mark = [&](int k) {
@@ -989,7 +990,8 @@ void finish_batch(Index &ix, const BatchBuffers &buf, const uint64_t *sk, const 
     hipStreamCaptureStatus cap_status = hipStreamCaptureStatusNone;
     PI_HIP(hipStreamIsCapturing(s, &cap_status));
     const uint32_t form = ix.cfg.post_form;
-    const bool fused = cap_status == hipStreamCaptureStatusNone && (form == 1 || (form == 0 && !ix.recent_writers));
+    const bool fused = cap_status == hipStreamCaptureStatusNone &&
+                       (form == 1 || (form == 0 && (one_launch || !ix.recent_writers)));
     if (fused) {
         static int occ = 0;
         if (!occ) {

@@ -226,11 +226,15 @@ __global__ void k_merge_base(const uint64_t *__restrict__ skey, const uint64_t *
                              const uint8_t *__restrict__ smeta, uint64_t nbase, const uint32_t *__restrict__ A,
                              const uint32_t *__restrict__ Bexcl, const uint32_t *__restrict__ H,
                              uint64_t *__restrict__ okey, uint64_t *__restrict__ oval,
-                             uint8_t *__restrict__ ometa, uint64_t slot_off) {
+                             uint8_t *__restrict__ ometa, uint64_t slot_off, uint64_t lim, unsigned int *errors) {
     const uint64_t b = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (b >= nbase) return;
     if (smeta[1 + b] & META_DEL) return;
     const uint64_t o = slot_off + A[b] + Bexcl[b] + H[b];
+    if (o >= lim) {  // more live flags than the live counter allows (flagged by the check)
+        atomicOr(errors, ERR_LIVE);
+        return;
+    }
     okey[o] = skey[1 + b];
     oval[o] = sval[1 + b];
     if (ometa) ometa[o] = 0;
@@ -241,10 +245,15 @@ __global__ void k_merge_ovf(const uint64_t *__restrict__ osk, const uint32_t *__
                             const uint64_t *__restrict__ sval, const uint32_t *__restrict__ olive,
                             const uint32_t *__restrict__ C, const uint32_t *__restrict__ opos,
                             const uint32_t *__restrict__ A, uint64_t *__restrict__ okey,
-                            uint64_t *__restrict__ oval, uint8_t *__restrict__ ometa, uint64_t slot_off) {
+                            uint64_t *__restrict__ oval, uint8_t *__restrict__ ometa, uint64_t slot_off, uint64_t lim,
+                            unsigned int *errors) {
     const uint64_t o = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (o >= novf || !olive[o]) return;
     const uint64_t d = slot_off + A[opos[o]] + C[o];
+    if (d >= lim) {
+        atomicOr(errors, ERR_LIVE);
+        return;
+    }
     okey[d] = osk[o];
     oval[d] = sval[first + orel[o]];
     if (ometa) ometa[d] = 0;
@@ -512,6 +521,17 @@ void bulk_load(Index &ix, const uint64_t *keys, const uint64_t *vals, uint64_t n
 
 // Writes the live pairs in key order to okey/oval (+ slot_off), and, when
 // ometa is given, clears their flags.  Returns the live count.  Synchronises.
+// The rebuild's live counts (base flags, overflow flags, overflow nodes
+// placed among the base) against the live counter: a disagreement means the
+// flags or the counter are wrong, and fails the handle at its next counter
+// read (the host does not wait for this).
+__global__ void k_check_live(const uint32_t *__restrict__ t, unsigned long long live, uint32_t has_ovf,
+                             unsigned int *errors) {
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    const unsigned long long flags = (unsigned long long)t[0] + (has_ovf ? t[1] : 0u);
+    if (flags != live || (has_ovf && t[2] != t[1])) atomicOr(errors, ERR_LIVE);
+}
+
 static uint64_t merge_live(Index &ix, uint64_t *okey, uint64_t *oval, uint8_t *ometa, uint64_t slot_off,
                            uint64_t cap, hipStream_t s, bool *too_small, const DevState *known = nullptr,
                            bool sync_end = true) {
@@ -525,6 +545,7 @@ static uint64_t merge_live(Index &ix, uint64_t *okey, uint64_t *oval, uint8_t *o
     const uint64_t novf = cur.nused > first ? cur.nused - first : 0;
     *too_small = cur.n_live > cap;
     if (*too_small) return cur.n_live;
+    const uint64_t lim = cap > ~0ull - slot_off ? ~0ull : slot_off + cap;  // output entries [slot_off, lim)
     DevBuf &A = ix.tmp[0];    // exclusive prefix of the base live flags (nb+1)
     DevBuf &H = ix.tmp[1];    // live overflow nodes placed at each base position (nb+1)
     DevBuf &B = ix.tmp[2];    // exclusive prefix of H
@@ -557,23 +578,16 @@ static uint64_t merge_live(Index &ix, uint64_t *okey, uint64_t *oval, uint8_t *o
         exclusive_scan_u32(ix.scanws, olive.as<uint32_t>(), C.as<uint32_t>(), novf, T.as<uint32_t>() + 1, nullptr, s);
     }
     exclusive_scan_u32(ix.scanws, H.as<uint32_t>(), B.as<uint32_t>(), nb + 1, T.as<uint32_t>() + 2, nullptr, s);
-    {
-        // the flags must agree with the live counter before anything is written
-        uint32_t *ht = reinterpret_cast<uint32_t *>(ix.hcounts);
-        PI_HIP(hipMemcpyAsync(ht, T.p, 12, hipMemcpyDeviceToHost, s));
-        PI_HIP(hipStreamSynchronize(s));
-        const uint64_t live_flags = (uint64_t)ht[0] + (novf > 0 ? ht[1] : 0u);
-        if (live_flags != cur.n_live || (novf > 0 && ht[2] != ht[1]))
-            throw Error{PI_ERR_DEVICE, "internal error: live flags disagree with the live counter"};
-    }
+    hipLaunchKernelGGL(k_check_live, dim3(1), dim3(64), 0, s, (const uint32_t *)T.as<uint32_t>(),
+                       (unsigned long long)cur.n_live, (uint32_t)(novf > 0), &ix.dstate->errors);
     if (nb > 0)
         hipLaunchKernelGGL(k_merge_base, dim3(blocks_for(nb, 256)), dim3(256), 0, s, ix.st.key.as<uint64_t>(),
                            ix.st.val.as<uint64_t>(), ix.st.meta.as<uint8_t>(), nb, A.as<uint32_t>(),
-                           B.as<uint32_t>(), H.as<uint32_t>(), okey, oval, ometa, slot_off);
+                           B.as<uint32_t>(), H.as<uint32_t>(), okey, oval, ometa, slot_off, lim, &ix.dstate->errors);
     if (novf > 0)
         hipLaunchKernelGGL(k_merge_ovf, dim3(blocks_for(novf, 256)), dim3(256), 0, s, osk, opos_in, (uint32_t)first, novf,
                            ix.st.val.as<uint64_t>(), olive.as<uint32_t>(), C.as<uint32_t>(), P.as<uint32_t>(),
-                           A.as<uint32_t>(), okey, oval, ometa, slot_off);
+                           A.as<uint32_t>(), okey, oval, ometa, slot_off, lim, &ix.dstate->errors);
     PI_LAUNCH_CHECK();
     if (sync_end) PI_HIP(hipStreamSynchronize(s));
     return cur.n_live;
@@ -597,26 +611,32 @@ void rebuild(Index &ix, hipStream_t s) {
     DevState cur;
     read_state(ix, s, &cur);
     const uint64_t live = cur.n_live;
-    uint64_t ncap = ix.cfg.capacity_hint ? ix.cfg.capacity_hint
-                                         : std::max<uint64_t>(ix.st.cap, live + 2 + storage_room(ix, live));
+    const uint64_t need = ix.cfg.capacity_hint ? ix.cfg.capacity_hint : live + 2 + storage_room(ix, live);
     // the new base region goes to the spare storage (the one replaced by the
     // previous rebuild) when it is large enough; the current one becomes the
-    // spare
+    // spare.  A spare that is too small is replaced by one of twice the need
+    // (and at least the current capacity): an index that keeps growing
+    // between rebuilds then reallocates a logarithmic number of times, not at
+    // every rebuild (each allocation and free waits for the whole device).
     Storage ns = ix.spare;
     ix.spare = Storage{};
-    if (ns.cap < ncap || (ix.cfg.capacity_hint && ns.cap != ncap)) {
+    if (ns.cap < need || (ix.cfg.capacity_hint && ns.cap != need)) {
         ns.release();
-        ns.alloc(ncap);
+        ns.alloc(ix.cfg.capacity_hint ? need : std::max<uint64_t>(2 * need, ix.st.cap));
     }
     bool small = false;
     try {
         // the counters were read above; the merge is ordered before the
         // level build on the stream, so nothing waits for it here
-        merge_live(ix, ns.key.as<uint64_t>(), ns.val.as<uint64_t>(), ns.meta.as<uint8_t>(), 1, ~0ull, s, &small,
+        merge_live(ix, ns.key.as<uint64_t>(), ns.val.as<uint64_t>(), ns.meta.as<uint8_t>(), 1, ns.cap - 2, s, &small,
                    &cur, false);
     } catch (...) {
         ix.spare = ns;
         throw;
+    }
+    if (small) {  // a fixed capacity below the live keys (cannot happen while inserts are checked)
+        ix.spare = ns;
+        throw Error{PI_ERR_CAPACITY, "internal error: the live keys do not fit the storage capacity"};
     }
     ix.spare = ix.st;
     ix.st = ns;

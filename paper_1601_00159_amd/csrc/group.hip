@@ -251,8 +251,10 @@ void run_group(pi_group *g, pi_index *const *indices, const pi_batch *batches, u
         for (uint32_t i = 0; i < count; i++) {
             const pi_batch &b = batches[i];
             if (!b.n || b.n <= fused_max) continue;
+            // one launch for the steps after the descent: the group call is
+            // bound by the host's launches, not by these batches' device time
             execute_batch(indices[i]->ix, ops_override ? ops_override : b.d_ops, b.d_keys, b.d_values, b.n,
-                          b.d_out_values, b.d_out_status, g->lane[r++ % lanes]);
+                          b.d_out_values, b.d_out_status, g->lane[r++ % lanes], true);
         }
         for (int k = 0; k < lanes; k++) {
             PI_HIP(hipEventRecord(g->ev_lane[k], g->lane[k]));

@@ -217,10 +217,14 @@ struct BatchBuffers {
     ScanWorkspace &scan;
     BatchWorkspace &bws;
 };
+// one_launch: the steps after the descent as one launch whatever the index's
+// recent batches were (for callers bound by launches, such as the group
+// call's large batches); otherwise as pi_config::post_form says.
 void execute_batch(Index &ix, const uint8_t *ops, const uint64_t *keys, const uint64_t *vals, uint64_t n,
-                   uint64_t *out_vals, uint8_t *out_status, hipStream_t s);
+                   uint64_t *out_vals, uint8_t *out_status, hipStream_t s, bool one_launch = false);
 void execute_batch(Index &ix, const BatchBuffers &buf, const uint8_t *ops, const uint64_t *keys,
-                   const uint64_t *vals, uint64_t n, uint64_t *out_vals, uint8_t *out_status, hipStream_t s);
+                   const uint64_t *vals, uint64_t n, uint64_t *out_vals, uint8_t *out_status, hipStream_t s,
+                   bool one_launch = false);
 // The two halves of execute_batch.  The ordering reads only the batch and
 // writes only buf.sort / buf.msd, so it may run on another stream beside the
 // steps of an earlier batch; finish_batch (the descent and everything after
@@ -229,7 +233,7 @@ void order_batch(const BatchBuffers &buf, const uint8_t *ops, const uint64_t *ke
                  const uint64_t **sk, const uint32_t **sidx);
 void finish_batch(Index &ix, const BatchBuffers &buf, const uint64_t *sk, const uint32_t *sidx, const uint8_t *ops,
                   const uint64_t *vals, uint64_t n, uint64_t *out_vals, uint8_t *out_status, hipStream_t s,
-                  Profiler::Rec *prec);
+                  Profiler::Rec *prec, bool one_launch = false);
 // Same result through a captured graph of the hot path for the smallest
 // power-of-two class >= n (padding with invalid queries).
 void execute_batch_graph(Index &ix, const uint8_t *ops, const uint64_t *keys, const uint64_t *vals, uint64_t n,

@@ -64,6 +64,7 @@ constexpr unsigned int ERR_WALK = 1;      // a storage walk passed its bound (th
 constexpr unsigned int ERR_CAPACITY = 2;  // new nodes would have passed the storage capacity (none written)
 constexpr unsigned int ERR_WRITERS = 4;   // a storage node had two writers in one phase of a batch (checked mode)
 constexpr unsigned int ERR_BARRIER = 8;   // a grid barrier outwaited its bound (blocks not co-resident)
+constexpr unsigned int ERR_LIVE = 16;     // a rebuild's live flags disagree with the live counter
 
 // Host message for DevState::errors (empty when 0).
 inline std::string device_error_text(unsigned int e) {
@@ -75,6 +76,8 @@ inline std::string device_error_text(unsigned int e) {
                               "internal error: a storage node had two writers in one phase of a batch";
     if (e & ERR_BARRIER) m += std::string(m.empty() ? "" : "; ") +
                               "internal error: a grid barrier did not complete";
+    if (e & ERR_LIVE) m += std::string(m.empty() ? "" : "; ") +
+                           "internal error: live flags disagree with the live counter";
     return m;
 }
 
