@@ -622,6 +622,8 @@ def main():
     ap.add_argument("--blocks-per-cu", type=int, default=0)
     ap.add_argument("--lds-budget", type=int, default=0)
     ap.add_argument("--descent-block", type=int, default=0)
+    ap.add_argument("--order-bits", type=int, default=0, choices=[0, 16, 24],
+                    help="width of the ordering's range position (0 = chosen per batch)")
     ap.add_argument("--workload", choices=["search", "range", "write", "serve", "many"], default="search",
                     help="search: the 64M-key SEARCH batches (default); range: range searches; "
                          "write: write-heavy Zipf batches; serve: continuous batching of Poisson arrivals; "
@@ -684,7 +686,7 @@ def main():
         log(f"calibration copy of {args.calibrate_copy_mib} MiB done")
 
     ix = Index(device=0, profile=1, queries_per_lane=args.queries_per_lane, blocks_per_cu=args.blocks_per_cu,
-               lds_budget=args.lds_budget, descent_block=args.descent_block)
+               lds_budget=args.lds_budget, descent_block=args.descent_block, order_bits=args.order_bits)
     t0 = time.perf_counter()
     ix.bulk_load(w.load_keys, w.load_vals)
     torch.cuda.synchronize()
@@ -756,6 +758,8 @@ def main():
         "vs_baseline": None, "dtype": "u64", "data": "synthetic",
         "config": {"workload": w.name, "loaded_keys": int(w.load_keys.size), "batch_queries": Q,
                    "op_mix": "100% SEARCH", "key_distribution": f"zipf {args.theta}" if args.theta else "uniform",
+                   "ordering": (f"{args.order_bits}-bit range position" if args.order_bits else
+                                "range position of 16 bits after a batch without updates, else 24"),
                    "parallelism": "single GPU"},
         "latency_ms": {"p50": round(float(np.percentile(lat, 50)), 4),
                        "p99": round(float(np.percentile(lat, 99)), 4)},

@@ -126,6 +126,12 @@ typedef struct {
                                  without INSERT/DELETE, separate kernels after one with them; default),
                                  1 = always one launch, 2 = always separate kernels.  Results are the same
                                  in every form; under graph capture the kernels are always separate */
+    uint32_t order_bits;      /* width of the position inside the batch's key span that the ordering sorts
+                                 by (Definition 3's order, then fixed up by key inside equal positions):
+                                 24, or 16 (one radix pass fewer; the descent then sorts each wave's 64
+                                 queries itself, which is all a batch without INSERT/DELETE needs for
+                                 locality), or 0 = chosen per batch like post_form (16 after a batch without
+                                 INSERT/DELETE, 24 after one with them; default).  Results are the same */
 } pi_config;
 
 /* Accumulated device time per stage of pi_execute_batch (profile = 1). */

@@ -34,7 +34,8 @@ class pi_config(ctypes.Structure):
                 ("lds_budget", ctypes.c_uint32), ("descent_block", ctypes.c_uint32),
                 ("graph_max_log2", ctypes.c_uint32), ("small_batch_log2", ctypes.c_uint32),
                 ("compact_percent", ctypes.c_uint32), ("rebuild_min", ctypes.c_uint64),
-                ("check_writers", ctypes.c_uint32), ("post_form", ctypes.c_uint32)]
+                ("check_writers", ctypes.c_uint32), ("post_form", ctypes.c_uint32),
+                ("order_bits", ctypes.c_uint32)]
 
 
 class pi_profile(ctypes.Structure):

@@ -42,7 +42,9 @@ def build(verbose: bool = False, jobs: int = 5) -> str:
             print(text)
     if failed:
         raise RuntimeError(f"hipcc failed for {failed}")
-    link = ["hipcc", f"--offload-arch={ARCH}", "-shared", "-fPIC", *objs, "-o", LIB + ".tmp"]
+    # roctx (named host ranges of the stages, for profilers)
+    link = ["hipcc", f"--offload-arch={ARCH}", "-shared", "-fPIC", *objs, "-o", LIB + ".tmp",
+            "-L", "/opt/rocm/lib", "-lrocprofiler-sdk-roctx", "-Wl,-rpath,/opt/rocm/lib"]
     if verbose:
         print(" ".join(link), flush=True)
     subprocess.run(link, check=True)

@@ -42,6 +42,31 @@ constexpr int ONW = OT / 64;
 // queries; a lane carries QPL queries of a tile (rows of DT) through the
 // descent together.  All waves of the block share one LDS copy of the upper
 // levels.
+// Sorts the wave's 64 (key, index) pairs by (key, index) across the lanes
+// (bitonic network over lane pairs).  A batch without INSERT/DELETE is
+// ordered only to 1/65536 of its key span: the queries of one wave come from
+// one or two such groups in arrival order, and this puts them back in key
+// order, which the descent's shared and per-lane windows rely on for
+// locality.  Past-the-end lanes hold +infinity and stay last.
+__device__ __forceinline__ void wave_sort_kv(uint64_t &k, uint32_t &v) {
+    const int lane = lane_id();
+#pragma unroll
+    for (int size = 2; size <= 64; size <<= 1) {
+#pragma unroll
+        for (int stride = size >> 1; stride > 0; stride >>= 1) {
+            const uint64_t pk = shfl_xor_u64(k, stride);
+            const uint32_t pv = (uint32_t)__shfl_xor((int)v, stride, 64);
+            const bool up = (lane & size) == 0;        // this block ascends
+            const bool low = (lane & stride) == 0;     // the lower lane of the pair
+            const bool pless = pk < k || (pk == k && pv < v);
+            if (low == up ? pless : !pless) {          // keep the min below in an ascending block
+                k = pk;
+                v = pv;
+            }
+        }
+    }
+}
+
 template <int MODE, int QPL, int DT>
 __global__ __launch_bounds__(DT) void k_descend(IndexDesc desc, const uint64_t *__restrict__ lkey,
                                                 const uint32_t *__restrict__ ldown, const uint64_t *__restrict__ skey,
@@ -49,6 +74,7 @@ __global__ __launch_bounds__(DT) void k_descend(IndexDesc desc, const uint64_t *
                                                 const uint8_t *__restrict__ smeta, const uint64_t *__restrict__ sk,
                                                 const uint32_t *__restrict__ sidx, uint32_t n, DevState *st,
                                                 uint2 *__restrict__ dpart, const unsigned int *__restrict__ wflag,
+                                                uint32_t wsort,
                                                 uint64_t *__restrict__ out_vals, uint8_t *__restrict__ out_status,
                                                 uint64_t *__restrict__ res_val, uint8_t *__restrict__ res_flags,
                                                 uint32_t *__restrict__ loc, uint32_t *__restrict__ locnext,
@@ -89,6 +115,7 @@ __global__ __launch_bounds__(DT) void k_descend(IndexDesc desc, const uint64_t *
             // inside the pads), answer nothing
             q[j] = idx[j] < n ? sk[idx[j]] : KEY_MAX;
         }
+        if (QPL == 1 && MODE == 0 && wsort && !mixed) wave_sort_kv(q[0], idx[0]);
         uint64_t qd[QPL];
 #pragma unroll
         for (int j = 0; j < QPL; j++) qd[j] = q[j] == KEY_MAX ? KEY_MAX - 1 : q[j];
@@ -825,14 +852,14 @@ template <int MODE, int QPL, int DT>
 uint32_t launch_descend_q(Index &ix, hipStream_t s, const uint64_t *sk, const uint32_t *sidx, uint64_t n,
                           uint64_t *out_vals, uint8_t *out_status, uint64_t *res_val, uint8_t *res_flags, uint32_t *loc,
                           uint32_t *locnext, const uint8_t *ops, const uint64_t *vals, uint8_t *sop, uint64_t *svin,
-                          uint2 *dpart, const unsigned int *wflag) {
+                          uint2 *dpart, const unsigned int *wflag, uint32_t wsort) {
     const IndexDesc &d = ix.desc;
     const size_t lds = (size_t)d.lds_entries * 12;
     auto kern = k_descend<MODE, QPL, DT>;
     const uint32_t g = persistent_grid(ix, kern, DT, lds, blocks_for(n, DT * QPL));
     hipLaunchKernelGGL(kern, dim3(g), dim3(DT), lds, s, d, ix.arena_key.as<uint64_t>(), ix.arena_down.as<uint32_t>(),
                        ix.st.key.as<uint64_t>(), ix.st.val.as<uint64_t>(), ix.st.next.as<uint32_t>(),
-                       ix.st.meta.as<uint8_t>(), sk, sidx, (uint32_t)n, ix.dstate, dpart, wflag, out_vals,
+                       ix.st.meta.as<uint8_t>(), sk, sidx, (uint32_t)n, ix.dstate, dpart, wflag, wsort, out_vals,
                        out_status, res_val, res_flags, loc, locnext, ops, vals, sop, svin);
     PI_LAUNCH_CHECK();
     return g;
@@ -842,17 +869,17 @@ template <int MODE, int DT>
 uint32_t launch_descend_b(Index &ix, hipStream_t s, const uint64_t *sk, const uint32_t *sidx, uint64_t n,
                           uint64_t *out_vals, uint8_t *out_status, uint64_t *res_val, uint8_t *res_flags,
                           uint32_t *loc, uint32_t *locnext, const uint8_t *ops, const uint64_t *vals, uint8_t *sop,
-                          uint64_t *svin, uint2 *dpart, const unsigned int *wflag) {
+                          uint64_t *svin, uint2 *dpart, const unsigned int *wflag, uint32_t wsort) {
     switch (ix.cfg.queries_per_lane) {
         case 2:
             return launch_descend_q<MODE, 2, DT>(ix, s, sk, sidx, n, out_vals, out_status, res_val, res_flags, loc,
-                                                 locnext, ops, vals, sop, svin, dpart, wflag);
+                                                 locnext, ops, vals, sop, svin, dpart, wflag, wsort);
         case 4:
             return launch_descend_q<MODE, 4, DT>(ix, s, sk, sidx, n, out_vals, out_status, res_val, res_flags, loc,
-                                                 locnext, ops, vals, sop, svin, dpart, wflag);
+                                                 locnext, ops, vals, sop, svin, dpart, wflag, wsort);
         default:
             return launch_descend_q<MODE, 1, DT>(ix, s, sk, sidx, n, out_vals, out_status, res_val, res_flags, loc,
-                                                 locnext, ops, vals, sop, svin, dpart, wflag);
+                                                 locnext, ops, vals, sop, svin, dpart, wflag, wsort);
     }
 }
 
@@ -862,17 +889,17 @@ template <int MODE>
 uint32_t launch_descend(Index &ix, hipStream_t s, const uint64_t *sk, const uint32_t *sidx, uint64_t n,
                         uint64_t *out_vals, uint8_t *out_status, uint64_t *res_val, uint8_t *res_flags, uint32_t *loc,
                         uint32_t *locnext, const uint8_t *ops, const uint64_t *vals, uint8_t *sop, uint64_t *svin,
-                        uint2 *dpart, const unsigned int *wflag) {
+                        uint2 *dpart, const unsigned int *wflag, uint32_t wsort) {
     switch (ix.cfg.descent_block) {
         case 256:
             return launch_descend_b<MODE, 256>(ix, s, sk, sidx, n, out_vals, out_status, res_val, res_flags, loc,
-                                               locnext, ops, vals, sop, svin, dpart, wflag);
+                                               locnext, ops, vals, sop, svin, dpart, wflag, wsort);
         case 512:
             return launch_descend_b<MODE, 512>(ix, s, sk, sidx, n, out_vals, out_status, res_val, res_flags, loc,
-                                               locnext, ops, vals, sop, svin, dpart, wflag);
+                                               locnext, ops, vals, sop, svin, dpart, wflag, wsort);
         default:
             return launch_descend_b<MODE, 1024>(ix, s, sk, sidx, n, out_vals, out_status, res_val, res_flags, loc,
-                                                locnext, ops, vals, sop, svin, dpart, wflag);
+                                                locnext, ops, vals, sop, svin, dpart, wflag, wsort);
     }
 }
 
@@ -933,6 +960,7 @@ void execute_batch(Index &ix, const uint8_t *ops, const uint64_t *keys, const ui
 void execute_batch(Index &ix, const BatchBuffers &buf, const uint8_t *ops, const uint64_t *keys,
                    const uint64_t *vals, uint64_t n, uint64_t *out_vals, uint8_t *out_status, hipStream_t s,
                    bool one_launch) {
+    TraceRange tr("pi:batch");
     Profiler::Rec rec{};
     auto mark = [&](int k) {
         if (!ix.prof.on) return;
@@ -942,19 +970,30 @@ void execute_batch(Index &ix, const BatchBuffers &buf, const uint8_t *ops, const
     mark(0);
     const uint64_t *sk = nullptr;
     const uint32_t *sidx = nullptr;
-    order_batch(buf, ops, keys, n, s, &sk, &sidx);
+    const uint32_t bits = order_bits(ix);
+    order_batch(buf, ops, keys, n, s, &sk, &sidx, bits);
     mark(1);
-    finish_batch(ix, buf, sk, sidx, ops, vals, n, out_vals, out_status, s, ix.prof.on ? &rec : nullptr, one_launch);
+    finish_batch(ix, buf, sk, sidx, ops, vals, n, out_vals, out_status, s, ix.prof.on ? &rec : nullptr, one_launch,
+                 bits);
+}
+
+uint32_t order_bits(const Index &ix) {
+    if (ix.cfg.queries_per_lane > 1) return 24;  // the wave sort serves one query per lane
+    const uint32_t b = ix.cfg.order_bits;
+    if (b) return b;
+    return ix.recent_writers ? 24 : 16;
 }
 
 void order_batch(const BatchBuffers &buf, const uint8_t *ops, const uint64_t *keys, uint64_t n, hipStream_t so,
-                 const uint64_t **sk, const uint32_t **sidx) {
-    sort_batch_by_range(buf.sort, buf.msd, keys, ops, n, true, so, sk, sidx);
+                 const uint64_t **sk, const uint32_t **sidx, uint32_t pos_bits) {
+    TraceRange tr("pi:order");
+    sort_batch_by_range(buf.sort, buf.msd, keys, ops, n, true, so, sk, sidx, pos_bits);
 }
 
 void finish_batch(Index &ix, const BatchBuffers &buf, const uint64_t *sk, const uint32_t *sidx, const uint8_t *ops,
                   const uint64_t *vals, uint64_t n, uint64_t *out_vals, uint8_t *out_status, hipStream_t s,
-                  Profiler::Rec *prec, bool one_launch) {
+                  Profiler::Rec *prec, bool one_launch, uint32_t pos_bits) {
+    TraceRange tr("pi:descend+update");
     buf.bws.ensure(n);
     DevState *st = ix.dstate;
     auto mark = [&](int k) {
@@ -972,7 +1011,8 @@ void finish_batch(Index &ix, const BatchBuffers &buf, const uint64_t *sk, const 
     const uint32_t dgrid = launch_descend<0>(ix, s, sk, sidx, n, out_vals, out_status, w.res_val.as<uint64_t>(),
                                              w.res_flags.as<uint8_t>(), w.loc.as<uint32_t>(), w.locnext.as<uint32_t>(),
                                              ops, vals, w.sop.as<uint8_t>(), w.svin.as<uint64_t>(),
-                                             w.dpart.as<uint2>(), buf.msd.wflag.as<unsigned int>());
+                                             w.dpart.as<uint2>(), buf.msd.wflag.as<unsigned int>(),
+                                             pos_bits == 16 ? 1u : 0u);
     if (dgrid > BatchWorkspace::DPART) throw Error{PI_ERR_DEVICE, "internal error: descent grid above its count slots"};
     PI_LAUNCH_CHECK();
     mark(2);
@@ -1247,7 +1287,7 @@ bool writer_selftest(Index &ix, hipStream_t s, uint32_t *same_writer_err, uint32
 void debug_interceptions(Index &ix, const uint64_t *keys, uint64_t n, uint64_t *icpt_keys, uint8_t *is_head,
                          hipStream_t s) {
     launch_descend<1>(ix, s, keys, nullptr, n, icpt_keys, is_head, nullptr, nullptr, nullptr, nullptr, nullptr,
-                      nullptr, nullptr, nullptr, nullptr, nullptr);
+                      nullptr, nullptr, nullptr, nullptr, nullptr, 0u);
 }
 
 }  // namespace pi

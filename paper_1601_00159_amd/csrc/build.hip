@@ -473,6 +473,7 @@ void grow_storage(Index &ix, uint64_t need, hipStream_t s) {
 }
 
 void bulk_load(Index &ix, const uint64_t *keys, const uint64_t *vals, uint64_t n, hipStream_t s) {
+    TraceRange tr("pi:bulk_load");
     bg_quiesce(ix);
     ix.changes_base = 0;
     const uint64_t *sk = nullptr;
@@ -601,6 +602,7 @@ uint64_t export_live(Index &ix, uint64_t *okeys, uint64_t *ovals, uint64_t cap, 
 }
 
 void rebuild(Index &ix, hipStream_t s) {
+    TraceRange tr("pi:rebuild");
     bg_quiesce(ix);  // a background index rebuild reads the storage about to be replaced
     Profiler::Rec rec{};
     if (ix.prof.on) {

@@ -178,6 +178,7 @@ void group_capacity(Index &ix, const pi_batch &b, hipStream_t s) {
 
 void run_group(pi_group *g, pi_index *const *indices, const pi_batch *batches, uint32_t count, hipStream_t s,
                uint64_t fused_max, const uint8_t *ops_override) {
+    TraceRange tr("pi:group");
     for (uint32_t i = 0; i < count; i++) indices[i]->ix.epoch++;
     settle_previous(g, s);
     for (uint32_t i = 0; i < count; i++)

@@ -6,6 +6,7 @@
 #include <vector>
 
 #include "pi_internal.h"
+#include "trace.h"
 
 namespace pi {
 
@@ -229,11 +230,17 @@ void execute_batch(Index &ix, const BatchBuffers &buf, const uint8_t *ops, const
 // writes only buf.sort / buf.msd, so it may run on another stream beside the
 // steps of an earlier batch; finish_batch (the descent and everything after
 // it, on s) must come after it.  prec: profiler record to complete, or null.
+// pos_bits: the width of the ordering's range position (order_bits), which
+// finish_batch must be told too (16: the descent sorts each wave's queries).
 void order_batch(const BatchBuffers &buf, const uint8_t *ops, const uint64_t *keys, uint64_t n, hipStream_t so,
-                 const uint64_t **sk, const uint32_t **sidx);
+                 const uint64_t **sk, const uint32_t **sidx, uint32_t pos_bits);
 void finish_batch(Index &ix, const BatchBuffers &buf, const uint64_t *sk, const uint32_t *sidx, const uint8_t *ops,
                   const uint64_t *vals, uint64_t n, uint64_t *out_vals, uint8_t *out_status, hipStream_t s,
-                  Profiler::Rec *prec, bool one_launch = false);
+                  Profiler::Rec *prec, bool one_launch, uint32_t pos_bits);
+// Width of a batch's range position: pi_config::order_bits, or 16 after a
+// batch without INSERT/DELETE (such a batch is ordered only for locality) and
+// 24 after one with them (a full order costs the fix-up less).
+uint32_t order_bits(const Index &ix);
 // Same result through a captured graph of the hot path for the smallest
 // power-of-two class >= n (padding with invalid queries).
 void execute_batch_graph(Index &ix, const uint8_t *ops, const uint64_t *keys, const uint64_t *vals, uint64_t n,

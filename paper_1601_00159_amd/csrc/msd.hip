@@ -89,7 +89,8 @@ __global__ __launch_bounds__(MT) void k_minmax(const uint64_t *__restrict__ keys
 // and the writers flag (when given): the first kernels to touch them run
 // after this one.
 __global__ __launch_bounds__(MT) void k_make_map(const uint64_t *__restrict__ partials, uint32_t nparts,
-                                                 RangeMap *map, unsigned int *nbig, unsigned int *writers) {
+                                                 RangeMap *map, unsigned int *nbig, unsigned int *writers,
+                                                 uint32_t bits) {
     __shared__ uint64_t s_red[MNW * 2];
     uint64_t lo = ~0ull, hi = 0;
     for (uint32_t i = threadIdx.x; i < nparts; i += MT) {
@@ -113,7 +114,7 @@ __global__ __launch_bounds__(MT) void k_make_map(const uint64_t *__restrict__ pa
             lo = s_red[i] < lo ? s_red[i] : lo;
             hi = s_red[MNW + i] > hi ? s_red[MNW + i] : hi;
         }
-        *map = span_map(lo, hi);
+        *map = span_map(lo, hi, bits);
         *nbig = 0;
         if (writers) *writers = 0;
     }
@@ -709,7 +710,9 @@ void MsdWorkspace::release() {
 }
 
 void sort_batch_by_range(SortWorkspace &ws, MsdWorkspace &mw, const uint64_t *keys, const uint8_t *ops, uint64_t n,
-                         bool batch, hipStream_t s, const uint64_t **out_keys, const uint32_t **out_idx) {
+                         bool batch, hipStream_t s, const uint64_t **out_keys, const uint32_t **out_idx,
+                         uint32_t pos_bits) {
+    if (pos_bits != 16 && pos_bits != 24) throw Error{PI_ERR_INVALID_ARG, "internal error: range position width"};
     ws.ensure(n);
     mw.ensure(n);
     uint64_t *ka = ws.keys[0].as<uint64_t>(), *kb = ws.keys[1].as<uint64_t>();
@@ -723,12 +726,18 @@ void sort_batch_by_range(SortWorkspace &ws, MsdWorkspace &mw, const uint64_t *ke
     hipLaunchKernelGGL(k_minmax, dim3(parts), dim3(MT), 0, s, keys, nn, mw.partials.as<uint64_t>());
     unsigned int *wf = batch ? mw.wflag.as<unsigned int>() : nullptr;
     hipLaunchKernelGGL(k_make_map, dim3(1), dim3(MT), 0, s, mw.partials.as<uint64_t>(), parts, map,
-                       mw.nbig.as<unsigned int>(), wf);
+                       mw.nbig.as<unsigned int>(), wf, pos_bits);
     PI_LAUNCH_CHECK();
-    // group by the 24-bit position inside the span, one byte per pass
-    radix_pass(ws, keys, nullptr, ops, nn, 0, map, wf, ka, ia, s);
-    radix_pass(ws, ka, ia, nullptr, nn, 8, map, nullptr, kb, ib, s);
-    radix_pass(ws, kb, ib, nullptr, nn, 16, map, nullptr, ka, ia, s);
+    // group by the position inside the span, one byte per pass; the result
+    // lands in (ka, ia) either way
+    if (pos_bits == 24) {
+        radix_pass(ws, keys, nullptr, ops, nn, 0, map, wf, ka, ia, s);
+        radix_pass(ws, ka, ia, nullptr, nn, 8, map, nullptr, kb, ib, s);
+        radix_pass(ws, kb, ib, nullptr, nn, 16, map, nullptr, ka, ia, s);
+    } else {
+        radix_pass(ws, keys, nullptr, ops, nn, 0, map, wf, kb, ib, s);
+        radix_pass(ws, kb, ib, nullptr, nn, 8, map, nullptr, ka, ia, s);
+    }
     const uint32_t nwin = (nn + WNOM - 1) / WNOM;
     hipLaunchKernelGGL(k_fixup, dim3(nwin), dim3(WT), 0, s, ka, ia, nn, map, mw.big.as<uint32_t>(),
                        mw.nbig.as<unsigned int>(), mw.dirty.as<unsigned int>(), (const unsigned int *)wf);

@@ -193,15 +193,16 @@ __device__ __forceinline__ uint32_t tower_height(uint64_t key, uint64_t seed, ui
     return 1 + extra;
 }
 
-// Key -> 24-bit position inside the batch's key span [lo, ...]: the top 24
-// significant bits of key - lo (keys below lo map to 0, above the span to
-// 2^24-1).  Monotone in the key, so ordering by it, then by key among equal
-// positions, orders by key.
+// Key -> position of `bits` bits (24, or 16 for a batch ordered only for
+// locality) inside the batch's key span [lo, ...]: the top significant bits of
+// key - lo (keys below lo map to 0, above the span to the largest position).
+// Monotone in the key, so ordering by it, then by key among equal positions,
+// orders by key.
 constexpr uint32_t RANGE_BITS = 24;
 struct RangeMap {
     uint64_t lo;
     uint32_t shift;
-    uint32_t pad_;
+    uint32_t top;  // largest position, 2^bits - 1
 };
 
 __device__ __forceinline__ uint64_t shfl_xor_u64(uint64_t x, int m) {
@@ -210,23 +211,23 @@ __device__ __forceinline__ uint64_t shfl_xor_u64(uint64_t x, int m) {
 }
 
 // Map of the span [lo, hi] of a batch's valid keys (lo > hi: no valid key)
-// onto RANGE_BITS-bit positions.
-__device__ __forceinline__ RangeMap span_map(uint64_t lo, uint64_t hi) {
+// onto positions of `bits` bits.
+__device__ __forceinline__ RangeMap span_map(uint64_t lo, uint64_t hi, uint32_t bits) {
     if (lo > hi) lo = hi = 0;
     const uint64_t span = hi - lo;
     uint32_t sbits = 0;
     while (sbits < 64 && (span >> sbits) != 0) sbits++;
     RangeMap m;
     m.lo = lo;
-    m.shift = sbits > RANGE_BITS ? sbits - RANGE_BITS : 0;
-    m.pad_ = 0;
+    m.shift = sbits > bits ? sbits - bits : 0;
+    m.top = (1u << bits) - 1;
     return m;
 }
 
 __device__ __forceinline__ uint32_t range_pos(uint64_t k, const RangeMap &m) {
     if (k <= m.lo) return 0;
     const uint64_t r = (k - m.lo) >> m.shift;
-    return r > ((1u << RANGE_BITS) - 1) ? ((1u << RANGE_BITS) - 1) : (uint32_t)r;
+    return r > m.top ? m.top : (uint32_t)r;
 }
 
 // ---------------------------------------------------------------------------
@@ -299,8 +300,13 @@ struct MsdWorkspace {
     void ensure(uint64_t n);
     void release();
 };
+// pos_bits (24 or 16): the width of the range position, one radix pass per
+// byte.  16 orders by key only to 1/65536 of the span before the in-group
+// fix-up, which is all a batch without INSERT/DELETE needs (its order serves
+// locality; the descent then sorts each wave's queries itself).
 void sort_batch_by_range(SortWorkspace &ws, MsdWorkspace &mw, const uint64_t *keys, const uint8_t *ops, uint64_t n,
-                         bool batch, hipStream_t s, const uint64_t **out_keys, const uint32_t **out_idx);
+                         bool batch, hipStream_t s, const uint64_t **out_keys, const uint32_t **out_idx,
+                         uint32_t pos_bits = RANGE_BITS);
 
 // One stable 8-bit LSD pass (hist, column scan, scatter).  The digit is
 // (key >> shift) & 255, or, when map is not null, (range_pos(key) >> shift)

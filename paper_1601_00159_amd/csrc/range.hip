@@ -258,6 +258,7 @@ uint32_t blocks_of(uint64_t n, uint64_t t) { return (uint32_t)((n + t - 1) / t);
 // order + locate; returns the sorted lower bounds and their range ids
 void locate(Index &ix, const uint64_t *lo, const uint64_t *hi, uint64_t n, hipStream_t s, const uint64_t **slo,
             const uint32_t **sperm) {
+    TraceRange tr("pi:range_locate");
     sort_batch_by_range(ix.sortws, ix.msdws, lo, nullptr, n, false, s, slo, sperm);
     ix.rng[0].ensure(n * 4);
     ix.rng[1].ensure(n * 4);

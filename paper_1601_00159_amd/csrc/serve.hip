@@ -97,6 +97,7 @@ uint64_t serve_batch_limit(uint32_t inflight) {
 void serve_loop(const double *arrival, uint64_t n, const ServePlan &plan, hipStream_t s,
                 const std::function<void(uint64_t, uint64_t)> &launch, double *done_us, uint64_t *batch_end,
                 uint64_t &nb) {
+    TraceRange tr("pi:serve");
     EventPool pool(plan.max_inflight + 1);
     hipEvent_t ev0 = pool.take();
     const auto clock0 = std::chrono::steady_clock::now();

@@ -48,7 +48,8 @@ class Index:
                  rebuild_policy: str = "threshold", capacity_hint: int = 0, lds_levels: int = 0,
                  profile: int = 0, queries_per_lane: int = 0, blocks_per_cu: int = 0, lds_budget: int = 0,
                  descent_block: int = 0, graph_max_log2: int = 0, small_batch_log2: int = 0,
-                 rebuild_min: int = 4096, compact_percent: int = 0, check_writers: int = 0, post_form: int = 0):
+                 rebuild_min: int = 4096, compact_percent: int = 0, check_writers: int = 0, post_form: int = 0,
+                 order_bits: int = 0):
         self._L = _lib.lib()
         cfg = _lib.pi_config()
         check(self._L.pi_config_default(ctypes.byref(cfg)))
@@ -71,6 +72,7 @@ class Index:
         cfg.compact_percent = compact_percent
         cfg.check_writers = check_writers
         cfg.post_form = post_form
+        cfg.order_bits = order_bits
         h = ctypes.c_void_p()
         check(self._L.pi_create(ctypes.byref(cfg), ctypes.byref(h)))
         self._h = h

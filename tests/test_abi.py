@@ -74,7 +74,8 @@ def test_config_default_without_gpu():
 @pytest.mark.parametrize("field,value", [("compact_percent", 1001), ("lds_budget", 13001), ("descent_block", 300),
                                          ("queries_per_lane", 3), ("small_batch_log2", 13), ("graph_max_log2", 11),
                                          ("max_height", 1), ("log2_inv_p", 9), ("rebuild_policy", 5),
-                                         ("check_writers", 2), ("post_form", 3)])
+                                         ("check_writers", 2), ("post_form", 3),
+                                         ("order_bits", 20)])
 def test_create_rejects_bad_config_before_device_work(field, value):
     """Every range check of pi_config runs before any device call: on this
     GPU-less host the error names the field, not the missing device."""

@@ -179,20 +179,22 @@ def _random_batch(rng, pool, n, p_invalid=0.01):
     return ops, keys, vals
 
 
-@pytest.mark.parametrize("policy,form", [("never", 0), ("always", 0), ("threshold", 0), ("never", 1),
-                                         ("threshold", 2)])
-def test_mixed_batches_vs_oracle(policy, form):
+@pytest.mark.parametrize("policy,form,bits", [("never", 0, 0), ("always", 0, 0), ("threshold", 0, 0),
+                                              ("never", 1, 16), ("threshold", 2, 24), ("never", 2, 16)])
+def test_mixed_batches_vs_oracle(policy, form, bits):
     """Mixed and SEARCH-only batches in turn (so that the default form of the
-    post-descent steps switches between its one launch and the separate
-    kernels), and each form forced."""
-    rng = np.random.default_rng({"never": 1, "always": 2, "threshold": 3}[policy] + 10 * form)
+    post-descent steps, and the width of the ordering's range position,
+    switch with them), and each form and width forced: batches with updates
+    ordered by a 16-bit position leave larger groups to the in-group fix-up,
+    and SEARCH-only ones leave each wave's queries to the descent's sort."""
+    rng = np.random.default_rng({"never": 1, "always": 2, "threshold": 3}[policy] + 10 * form + bits)
     lk = rng.integers(0, 1 << 63, size=50_000, dtype=np.uint64)
     lv = rng.integers(0, 1 << 64, size=50_000, dtype=np.uint64, endpoint=False)
     pool = np.concatenate([lk[:20_000], rng.integers(0, 1 << 63, size=20_000, dtype=np.uint64),
                            np.array([0, (1 << 64) - 2], dtype=np.uint64)])
     orc = SkipList()
     orc.bulk_load(lk, lv)
-    with Index(rebuild_policy=policy, rebuild_fraction=0.05, rebuild_min=1, post_form=form) as ix:
+    with Index(rebuild_policy=policy, rebuild_fraction=0.05, rebuild_min=1, post_form=form, order_bits=bits) as ix:
         ix.bulk_load(lk, lv)
         tot = {"queries": 0, "hits": 0, "invalid": 0}
         for b in range(9):
