@@ -549,12 +549,13 @@ def run_many(args):
                             torch.empty(len(b), dtype=torch.int64, device=dev),
                             torch.empty(len(b), dtype=torch.uint8, device=dev)) for b in batches])
     q_per_round = [sum(len(b) for b in batches) for batches in w.rounds]
-    for mode in ("per-index", "group"):
+    for mode in args.many_modes.split(","):
         ixs = [Index(device=0, rebuild_policy=args.many_policy) for _ in w.loads]
         for ix, (k, v) in zip(ixs, w.loads):
             ix.bulk_load(k, v)
         torch.cuda.synchronize()
-        g = Group() if mode == "group" else None
+        threads = 1 if mode == "group-1-thread" else 0
+        g = Group(host_threads=threads) if mode.startswith("group") else None
         fused = None
         shape = None
         if g is not None:
@@ -596,6 +597,7 @@ def run_many(args):
             "config": {"workload": w.name, "indices": args.indices, "total_keys": int(total_keys),
                        "queries_per_round": int(np.mean(q_per_round)), "op_mix": "90/5/5 S/I/D", "mode": mode,
                        "fused_max": fused, "rebuild_policy": args.many_policy,
+                       "host_threads": (threads or 4) if g is not None else 1,
                        "descent_shape": shape,
                        "parallelism": "single GPU"},
             "latency_ms": {"round_p50": round(float(np.percentile(lat, 50)) * 1e3, 3),
@@ -629,6 +631,8 @@ def main():
                          "write: write-heavy Zipf batches; serve: continuous batching of Poisson arrivals; "
                          "many: one batch on each of many indices per round")
     ap.add_argument("--indices", type=int, default=512, help="indices (--workload many)")
+    ap.add_argument("--many-modes", default="per-index,group",
+                    help="comma list of per-index, group (4 host threads), group-1-thread (--workload many)")
     ap.add_argument("--many-policy", default="threshold", choices=["threshold", "never", "slices"],
                     help="rebuild policy of the indices (--workload many)")
     ap.add_argument("--rebuild-policy", default="background", choices=["threshold", "background", "never"],

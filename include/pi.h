@@ -329,6 +329,11 @@ typedef struct {
     uint32_t struct_size;  /* sizeof(pi_group_config) */
     uint32_t max_indices;  /* most indices per call (0 = 4096) */
     uint64_t fused_max;    /* largest batch run in the fused launch (0 = 4096) */
+    uint32_t host_threads; /* host threads that issue the work of the indices
+                            * with large batches or a rebuild due, each on a
+                            * lane stream of its own (0 = 4, at most 4; 1 =
+                            * everything from the calling thread) */
+    uint32_t reserved;     /* must be 0 */
 } pi_group_config;
 
 pi_status pi_group_config_default(pi_group_config *cfg);
@@ -338,8 +343,10 @@ pi_status pi_group_destroy(pi_group *g);
 /* Runs batches[i] on indices[i] for i < count, asynchronously on the stream:
  * batches of at most fused_max queries in one persistent fused launch on a
  * stream of the group's own, the others on the multi-kernel path spread over
- * four lane streams of the group; all of it is joined back into the caller's
- * stream.  The indices must be distinct, live on one device and not be used
+ * four lane streams of the group, issued by host_threads host threads (the
+ * calling one and workers that live for the call); the rebuilds the indices'
+ * policies start at the call (for the counters of the group's previous call)
+ * run the same way; all of it is joined back into the caller's stream.  The indices must be distinct, live on one device and not be used
  * by other calls until this one completes.  Errors: PI_ERR_INVALID_ARG (NULL pointers,
  * count above max_indices, a repeated index, mixed devices, n above 2^31 - 1),
  * PI_ERR_CAPACITY (an index with a fixed capacity has no room; nothing is

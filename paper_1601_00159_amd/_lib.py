@@ -72,7 +72,8 @@ class pi_batch(ctypes.Structure):
 
 
 class pi_group_config(ctypes.Structure):
-    _fields_ = [("struct_size", ctypes.c_uint32), ("max_indices", ctypes.c_uint32), ("fused_max", ctypes.c_uint64)]
+    _fields_ = [("struct_size", ctypes.c_uint32), ("max_indices", ctypes.c_uint32), ("fused_max", ctypes.c_uint64),
+                ("host_threads", ctypes.c_uint32), ("reserved", ctypes.c_uint32)]
 
 
 class PiError(RuntimeError):

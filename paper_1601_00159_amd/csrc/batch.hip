@@ -1033,11 +1033,12 @@ void finish_batch(Index &ix, const BatchBuffers &buf, const uint64_t *sk, const 
     const bool fused = cap_status == hipStreamCaptureStatusNone &&
                        (form == 1 || (form == 0 && (one_launch || !ix.recent_writers)));
     if (fused) {
-        static int occ = 0;
-        if (!occ) {
-            PI_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, k_post, OT, 0));
-            if (occ < 1) throw Error{PI_ERR_DEVICE, "fused post-descent step cannot be resident"};
-        }
+        static const int occ = [] {  // once per process, thread-safe
+            int o = 0;
+            PI_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&o, k_post, OT, 0));
+            if (o < 1) throw Error{PI_ERR_DEVICE, "fused post-descent step cannot be resident"};
+            return o;
+        }();
         // two blocks per CU: every block that takes part costs same-address
         // atomics (joining, each barrier), slow with five blocks per CU
         const uint32_t grid =

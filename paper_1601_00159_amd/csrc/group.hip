@@ -15,9 +15,12 @@
 // The threshold between the two paths is picked by an autotuner that times
 // SEARCH-only replays of the caller's batches.
 #include <algorithm>
+#include <atomic>
 #include <chrono>
+#include <exception>
 #include <cstring>
 #include <string>
+#include <thread>
 #include <unordered_set>
 #include <vector>
 
@@ -114,10 +117,95 @@ void ensure_host(pi_group *g, uint32_t count) {
 }
 
 // Counters of the previous call: storage use and the threshold rebuild.
+void ensure_lanes(pi_group *g) {
+    if (g->ev_fork) return;
+    for (int k = 0; k < pi_group::LANES; k++) {
+        if (!g->lane[k]) PI_HIP(hipStreamCreateWithFlags(&g->lane[k], hipStreamNonBlocking));
+        if (!g->ev_lane[k]) PI_HIP(hipEventCreateWithFlags(&g->ev_lane[k], hipEventDisableTiming));
+    }
+    PI_HIP(hipEventCreateWithFlags(&g->ev_fork, hipEventDisableTiming));
+}
+
+// Runs fn(j, stream) for every job j < njobs, the jobs touching disjoint
+// indices, on the group's lane streams (ordered after the work already on s,
+// joined back into s).  Up to host_threads host threads take the jobs from a
+// shared counter, each issuing on a lane stream of its own: a round over many
+// indices is bound by the host's launches (a large batch is ~16 launches, a
+// rebuild ~30 plus a wait for its index's counters), not by the device.  The
+// first error a job raises stops the taking of new jobs and is rethrown once
+// every thread has finished and the lanes are joined.
+template <class F>
+void on_lanes(pi_group *g, hipStream_t s, uint32_t njobs, F &&fn) {
+    if (!njobs) return;
+    ensure_lanes(g);
+    const int lanes = (int)std::min<uint32_t>(njobs, pi_group::LANES);
+    const int threads = std::min<int>(lanes, (int)g->cfg.host_threads);
+    PI_HIP(hipEventRecord(g->ev_fork, s));
+    for (int k = 0; k < lanes; k++) PI_HIP(hipStreamWaitEvent(g->lane[k], g->ev_fork, 0));
+    int dev = 0;
+    PI_HIP(hipGetDevice(&dev));
+    std::atomic<uint32_t> next{0};
+    std::atomic<bool> failed{false};
+    std::exception_ptr err[pi_group::LANES];
+    auto work = [&](int t) {
+        try {
+            if (t) PI_HIP(hipSetDevice(dev));
+            uint32_t j;
+            // one thread (host_threads 1) cycles the lanes as the jobs come
+            for (uint32_t m = 0; !failed.load() && (j = next.fetch_add(1)) < njobs; m++)
+                fn(j, g->lane[threads == 1 ? (int)(m % lanes) : t]);
+        } catch (...) {
+            err[t] = std::current_exception();
+            failed.store(true);
+        }
+    };
+    std::vector<std::thread> th;
+    th.reserve(threads - 1);
+    for (int t = 1; t < threads; t++) th.emplace_back(work, t);
+    work(0);
+    for (std::thread &t : th) t.join();
+    for (int k = 0; k < lanes; k++) {
+        PI_HIP(hipEventRecord(g->ev_lane[k], g->lane[k]));
+        PI_HIP(hipStreamWaitEvent(s, g->ev_lane[k], 0));
+    }
+    for (int t = 0; t < threads; t++)
+        if (err[t]) std::rethrow_exception(err[t]);
+}
+
+// The index's rebuild policy after a batch whose counters are st.
+void apply_policy(Index &ix, const DevState &st, hipStream_t s) {
+    const uint32_t pol = ix.cfg.rebuild_policy;
+    const double thr = rebuild_threshold(ix);
+    if (pol == PI_REBUILD_BACKGROUND || pol == PI_REBUILD_SLICES) {
+        if (pol == PI_REBUILD_BACKGROUND) bg_advance(ix);
+        const double compact = (ix.cfg.compact_percent ? ix.cfg.compact_percent : 100) / 100.0 *
+                               (double)std::max<uint64_t>(ix.nbase, 1);
+        if ((double)st.changes >= std::max(compact, thr)) {
+            rebuild(ix, s);
+            ix.ring_seen = ix.ring_head;
+        } else if (st.changes >= ix.changes_base && (double)(st.changes - ix.changes_base) >= thr) {
+            if (pol == PI_REBUILD_BACKGROUND) {
+                bg_start(ix, st, s);
+            } else if (slice_round(ix, st.nused, s)) {
+                ix.changes_base = st.changes;
+            } else {
+                rebuild(ix, s);
+                ix.ring_seen = ix.ring_head;
+            }
+        }
+        return;
+    }
+    if ((pol == PI_REBUILD_ALWAYS && st.changes > 0) || (double)st.changes >= thr) {
+        rebuild(ix, s);
+        ix.ring_seen = ix.ring_head;
+    }
+}
+
 void settle_previous(pi_group *g, hipStream_t s) {
     if (!g->pending) return;
     PI_HIP(hipEventSynchronize(g->ev));
     g->pending = false;
+    std::vector<uint32_t> act;  // indices whose policy may act
     for (size_t k = 0; k < g->last.size(); k++) {
         Index &ix = g->last[k]->ix;
         const DevState &st = g->h_states[k];
@@ -130,33 +218,10 @@ void settle_previous(pi_group *g, hipStream_t s) {
         // copy (group or single calls) bounds the storage in use now
         ix.used_upper = std::min<uint64_t>(ix.used_upper, st.nused + (ix.enq_queries - g->last_enq[k]));
         ix.recent_writers = st.b_writers != 0;  // the form of the next large batch's post-descent steps
-        const uint32_t pol = ix.cfg.rebuild_policy;
-        if (pol == PI_REBUILD_NEVER) continue;
-        const double thr = rebuild_threshold(ix);
-        if (pol == PI_REBUILD_BACKGROUND || pol == PI_REBUILD_SLICES) {
-            if (pol == PI_REBUILD_BACKGROUND) bg_advance(ix);
-            const double compact = (ix.cfg.compact_percent ? ix.cfg.compact_percent : 100) / 100.0 *
-                                   (double)std::max<uint64_t>(ix.nbase, 1);
-            if ((double)st.changes >= std::max(compact, thr)) {
-                rebuild(ix, s);
-                ix.ring_seen = ix.ring_head;
-            } else if (st.changes >= ix.changes_base && (double)(st.changes - ix.changes_base) >= thr) {
-                if (pol == PI_REBUILD_BACKGROUND) {
-                    bg_start(ix, st, s);
-                } else if (slice_round(ix, st.nused, s)) {
-                    ix.changes_base = st.changes;
-                } else {
-                    rebuild(ix, s);
-                    ix.ring_seen = ix.ring_head;
-                }
-            }
-            continue;
-        }
-        if ((pol == PI_REBUILD_ALWAYS && st.changes > 0) || (double)st.changes >= thr) {
-            rebuild(ix, s);
-            ix.ring_seen = ix.ring_head;
-        }
+        if (ix.cfg.rebuild_policy != PI_REBUILD_NEVER) act.push_back((uint32_t)k);
     }
+    on_lanes(g, s, (uint32_t)act.size(),
+             [&](uint32_t j, hipStream_t ls) { apply_policy(g->last[act[j]]->ix, g->h_states[act[j]], ls); });
     g->last.clear();
     g->last_enq.clear();
 }
@@ -231,37 +296,20 @@ void run_group(pi_group *g, pi_index *const *indices, const pi_batch *batches, u
         PI_LAUNCH_CHECK();
         PI_HIP(hipEventRecord(g->ev_fused, fs));
     }
-    // large batches: the GPU-wide path, spread round-robin over the group's
-    // lane streams (the indices are disjoint, and one batch of a few hundred
-    // thousand queries does not fill the GPU), joined back into the caller's
-    // stream
-    uint32_t nlarge = 0;
-    for (uint32_t i = 0; i < count; i++) nlarge += batches[i].n > fused_max;
-    const int lanes = (int)std::min<uint32_t>(nlarge, pi_group::LANES);
-    if (lanes > 0) {
-        if (!g->ev_fork) {
-            PI_HIP(hipEventCreateWithFlags(&g->ev_fork, hipEventDisableTiming));
-            for (int k = 0; k < pi_group::LANES; k++) {
-                PI_HIP(hipStreamCreateWithFlags(&g->lane[k], hipStreamNonBlocking));
-                PI_HIP(hipEventCreateWithFlags(&g->ev_lane[k], hipEventDisableTiming));
-            }
-        }
-        PI_HIP(hipEventRecord(g->ev_fork, s));
-        for (int k = 0; k < lanes; k++) PI_HIP(hipStreamWaitEvent(g->lane[k], g->ev_fork, 0));
-        uint32_t r = 0;
-        for (uint32_t i = 0; i < count; i++) {
-            const pi_batch &b = batches[i];
-            if (!b.n || b.n <= fused_max) continue;
-            // one launch for the steps after the descent: the group call is
-            // bound by the host's launches, not by these batches' device time
-            execute_batch(indices[i]->ix, ops_override ? ops_override : b.d_ops, b.d_keys, b.d_values, b.n,
-                          b.d_out_values, b.d_out_status, g->lane[r++ % lanes], true);
-        }
-        for (int k = 0; k < lanes; k++) {
-            PI_HIP(hipEventRecord(g->ev_lane[k], g->lane[k]));
-            PI_HIP(hipStreamWaitEvent(s, g->ev_lane[k], 0));
-        }
-    }
+    // large batches: the GPU-wide path on the group's lane streams (the
+    // indices are disjoint, and one batch of a few hundred thousand queries
+    // does not fill the GPU), joined back into the caller's stream
+    std::vector<uint32_t> large;
+    for (uint32_t i = 0; i < count; i++)
+        if (batches[i].n > fused_max) large.push_back(i);
+    on_lanes(g, s, (uint32_t)large.size(), [&](uint32_t j, hipStream_t ls) {
+        const uint32_t i = large[j];
+        const pi_batch &b = batches[i];
+        // one launch for the steps after the descent: the group call is
+        // bound by the host's launches, not by these batches' device time
+        execute_batch(indices[i]->ix, ops_override ? ops_override : b.d_ops, b.d_keys, b.d_values, b.n,
+                      b.d_out_values, b.d_out_status, ls, true);
+    });
     if (!fused.empty()) PI_HIP(hipStreamWaitEvent(s, g->ev_fused, 0));
     // one copy of every index's counters
     uint32_t ns = 0;
@@ -342,6 +390,7 @@ pi_status pi_group_config_default(pi_group_config *cfg) {
     cfg->struct_size = sizeof(pi_group_config);
     cfg->max_indices = 4096;
     cfg->fused_max = 4096;
+    cfg->host_threads = pi_group::LANES;
     return PI_OK;
 }
 
@@ -355,8 +404,10 @@ pi_status pi_group_create(const pi_group_config *cfg, pi_group **out) {
         c = *cfg;
         if (!c.max_indices) c.max_indices = 4096;
         if (!c.fused_max) c.fused_max = 4096;
+        if (!c.host_threads) c.host_threads = pi_group::LANES;
     }
     if (c.fused_max > (1ull << 31) - 1) return PI_ERR_INVALID_ARG;
+    if (c.host_threads > (uint32_t)pi_group::LANES || c.reserved) return PI_ERR_INVALID_ARG;
     pi_group *g = new pi_group;
     g->cfg = c;
     if (hipEventCreateWithFlags(&g->ev, hipEventDisableTiming) != hipSuccess) {

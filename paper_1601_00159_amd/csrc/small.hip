@@ -46,11 +46,13 @@ void execute_batch_small(Index &ix, const uint8_t *ops, const uint64_t *keys, co
     v.owner = wc.owner;
     BatchView b{ops, keys, vals, (uint32_t)n, out_vals, out_status, wc.unit};
     const uint32_t lds = SmallLds::bytes();
-    static bool attr = false;
-    if (!attr) {
+    // once per process (thread-safe: calls on different indices may run in
+    // parallel threads)
+    static const bool attr = [&] {
         PI_HIP(hipFuncSetAttribute((const void *)k_batch_block, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
-        attr = true;
-    }
+        return true;
+    }();
+    (void)attr;
     hipLaunchKernelGGL(k_batch_block, dim3(1), dim3(SBT), lds, s, v, b);
     PI_LAUNCH_CHECK();
 }

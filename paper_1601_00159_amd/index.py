@@ -253,7 +253,7 @@ class Group:
     """Many indices, one launch (pi_group_*): runs one batch on each of
     several distinct indices of one device."""
 
-    def __init__(self, fused_max: int = 0, max_indices: int = 0):
+    def __init__(self, fused_max: int = 0, max_indices: int = 0, host_threads: int = 0):
         self._L = _lib.lib()
         cfg = _lib.pi_group_config()
         check(self._L.pi_group_config_default(ctypes.byref(cfg)))
@@ -261,6 +261,8 @@ class Group:
             cfg.fused_max = fused_max
         if max_indices:
             cfg.max_indices = max_indices
+        if host_threads:
+            cfg.host_threads = host_threads
         h = ctypes.c_void_p()
         check(self._L.pi_group_create(ctypes.byref(cfg), ctypes.byref(h)))
         self._h = h

@@ -39,7 +39,8 @@ def test_struct_layout_matches_header(tmp_path):
     src.write_text('#include <stdio.h>\n#include <stddef.h>\n#include "pi.h"\n'
                    'int main(void){printf("%zu %zu %zu %zu %zu %zu\\n", sizeof(pi_config), sizeof(pi_stats),'
                    ' offsetof(pi_config, capacity_hint), offsetof(pi_stats, level_size),'
-                   ' sizeof(pi_serve_config), offsetof(pi_serve_config, max_batch));return 0;}\n')
+                   ' sizeof(pi_serve_config), offsetof(pi_serve_config, max_batch));'
+                   'printf("%zu %zu\\n", sizeof(pi_group_config), offsetof(pi_group_config, host_threads));return 0;}\n')
     exe = tmp_path / "sz"
     subprocess.run(["gcc", "-std=c11", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)], check=True)
     out = subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout.split()
@@ -49,6 +50,8 @@ def test_struct_layout_matches_header(tmp_path):
     assert int(out[3]) == _lib.pi_stats.level_size.offset
     assert int(out[4]) == ctypes.sizeof(_lib.pi_serve_config)
     assert int(out[5]) == _lib.pi_serve_config.max_batch.offset
+    assert int(out[6]) == ctypes.sizeof(_lib.pi_group_config)
+    assert int(out[7]) == _lib.pi_group_config.host_threads.offset
 
 
 def test_config_default_without_gpu():
@@ -69,6 +72,23 @@ def test_config_default_without_gpu():
     assert L.pi_serve_config_default(ctypes.byref(scfg)) == _lib.PI_OK
     assert scfg.struct_size == ctypes.sizeof(_lib.pi_serve_config)
     assert scfg.deadline_us == 100.0 and scfg.max_inflight == 1 and scfg.max_batch == 0
+
+
+@pytest.mark.parametrize("field,value", [("host_threads", 5), ("reserved", 1), ("fused_max", 1 << 31),
+                                         ("struct_size", 8)])
+def test_group_create_rejects_bad_config_before_device_work(field, value):
+    """The group's range checks run before its first device call."""
+    if not os.path.exists(_lib.LIB_PATH):
+        pytest.skip("libpi.so not built")
+    L = _lib.load()
+    cfg = _lib.pi_group_config()
+    assert L.pi_group_config_default(ctypes.byref(cfg)) == _lib.PI_OK
+    assert cfg.struct_size == ctypes.sizeof(_lib.pi_group_config)
+    assert (cfg.max_indices, cfg.fused_max, cfg.host_threads, cfg.reserved) == (4096, 4096, 4, 0)
+    setattr(cfg, field, value)
+    h = ctypes.c_void_p(1)
+    assert L.pi_group_create(ctypes.byref(cfg), ctypes.byref(h)) == _lib.PI_ERR_INVALID_ARG
+    assert not h.value
 
 
 @pytest.mark.parametrize("field,value", [("compact_percent", 1001), ("lds_budget", 13001), ("descent_block", 300),

@@ -1,4 +1,6 @@
-"""Full-size parity of the write-heavy workload (Algorithm 4 with the
+"""Full-size parity.  Read scaling: 2^24 loaded keys, 2^22-query SEARCH
+batches, uniform and Zipf 0.99, against the sorted-array map oracle.  The
+write-heavy workload (Algorithm 4 with the
 threshold rebuild of Section 4.3.5 and the background index rebuild): 2^26
 loaded keys, eight batches of 2^22 queries, 40/50/10 SEARCH/INSERT/DELETE,
 SEARCH and DELETE keys Zipf 0.99 over the loaded keys, INSERT keys fresh.
@@ -84,3 +86,31 @@ def test_write_skew_full_size(policy):
         assert bad.size == 0, f"batch {i}: {bad.size} mismatches, first at {int(bad[0])}"
     assert np.array_equal(ek, ok) and np.array_equal(ev, ov)
     assert st["live_nodes"] == ok.size
+
+
+@pytest.mark.timeout(600)
+@pytest.mark.parametrize("theta", [0.0, 0.99])
+def test_read_scaling_full_size(theta):
+    """Read scaling at full size: 2^24 loaded keys, four batches of 2^22
+    SEARCH queries (uniform, then Zipf 0.99 over the loaded keys), every
+    answer against the sorted-array map oracle.  After the first batch the
+    ordering switches to the 16-bit position and the descent's per-wave sort;
+    the last batch repeats with the 24-bit ordering forced."""
+    from oracle import mapref
+    w = W.read_scaling(theta, load_log2=24, query_log2=22, n_batches=4)
+    ms = mapref.MapState(w.load_keys, w.load_vals)
+    dev = torch.device("cuda", 0)
+    for bits in (0, 24):
+        with Index(order_bits=bits) as ix:
+            ix.bulk_load(w.load_keys, w.load_vals)
+            for i, b in enumerate(w.batches if bits == 0 else w.batches[-1:]):
+                ov = torch.empty(b.keys.size, dtype=torch.int64, device=dev)
+                os_ = torch.empty(b.keys.size, dtype=torch.uint8, device=dev)
+                ix.execute_raw(to_device_u8(b.ops, dev), to_device_u64(b.keys, dev), to_device_u64(b.vals, dev),
+                               ov, os_)
+                torch.cuda.synchronize()
+                wv, ws = ms.search_batch(b.keys)
+                gs = os_.cpu().numpy()
+                assert np.array_equal(gs, ws), (theta, bits, i)
+                assert np.array_equal(to_numpy_u64(ov), wv), (theta, bits, i)
+                print(f"  theta {theta} bits {bits} batch {i}: {int((gs == 1).sum())} hits of {gs.size}", flush=True)

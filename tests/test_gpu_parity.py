@@ -597,22 +597,26 @@ def test_small_batches_in_one_workgroup(policy):
 
 # ------------------------------------------------------- many indices
 
-@pytest.mark.parametrize("fused_max", [4096, 0, 16384])
-def test_group_matches_each_index_alone(fused_max):
+@pytest.mark.parametrize("fused_max,threads,policy", [(4096, 0, "threshold"), (0, 0, "threshold"),
+                                                       (16384, 0, "threshold"), (0, 1, "threshold"),
+                                                       (0, 2, "always"), (0, 0, "background"), (0, 0, "slices")])
+def test_group_matches_each_index_alone(fused_max, threads, policy):
     """One batch on each of many indices per call (pi_group_execute): each
     index's answers and final set equal the serial replay of its own
     batches, whichever batches take the fused launch (fused_max 0: none;
-    16384: chunks of 4096 in one workgroup)."""
+    16384: chunks of 4096 in one workgroup), with the large batches and the
+    rebuilds the policies start issued by one to four host threads."""
     from paper_1601_00159_amd.index import Group
     from paper_1601_00159_amd.index import to_device_u64 as d64, to_device_u8 as d8
-    w = W.many_indices(n_indices=24, size_log2=(8, 15), batch_log2=(5, 14), n_rounds=3, seed_id=10 + fused_max % 7)
+    w = W.many_indices(n_indices=24, size_log2=(8, 15), batch_log2=(5, 14), n_rounds=4,
+                       seed_id=10 + fused_max % 7 + threads + len(policy))
     dev = torch.device("cuda", 0)
     refs = [mapref.MapState(k, v) for k, v in w.loads]
-    ixs = [Index(rebuild_policy="threshold", rebuild_fraction=0.05, rebuild_min=1) for _ in w.loads]
+    ixs = [Index(rebuild_policy=policy, rebuild_fraction=0.05, rebuild_min=1) for _ in w.loads]
     try:
         for ix, (k, v) in zip(ixs, w.loads):
             ix.bulk_load(k, v)
-        with Group(fused_max=fused_max if fused_max else 1) as g:
+        with Group(fused_max=fused_max if fused_max else 1, host_threads=threads) as g:
             for r, batches in enumerate(w.rounds):
                 dev_b = [(d8(b.ops, dev), d64(b.keys, dev), d64(b.vals, dev),
                           torch.empty(len(b), dtype=torch.int64, device=dev),
@@ -630,6 +634,11 @@ def test_group_matches_each_index_alone(fused_max):
         for i, ix in enumerate(ixs):
             ek, ev = export_np(ix)
             assert np.array_equal(ek, refs[i].keys) and np.array_equal(ev, refs[i].vals), i
+        st = [ix.stats() for ix in ixs]
+        print(f"  rebuilds {sum(x['repairs'] for x in st)}, slice rounds {sum(x['slice_rounds'] for x in st)}",
+              flush=True)
+        if policy in ("threshold", "always"):
+            assert sum(x["repairs"] for x in st) > 0
     finally:
         for ix in ixs:
             ix.close()
