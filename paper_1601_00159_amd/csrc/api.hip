@@ -11,6 +11,7 @@
 namespace pi {
 
 thread_local Arena *t_arena = nullptr;
+thread_local std::vector<void *> *t_defer = nullptr;
 
 void DevBuf::ensure(size_t need) {
     if (need <= bytes && p) return;
@@ -30,7 +31,10 @@ void DevBuf::ensure(size_t need) {
     // asked the first time and gets half as much again when it has to grow.
     const bool regrow = p != nullptr;
     if (p) {
-        PI_HIP(hipFree(p));
+        if (t_defer)
+            t_defer->push_back(p);
+        else
+            PI_HIP(hipFree(p));
         p = nullptr;
         bytes = 0;
     }
@@ -51,7 +55,10 @@ void DevBuf::ensure(size_t need) {
 }
 
 void DevBuf::release() {
-    if (p) (void)hipFree(p);
+    if (p && t_defer)
+        t_defer->push_back(p);
+    else if (p)
+        (void)hipFree(p);
     p = nullptr;
     bytes = 0;
 }
@@ -219,6 +226,7 @@ void push_state(pi::Index &ix, hipStream_t s) {
 }
 
 void ensure_capacity(pi::Index &ix, const uint8_t *ops, const uint64_t *keys, uint64_t n, hipStream_t s) {
+    ix.batch_peak = std::max(ix.batch_peak, n);
     if (ix.used_upper + n <= ix.st.cap) return;
     pi::DevState cur;
     pi::read_state(ix, s, &cur);  // refreshes used_upper
@@ -232,7 +240,7 @@ void ensure_capacity(pi::Index &ix, const uint8_t *ops, const uint64_t *keys, ui
     }
     // room for two batches of this size: batch sizes that vary do not force a
     // counter read (a wait for the stream) on every call
-    pi::grow_storage(ix, std::max<uint64_t>(cur.nused + 2 * n, ix.st.cap * 2), s);
+    pi::grow_storage(ix, cur.nused + n, std::max<uint64_t>(cur.nused + 2 * n, ix.st.cap * 2), s);
 }
 
 }  // namespace
@@ -331,7 +339,7 @@ pi_status pi_create(const pi_config *cfg_in, pi_index **out) {
         std::memset(ix.hstate, 0, sizeof(pi::DevState));
         std::memset(ix.hring, 0, pi::Index::STATE_RING * sizeof(pi::DevState));
         const uint64_t cap = std::max<uint64_t>(cfg.capacity_hint ? cfg.capacity_hint : (1u << 16), 4);
-        ix.st.alloc(cap);
+        ix.st.alloc(cap, cfg.capacity_hint != 0);
         pi::noalloc_init(ix.device);
         pi::init_empty(ix, nullptr);
         PI_HIP(hipDeviceSynchronize());
@@ -461,6 +469,7 @@ pi_status pi_execute_batch_noalloc(pi_index *h, const uint8_t *d_ops, const uint
         maybe_rebuild(ix, s, false);
         // room for the new nodes, never by growing the storage; the insert
         // count goes to the first word of the scratch
+        ix.batch_peak = std::max(ix.batch_peak, n);
         if (ix.used_upper + n > ix.st.cap) {
             pi::DevState cur;
             pi::read_state(ix, s, &cur);

@@ -285,21 +285,33 @@ void scatter_reserve(DevBuf &cnt, DevBuf &tot, uint64_t n) {
 }
 
 // STORAGE_SLACK slots past the capacity keep the speculative reads of the
-// storage walk (up to two slots past a node) inside the allocation.
-void Storage::alloc(uint64_t c) {
-    cap = c;
-    const uint64_t phys = c + STORAGE_SLACK;
-    key.ensure(phys * sizeof(uint64_t));
-    val.ensure(phys * sizeof(uint64_t));
-    next.ensure(phys * sizeof(uint32_t));
-    meta.ensure(phys * sizeof(uint8_t));
+// storage walk (up to two slots past a node) inside the allocation.  The
+// four arrays share one allocation (each array 256-byte aligned): a fourth
+// of the allocations and frees.  Unless exact, the capacity takes whatever
+// the allocation's rounding leaves room for.
+void Storage::alloc(uint64_t c, bool exact) {
+    constexpr uint64_t BYTES_PER_SLOT = 8 + 8 + 4 + 1, ALIGN_PAD = 4 * 256;
+    auto up = [](uint64_t b) { return (b + 255) & ~uint64_t(255); };
+    all.ensure((c + STORAGE_SLACK) * BYTES_PER_SLOT + ALIGN_PAD);
+    uint64_t phys = c + STORAGE_SLACK;
+    if (!exact) phys = std::max<uint64_t>(phys, (all.bytes - ALIGN_PAD) / BYTES_PER_SLOT);
+    cap = phys - STORAGE_SLACK;
+    const uint64_t o_val = up(phys * 8), o_next = o_val + up(phys * 8), o_meta = o_next + up(phys * 4);
+    auto view = [&](uint64_t off, uint64_t bytes) {
+        DevBuf v;
+        v.p = static_cast<uint8_t *>(all.p) + off;
+        v.bytes = bytes;
+        return v;
+    };
+    key = view(0, phys * 8);
+    val = view(o_val, phys * 8);
+    next = view(o_next, phys * 4);
+    meta = view(o_meta, phys);
 }
 
 void Storage::release() {
-    key.release();
-    val.release();
-    next.release();
-    meta.release();
+    all.release();
+    key = val = next = meta = DevBuf{};
     cap = 0;
 }
 
@@ -453,21 +465,34 @@ void init_empty(Index &ix, hipStream_t s) {
     build_levels(ix, s);
 }
 
-void grow_storage(Index &ix, uint64_t need, hipStream_t s) {
+void grow_storage(Index &ix, uint64_t need, uint64_t want, hipStream_t s) {
     if (need <= ix.st.cap) return;
     bg_quiesce(ix);
     DevState cur;
     read_state(ix, s, &cur);
-    uint64_t ncap = std::max<uint64_t>(need, ix.st.cap + ix.st.cap / 2);
+    // into the spare storage (the one the last rebuild replaced) when it is
+    // large enough, else into a new one; of the replaced storage and the
+    // spare, the larger stays as the spare (allocations and frees wait for
+    // the whole device)
     Storage ns;
-    ns.alloc(ncap);
+    if (ix.spare.cap >= need) {
+        ns = ix.spare;
+        ix.spare = Storage{};
+    } else {
+        ns.alloc(std::max<uint64_t>(std::max(need, want), ix.st.cap + ix.st.cap / 2), false);
+    }
     const uint64_t used = cur.nused;
     PI_HIP(hipMemcpyAsync(ns.key.p, ix.st.key.p, used * 8, hipMemcpyDeviceToDevice, s));
     PI_HIP(hipMemcpyAsync(ns.val.p, ix.st.val.p, used * 8, hipMemcpyDeviceToDevice, s));
     PI_HIP(hipMemcpyAsync(ns.next.p, ix.st.next.p, used * 4, hipMemcpyDeviceToDevice, s));
     PI_HIP(hipMemcpyAsync(ns.meta.p, ix.st.meta.p, used, hipMemcpyDeviceToDevice, s));
     PI_HIP(hipStreamSynchronize(s));
-    ix.st.release();
+    if (ix.spare.cap < ix.st.cap) {
+        ix.spare.release();
+        ix.spare = ix.st;
+    } else {
+        ix.st.release();
+    }
     ix.st = ns;
     bg_reserve(ix);
 }
@@ -501,7 +526,7 @@ void bulk_load(Index &ix, const uint64_t *keys, const uint64_t *vals, uint64_t n
         const uint64_t want = ix.cfg.capacity_hint ? ix.cfg.capacity_hint : nb + 2 + storage_room(ix, nb);
         if (want > ix.st.cap) {
             Storage ns;
-            ns.alloc(want);
+            ns.alloc(want, ix.cfg.capacity_hint != 0);
             ix.st.release();
             ix.st = ns;
         }
@@ -613,7 +638,10 @@ void rebuild(Index &ix, hipStream_t s) {
     DevState cur;
     read_state(ix, s, &cur);
     const uint64_t live = cur.n_live;
-    const uint64_t need = ix.cfg.capacity_hint ? ix.cfg.capacity_hint : live + 2 + storage_room(ix, live);
+    // room for the largest batch the index has taken as well: a rebuilt
+    // storage that the next such batch does not fit would grow again at once
+    const uint64_t need = ix.cfg.capacity_hint ? ix.cfg.capacity_hint
+                                               : live + 2 + std::max(storage_room(ix, live), ix.batch_peak);
     // the new base region goes to the spare storage (the one replaced by the
     // previous rebuild) when it is large enough; the current one becomes the
     // spare.  A spare that is too small is replaced by one of twice the need
@@ -624,7 +652,7 @@ void rebuild(Index &ix, hipStream_t s) {
     ix.spare = Storage{};
     if (ns.cap < need || (ix.cfg.capacity_hint && ns.cap != need)) {
         ns.release();
-        ns.alloc(ix.cfg.capacity_hint ? need : std::max<uint64_t>(2 * need, ix.st.cap));
+        ns.alloc(ix.cfg.capacity_hint ? need : std::max<uint64_t>(2 * need, ix.st.cap), ix.cfg.capacity_hint != 0);
     }
     bool small = false;
     try {

@@ -88,6 +88,21 @@ struct pi_group {
     static constexpr int LANES = 4;                     // streams the large batches are spread over
     hipStream_t lane[LANES] = {};
     hipEvent_t ev_fork = nullptr, ev_lane[LANES] = {};
+    // the workspaces of the large batches and of the rebuilds, one set per
+    // lane (the lane's stream orders their uses): they grow to the largest
+    // batch and index the group has run once, where each index's own would
+    // grow with that index (every growth frees a buffer, and a free waits
+    // for the whole device)
+    struct LaneBuffers {
+        pi::SortWorkspace sort;
+        pi::MsdWorkspace msd;
+        pi::ScanWorkspace scan;
+        pi::BatchWorkspace bws;
+        pi::DevBuf tmp[10];
+    } lbuf[LANES];
+    // device buffers released during a call (by the calling thread and by
+    // each worker), freed at the next call once this one has completed
+    std::vector<void *> graveyard[LANES];
     bool pending = false;
     bool lds_attr = false;
     uint32_t tuned_block = 0, tuned_lds = 0;  // descent shape the autotuner applied (0 = none)
@@ -126,7 +141,7 @@ void ensure_lanes(pi_group *g) {
     PI_HIP(hipEventCreateWithFlags(&g->ev_fork, hipEventDisableTiming));
 }
 
-// Runs fn(j, stream) for every job j < njobs, the jobs touching disjoint
+// Runs fn(j, lane) for every job j < njobs, the jobs touching disjoint
 // indices, on the group's lane streams (ordered after the work already on s,
 // joined back into s).  Up to host_threads host threads take the jobs from a
 // shared counter, each issuing on a lane stream of its own: a round over many
@@ -148,12 +163,13 @@ void on_lanes(pi_group *g, hipStream_t s, uint32_t njobs, F &&fn) {
     std::atomic<bool> failed{false};
     std::exception_ptr err[pi_group::LANES];
     auto work = [&](int t) {
+        DeferFrees defer(&g->graveyard[t]);
         try {
             if (t) PI_HIP(hipSetDevice(dev));
             uint32_t j;
             // one thread (host_threads 1) cycles the lanes as the jobs come
             for (uint32_t m = 0; !failed.load() && (j = next.fetch_add(1)) < njobs; m++)
-                fn(j, g->lane[threads == 1 ? (int)(m % lanes) : t]);
+                fn(j, threads == 1 ? (int)(m % lanes) : t);
         } catch (...) {
             err[t] = std::current_exception();
             failed.store(true);
@@ -171,6 +187,20 @@ void on_lanes(pi_group *g, hipStream_t s, uint32_t njobs, F &&fn) {
     for (int t = 0; t < threads; t++)
         if (err[t]) std::rethrow_exception(err[t]);
 }
+
+// Lends a lane's workspaces to an index for the span of its rebuild.
+struct LentScratch {
+    Index &ix;
+    pi_group::LaneBuffers &lb;
+    LentScratch(Index &i, pi_group::LaneBuffers &l) : ix(i), lb(l) { swap(); }
+    ~LentScratch() { swap(); }
+    void swap() {
+        std::swap(ix.sortws, lb.sort);
+        std::swap(ix.msdws, lb.msd);
+        std::swap(ix.scanws, lb.scan);
+        for (int k = 0; k < 10; k++) std::swap(ix.tmp[k], lb.tmp[k]);
+    }
+};
 
 // The index's rebuild policy after a batch whose counters are st.
 void apply_policy(Index &ix, const DevState &st, hipStream_t s) {
@@ -201,10 +231,27 @@ void apply_policy(Index &ix, const DevState &st, hipStream_t s) {
     }
 }
 
+// Frees the buffers released during earlier calls, after every stream of
+// the group has finished what may still read them (the wait costs nothing
+// once the previous call has completed).
+void free_deferred(pi_group *g) {
+    bool any = false;
+    for (const auto &l : g->graveyard) any |= !l.empty();
+    if (!any) return;
+    if (g->fstream) PI_HIP(hipStreamSynchronize(g->fstream));
+    for (hipStream_t l : g->lane)
+        if (l) PI_HIP(hipStreamSynchronize(l));
+    for (auto &l : g->graveyard) {
+        for (void *p : l) PI_HIP(hipFree(p));
+        l.clear();
+    }
+}
+
 void settle_previous(pi_group *g, hipStream_t s) {
     if (!g->pending) return;
     PI_HIP(hipEventSynchronize(g->ev));
     g->pending = false;
+    free_deferred(g);
     std::vector<uint32_t> act;  // indices whose policy may act
     for (size_t k = 0; k < g->last.size(); k++) {
         Index &ix = g->last[k]->ix;
@@ -221,7 +268,11 @@ void settle_previous(pi_group *g, hipStream_t s) {
         if (ix.cfg.rebuild_policy != PI_REBUILD_NEVER) act.push_back((uint32_t)k);
     }
     on_lanes(g, s, (uint32_t)act.size(),
-             [&](uint32_t j, hipStream_t ls) { apply_policy(g->last[act[j]]->ix, g->h_states[act[j]], ls); });
+             [&](uint32_t j, int k) {
+                 Index &ix = g->last[act[j]]->ix;
+                 LentScratch lent(ix, g->lbuf[k]);
+                 apply_policy(ix, g->h_states[act[j]], g->lane[k]);
+             });
     g->last.clear();
     g->last_enq.clear();
 }
@@ -229,6 +280,7 @@ void settle_previous(pi_group *g, hipStream_t s) {
 // Room for the batch's new nodes (the host bound first, the device count
 // when the bound does not fit).
 void group_capacity(Index &ix, const pi_batch &b, hipStream_t s) {
+    ix.batch_peak = std::max(ix.batch_peak, b.n);
     if (ix.used_upper + b.n <= ix.st.cap) return;
     DevState cur;
     read_state(ix, s, &cur);
@@ -238,12 +290,31 @@ void group_capacity(Index &ix, const pi_batch &b, hipStream_t s) {
         if (cur.nused + ins > ix.st.cap) throw GroupError{PI_ERR_CAPACITY, "an index of the group has no room"};
         return;
     }
-    grow_storage(ix, std::max<uint64_t>(cur.nused + 2 * b.n, ix.st.cap * 2), s);
+    grow_storage(ix, cur.nused + b.n, std::max<uint64_t>(cur.nused + 2 * b.n, ix.st.cap * 2), s);
 }
+
+void run_group_body(pi_group *g, pi_index *const *indices, const pi_batch *batches, uint32_t count, hipStream_t s,
+                    uint64_t fused_max, const uint8_t *ops_override);
 
 void run_group(pi_group *g, pi_index *const *indices, const pi_batch *batches, uint32_t count, hipStream_t s,
                uint64_t fused_max, const uint8_t *ops_override) {
     TraceRange tr("pi:group");
+    DeferFrees defer(&g->graveyard[0]);
+    try {
+        run_group_body(g, indices, batches, count, s, fused_max, ops_override);
+    } catch (...) {
+        // what this call enqueued may still read the released buffers
+        (void)hipDeviceSynchronize();
+        for (auto &l : g->graveyard) {
+            for (void *p : l) (void)hipFree(p);
+            l.clear();
+        }
+        throw;
+    }
+}
+
+void run_group_body(pi_group *g, pi_index *const *indices, const pi_batch *batches, uint32_t count, hipStream_t s,
+                    uint64_t fused_max, const uint8_t *ops_override) {
     for (uint32_t i = 0; i < count; i++) indices[i]->ix.epoch++;
     settle_previous(g, s);
     for (uint32_t i = 0; i < count; i++)
@@ -302,13 +373,15 @@ void run_group(pi_group *g, pi_index *const *indices, const pi_batch *batches, u
     std::vector<uint32_t> large;
     for (uint32_t i = 0; i < count; i++)
         if (batches[i].n > fused_max) large.push_back(i);
-    on_lanes(g, s, (uint32_t)large.size(), [&](uint32_t j, hipStream_t ls) {
+    on_lanes(g, s, (uint32_t)large.size(), [&](uint32_t j, int k) {
         const uint32_t i = large[j];
         const pi_batch &b = batches[i];
+        pi_group::LaneBuffers &lb = g->lbuf[k];
         // one launch for the steps after the descent: the group call is
         // bound by the host's launches, not by these batches' device time
-        execute_batch(indices[i]->ix, ops_override ? ops_override : b.d_ops, b.d_keys, b.d_values, b.n,
-                      b.d_out_values, b.d_out_status, ls, true);
+        execute_batch(indices[i]->ix, BatchBuffers{lb.sort, lb.msd, lb.scan, lb.bws},
+                      ops_override ? ops_override : b.d_ops, b.d_keys, b.d_values, b.n, b.d_out_values,
+                      b.d_out_status, g->lane[k], true);
     });
     if (!fused.empty()) PI_HIP(hipStreamWaitEvent(s, g->ev_fused, 0));
     // one copy of every index's counters
@@ -444,7 +517,15 @@ pi_status pi_group_destroy(pi_group *g) {
             (void)hipStreamDestroy(g->lane[k]);
         }
         if (g->ev_lane[k]) (void)hipEventDestroy(g->ev_lane[k]);
+        pi_group::LaneBuffers &lb = g->lbuf[k];
+        lb.sort.release();
+        lb.msd.release();
+        lb.scan.release();
+        lb.bws.release();
+        for (pi::DevBuf &b : lb.tmp) b.release();
     }
+    for (auto &l : g->graveyard)
+        for (void *p : l) (void)hipFree(p);
     if (g->ev_fork) (void)hipEventDestroy(g->ev_fork);
     delete g;
     return PI_OK;

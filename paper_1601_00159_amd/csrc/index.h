@@ -19,8 +19,10 @@ namespace pi {
 //                     key-sorted run per batch, successor always in snext
 struct Storage {
     uint64_t cap = 0;
-    DevBuf key, val, next, meta;
-    void alloc(uint64_t cap);
+    DevBuf all;                   // the one allocation
+    DevBuf key, val, next, meta;  // views into it (never grown or freed on their own)
+    // capacity of at least cap slots (exactly cap when exact)
+    void alloc(uint64_t cap, bool exact);
     void release();
 };
 
@@ -72,6 +74,7 @@ struct Index {
     Storage spare;                 // the previous storage, reused by the next rebuild
     uint64_t nbase = 0;        // base-region nodes
     uint64_t used_upper = 2;   // host upper bound of DevState::nused
+    uint64_t batch_peak = 0;   // largest batch taken (queries), for the room a rebuild leaves
     // Queries enqueued on this index so far, by any path (single batches,
     // group calls, serving).  Every counter copy records the value at the
     // time it was enqueued, so nused in the copy plus the queries enqueued
@@ -207,7 +210,9 @@ void bulk_load(Index &ix, const uint64_t *keys, const uint64_t *vals, uint64_t n
 void rebuild(Index &ix, hipStream_t s);  // merge + drop deleted + rebuild levels
 uint64_t export_live(Index &ix, uint64_t *okeys, uint64_t *ovals, uint64_t cap, hipStream_t s);
 void read_state(Index &ix, hipStream_t s, DevState *out);  // synchronises s
-void grow_storage(Index &ix, uint64_t need_slots, hipStream_t s);
+// Storage of at least need slots (the slots in use plus a batch), sized want
+// when it has to be allocated; synchronises s.
+void grow_storage(Index &ix, uint64_t need, uint64_t want, hipStream_t s);
 
 // batch.hip
 // The per-batch buffers of the multi-kernel path (the index's own, or ones

@@ -6,6 +6,7 @@
 #include <stdint.h>
 
 #include <string>
+#include <vector>
 
 #include "pi.h"
 
@@ -261,6 +262,17 @@ struct ArenaScope {
     Arena *prev;
     explicit ArenaScope(Arena *a) : prev(t_arena) { t_arena = a; }
     ~ArenaScope() { t_arena = prev; }
+};
+
+// While a DeferFrees is active on the calling thread, the device buffers
+// that DevBufs release (a regrow, a release) go to its list instead of
+// hipFree, which waits for the whole device: its owner frees them once the
+// work that may still read them has completed.
+extern thread_local std::vector<void *> *t_defer;
+struct DeferFrees {
+    std::vector<void *> *prev;
+    explicit DeferFrees(std::vector<void *> *l) : prev(t_defer) { t_defer = l; }
+    ~DeferFrees() { t_defer = prev; }
 };
 
 // A device buffer that only grows.
