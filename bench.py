@@ -550,7 +550,7 @@ def run_many(args):
                             torch.empty(len(b), dtype=torch.uint8, device=dev)) for b in batches])
     q_per_round = [sum(len(b) for b in batches) for batches in w.rounds]
     for mode in args.many_modes.split(","):
-        ixs = [Index(device=0, rebuild_policy=args.many_policy) for _ in w.loads]
+        ixs = [Index(device=0, rebuild_policy=args.many_policy, post_form=args.many_post_form) for _ in w.loads]
         for ix, (k, v) in zip(ixs, w.loads):
             ix.bulk_load(k, v)
         torch.cuda.synchronize()
@@ -558,7 +558,12 @@ def run_many(args):
         g = Group(host_threads=threads) if mode.startswith("group") else None
         fused = None
         shape = None
-        if g is not None:
+        if g is not None and args.many_fused_max:
+            g.close()
+            g = Group(fused_max=args.many_fused_max, host_threads=threads)
+            fused = args.many_fused_max
+            log(f"fused_max fixed at {fused} (no autotuning)")
+        elif g is not None:
             fused = g.autotune(ixs, dev_rounds[-1])
             _, tb, tl = g.tuning()
             shape = {"block": tb, "lds_budget": tl}
@@ -633,6 +638,10 @@ def main():
     ap.add_argument("--indices", type=int, default=512, help="indices (--workload many)")
     ap.add_argument("--many-modes", default="per-index,group",
                     help="comma list of per-index, group (4 host threads), group-1-thread (--workload many)")
+    ap.add_argument("--many-post-form", type=int, default=0, choices=[0, 1, 2],
+                    help="post-descent form of the indices: 0 chosen, 1 one launch, 2 separate (--workload many)")
+    ap.add_argument("--many-fused-max", type=int, default=0,
+                    help="fused threshold of the group launch (0 = autotuned) (--workload many)")
     ap.add_argument("--many-policy", default="threshold", choices=["threshold", "never", "slices"],
                     help="rebuild policy of the indices (--workload many)")
     ap.add_argument("--rebuild-policy", default="background", choices=["threshold", "background", "never"],

@@ -433,7 +433,7 @@ void serve_step(pi::Index &ix, const uint8_t *d_ops, const uint64_t *d_keys, con
     pi::order_batch(buf, d_ops, d_keys, n, p.side, &sk, &sidx, bits);
     PI_HIP(hipEventRecord(set.ordered, p.side));
     PI_HIP(hipStreamWaitEvent(s, set.ordered, 0));
-    pi::finish_batch(ix, buf, sk, sidx, d_ops, d_values, n, d_out_values, d_out_status, s, nullptr, false, bits);
+    pi::finish_batch(ix, buf, sk, sidx, d_ops, d_values, n, d_out_values, d_out_status, s, nullptr, bits);
     PI_HIP(hipEventRecord(set.done, s));
     set.used = true;
     ix.used_upper = std::min<uint64_t>(ix.used_upper + n, ~0ull);

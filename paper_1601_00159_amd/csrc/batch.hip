@@ -952,14 +952,13 @@ uint64_t count_inserts(Index &ix, const uint8_t *ops, const uint64_t *keys, uint
 }
 
 void execute_batch(Index &ix, const uint8_t *ops, const uint64_t *keys, const uint64_t *vals, uint64_t n,
-                   uint64_t *out_vals, uint8_t *out_status, hipStream_t s, bool one_launch) {
+                   uint64_t *out_vals, uint8_t *out_status, hipStream_t s) {
     execute_batch(ix, BatchBuffers{ix.sortws, ix.msdws, ix.scanws, ix.bws}, ops, keys, vals, n, out_vals,
-                  out_status, s, one_launch);
+                  out_status, s);
 }
 
 void execute_batch(Index &ix, const BatchBuffers &buf, const uint8_t *ops, const uint64_t *keys,
-                   const uint64_t *vals, uint64_t n, uint64_t *out_vals, uint8_t *out_status, hipStream_t s,
-                   bool one_launch) {
+                   const uint64_t *vals, uint64_t n, uint64_t *out_vals, uint8_t *out_status, hipStream_t s) {
     TraceRange tr("pi:batch");
     Profiler::Rec rec{};
     auto mark = [&](int k) {
@@ -973,8 +972,7 @@ void execute_batch(Index &ix, const BatchBuffers &buf, const uint8_t *ops, const
     const uint32_t bits = order_bits(ix);
     order_batch(buf, ops, keys, n, s, &sk, &sidx, bits);
     mark(1);
-    finish_batch(ix, buf, sk, sidx, ops, vals, n, out_vals, out_status, s, ix.prof.on ? &rec : nullptr, one_launch,
-                 bits);
+    finish_batch(ix, buf, sk, sidx, ops, vals, n, out_vals, out_status, s, ix.prof.on ? &rec : nullptr, bits);
 }
 
 uint32_t order_bits(const Index &ix) {
@@ -992,7 +990,7 @@ void order_batch(const BatchBuffers &buf, const uint8_t *ops, const uint64_t *ke
 
 void finish_batch(Index &ix, const BatchBuffers &buf, const uint64_t *sk, const uint32_t *sidx, const uint8_t *ops,
                   const uint64_t *vals, uint64_t n, uint64_t *out_vals, uint8_t *out_status, hipStream_t s,
-                  Profiler::Rec *prec, bool one_launch, uint32_t pos_bits) {
+                  Profiler::Rec *prec, uint32_t pos_bits) {
     TraceRange tr("pi:descend+update");
     buf.bws.ensure(n);
     DevState *st = ix.dstate;
@@ -1031,7 +1029,7 @@ void finish_batch(Index &ix, const BatchBuffers &buf, const uint64_t *sk, const 
     PI_HIP(hipStreamIsCapturing(s, &cap_status));
     const uint32_t form = ix.cfg.post_form;
     const bool fused = cap_status == hipStreamCaptureStatusNone &&
-                       (form == 1 || (form == 0 && (one_launch || !ix.recent_writers)));
+                       (form == 1 || (form == 0 && !ix.recent_writers));
     if (fused) {
         static const int occ = [] {  // once per process, thread-safe
             int o = 0;

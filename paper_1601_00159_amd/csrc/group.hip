@@ -21,6 +21,7 @@
 #include <cstring>
 #include <string>
 #include <thread>
+#include <unordered_map>
 #include <unordered_set>
 #include <vector>
 
@@ -55,6 +56,7 @@ __global__ __launch_bounds__(SBT) void k_group_batches(const GroupItem *__restri
             b.out_status += c;
             b.n = n - c < SB_MAX ? n - c : SB_MAX;
             b.unit = g.b.unit + c / SB_MAX;  // each chunk is a batch of its own for the writer check
+            b.first = c == 0;
             block_batch(g.v, b, s_raw);
         }
     }
@@ -88,6 +90,7 @@ struct pi_group {
     static constexpr int LANES = 4;                     // streams the large batches are spread over
     hipStream_t lane[LANES] = {};
     hipEvent_t ev_fork = nullptr, ev_lane[LANES] = {};
+    hipEvent_t ev_in = nullptr;  // the caller's stream at the start of a call
     // the workspaces of the large batches and of the rebuilds, one set per
     // lane (the lane's stream orders their uses): they grow to the largest
     // batch and index the group has run once, where each index's own would
@@ -138,6 +141,7 @@ void ensure_lanes(pi_group *g) {
         if (!g->lane[k]) PI_HIP(hipStreamCreateWithFlags(&g->lane[k], hipStreamNonBlocking));
         if (!g->ev_lane[k]) PI_HIP(hipEventCreateWithFlags(&g->ev_lane[k], hipEventDisableTiming));
     }
+    if (!g->ev_in) PI_HIP(hipEventCreateWithFlags(&g->ev_in, hipEventDisableTiming));
     PI_HIP(hipEventCreateWithFlags(&g->ev_fork, hipEventDisableTiming));
 }
 
@@ -149,14 +153,18 @@ void ensure_lanes(pi_group *g) {
 // rebuild ~30 plus a wait for its index's counters), not by the device.  The
 // first error a job raises stops the taking of new jobs and is rethrown once
 // every thread has finished and the lanes are joined.
+// after: what the lanes wait for (null: everything on s so far).
 template <class F>
-void on_lanes(pi_group *g, hipStream_t s, uint32_t njobs, F &&fn) {
+void on_lanes(pi_group *g, hipStream_t s, uint32_t njobs, F &&fn, hipEvent_t after = nullptr) {
     if (!njobs) return;
     ensure_lanes(g);
     const int lanes = (int)std::min<uint32_t>(njobs, pi_group::LANES);
     const int threads = std::min<int>(lanes, (int)g->cfg.host_threads);
-    PI_HIP(hipEventRecord(g->ev_fork, s));
-    for (int k = 0; k < lanes; k++) PI_HIP(hipStreamWaitEvent(g->lane[k], g->ev_fork, 0));
+    if (!after) {
+        PI_HIP(hipEventRecord(g->ev_fork, s));
+        after = g->ev_fork;
+    }
+    for (int k = 0; k < lanes; k++) PI_HIP(hipStreamWaitEvent(g->lane[k], after, 0));
     int dev = 0;
     PI_HIP(hipGetDevice(&dev));
     std::atomic<uint32_t> next{0};
@@ -247,12 +255,21 @@ void free_deferred(pi_group *g) {
     }
 }
 
-void settle_previous(pi_group *g, hipStream_t s) {
-    if (!g->pending) return;
+// An index whose rebuild policy may act, and the counters it acts on.
+struct Due {
+    pi_index *h;
+    DevState st;
+};
+
+// Waits for the previous call and takes up its counters: an index whose
+// counters carry a device error fails; the host bounds are refreshed.
+// Returns the indices whose rebuild policy may act on those counters.
+std::vector<Due> settle_previous(pi_group *g) {
+    std::vector<Due> due;
+    if (!g->pending) return due;
     PI_HIP(hipEventSynchronize(g->ev));
     g->pending = false;
     free_deferred(g);
-    std::vector<uint32_t> act;  // indices whose policy may act
     for (size_t k = 0; k < g->last.size(); k++) {
         Index &ix = g->last[k]->ix;
         const DevState &st = g->h_states[k];
@@ -265,16 +282,11 @@ void settle_previous(pi_group *g, hipStream_t s) {
         // copy (group or single calls) bounds the storage in use now
         ix.used_upper = std::min<uint64_t>(ix.used_upper, st.nused + (ix.enq_queries - g->last_enq[k]));
         ix.recent_writers = st.b_writers != 0;  // the form of the next large batch's post-descent steps
-        if (ix.cfg.rebuild_policy != PI_REBUILD_NEVER) act.push_back((uint32_t)k);
+        if (ix.cfg.rebuild_policy != PI_REBUILD_NEVER) due.push_back(Due{g->last[k], st});
     }
-    on_lanes(g, s, (uint32_t)act.size(),
-             [&](uint32_t j, int k) {
-                 Index &ix = g->last[act[j]]->ix;
-                 LentScratch lent(ix, g->lbuf[k]);
-                 apply_policy(ix, g->h_states[act[j]], g->lane[k]);
-             });
     g->last.clear();
     g->last_enq.clear();
+    return due;
 }
 
 // Room for the batch's new nodes (the host bound first, the device count
@@ -316,14 +328,48 @@ void run_group(pi_group *g, pi_index *const *indices, const pi_batch *batches, u
 void run_group_body(pi_group *g, pi_index *const *indices, const pi_batch *batches, uint32_t count, hipStream_t s,
                     uint64_t fused_max, const uint8_t *ops_override) {
     for (uint32_t i = 0; i < count; i++) indices[i]->ix.epoch++;
-    settle_previous(g, s);
+    const std::vector<Due> due = settle_previous(g);
+    ensure_lanes(g);
+    PI_HIP(hipEventRecord(g->ev_in, s));
+    // A policy acts before its index's batch.  Before the fused launch: the
+    // indices whose batch it runs, and those of fixed capacity (all such
+    // rooms are checked before any batch of the call is enqueued).  The
+    // others act on their lane right before their large batch, or, with no
+    // batch in this call, beside the rest: neither waits for the fused launch
+    // nor holds it up.
+    std::unordered_map<const pi_index *, uint32_t> slot;
+    slot.reserve(2 * (size_t)count);
+    for (uint32_t i = 0; i < count; i++) slot.emplace(indices[i], i);
+    auto early = [&](uint32_t i) {
+        return batches[i].n && (batches[i].n <= fused_max || indices[i]->ix.cfg.capacity_hint);
+    };
+    struct Job {
+        int32_t batch, due;  // -1: none
+    };
+    std::vector<uint32_t> first;
+    std::vector<int32_t> due_of(count, -1);
+    std::vector<Job> jobs;
+    for (uint32_t j = 0; j < due.size(); j++) {
+        const auto it = slot.find(due[j].h);
+        if (it == slot.end() || !batches[it->second].n)
+            jobs.push_back(Job{-1, (int32_t)j});
+        else if (early(it->second))
+            first.push_back(j);
+        else
+            due_of[it->second] = (int32_t)j;
+    }
+    on_lanes(g, s, (uint32_t)first.size(), [&](uint32_t j, int k) {
+        const Due &d = due[first[j]];
+        LentScratch lent(d.h->ix, g->lbuf[k]);
+        apply_policy(d.h->ix, d.st, g->lane[k]);
+    });
     for (uint32_t i = 0; i < count; i++)
-        if (batches[i].n) group_capacity(indices[i]->ix, batches[i], s);
+        if (early(i)) group_capacity(indices[i]->ix, batches[i], s);
     ensure_host(g, count);
     std::vector<uint32_t> fused;
     for (uint32_t i = 0; i < count; i++) {
         const pi_batch &b = batches[i];
-        if (!b.n) continue;
+        if (!early(i)) continue;
         if (b.n <= fused_max) fused.push_back(i);
         indices[i]->ix.used_upper = std::min<uint64_t>(indices[i]->ix.used_upper + b.n, ~0ull);
         indices[i]->ix.enq_queries += b.n;
@@ -348,7 +394,7 @@ void run_group_body(pi_group *g, pi_index *const *indices, const pi_batch *batch
             it.v = index_view(fx);
             it.v.owner = wc.owner;
             it.b = BatchView{ops_override ? ops_override : b.d_ops, b.d_keys, b.d_values, (uint32_t)b.n,
-                             b.d_out_values, b.d_out_status, wc.unit};
+                             b.d_out_values, b.d_out_status, wc.unit, 1};
         }
         g->d_items.ensure((size_t)g->cap_items * sizeof(GroupItem));
         g->d_counter.ensure(64);
@@ -369,20 +415,38 @@ void run_group_body(pi_group *g, pi_index *const *indices, const pi_batch *batch
     }
     // large batches: the GPU-wide path on the group's lane streams (the
     // indices are disjoint, and one batch of a few hundred thousand queries
-    // does not fill the GPU), joined back into the caller's stream
-    std::vector<uint32_t> large;
+    // does not fill the GPU), each after its index's policy, beside the fused
+    // launch; joined back into the caller's stream
     for (uint32_t i = 0; i < count; i++)
-        if (batches[i].n > fused_max) large.push_back(i);
-    on_lanes(g, s, (uint32_t)large.size(), [&](uint32_t j, int k) {
-        const uint32_t i = large[j];
-        const pi_batch &b = batches[i];
-        pi_group::LaneBuffers &lb = g->lbuf[k];
-        // one launch for the steps after the descent: the group call is
-        // bound by the host's launches, not by these batches' device time
-        execute_batch(indices[i]->ix, BatchBuffers{lb.sort, lb.msd, lb.scan, lb.bws},
-                      ops_override ? ops_override : b.d_ops, b.d_keys, b.d_values, b.n, b.d_out_values,
-                      b.d_out_status, g->lane[k], true);
+        if (batches[i].n > fused_max) jobs.push_back(Job{(int32_t)i, due_of[i]});
+    // the largest batches first; the policies of indices without a batch last
+    std::sort(jobs.begin(), jobs.end(), [&](const Job &a, const Job &b) {
+        const uint64_t na = a.batch < 0 ? 0 : batches[a.batch].n, nb = b.batch < 0 ? 0 : batches[b.batch].n;
+        return na > nb;
     });
+    on_lanes(
+        g, s, (uint32_t)jobs.size(),
+        [&](uint32_t j, int k) {
+            const Job &jb = jobs[j];
+            hipStream_t ls = g->lane[k];
+            pi_group::LaneBuffers &lb = g->lbuf[k];
+            if (jb.due >= 0) {
+                const Due &d = due[jb.due];
+                LentScratch lent(d.h->ix, lb);
+                apply_policy(d.h->ix, d.st, ls);
+            }
+            if (jb.batch < 0) return;
+            const pi_batch &b = batches[jb.batch];
+            Index &ix = indices[jb.batch]->ix;
+            if (!ix.cfg.capacity_hint) {  // (a fixed capacity was checked before the fused launch)
+                group_capacity(ix, b, ls);
+                ix.used_upper = std::min<uint64_t>(ix.used_upper + b.n, ~0ull);
+                ix.enq_queries += b.n;
+            }
+            execute_batch(ix, BatchBuffers{lb.sort, lb.msd, lb.scan, lb.bws}, ops_override ? ops_override : b.d_ops,
+                          b.d_keys, b.d_values, b.n, b.d_out_values, b.d_out_status, ls);
+        },
+        g->ev_in);
     if (!fused.empty()) PI_HIP(hipStreamWaitEvent(s, g->ev_fused, 0));
     // one copy of every index's counters
     uint32_t ns = 0;
@@ -527,6 +591,7 @@ pi_status pi_group_destroy(pi_group *g) {
     for (auto &l : g->graveyard)
         for (void *p : l) (void)hipFree(p);
     if (g->ev_fork) (void)hipEventDestroy(g->ev_fork);
+    if (g->ev_in) (void)hipEventDestroy(g->ev_in);
     delete g;
     return PI_OK;
 }
@@ -563,7 +628,7 @@ pi_status pi_group_autotune(pi_group *g, pi_index *const *indices, const pi_batc
         // all-SEARCH replays: a zero op array as long as the longest batch
         g->d_zero_ops.ensure(std::max<uint64_t>(nmax, 1));
         PI_HIP(hipMemsetAsync(g->d_zero_ops.p, 0, std::max<uint64_t>(nmax, 1), s));
-        const uint64_t candidates[] = {0, 1024, 4096, 16384, 65536, 262144, 1048576};
+        const uint64_t candidates[] = {0, 1024, 4096, 16384, 32768, 65536, 131072, 262144, 524288, 1048576};
         double best = 1e30;
         uint64_t pick = g->cfg.fused_max;
         uint64_t prev = 0;

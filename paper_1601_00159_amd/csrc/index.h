@@ -223,14 +223,10 @@ struct BatchBuffers {
     ScanWorkspace &scan;
     BatchWorkspace &bws;
 };
-// one_launch: the steps after the descent as one launch whatever the index's
-// recent batches were (for callers bound by launches, such as the group
-// call's large batches); otherwise as pi_config::post_form says.
 void execute_batch(Index &ix, const uint8_t *ops, const uint64_t *keys, const uint64_t *vals, uint64_t n,
-                   uint64_t *out_vals, uint8_t *out_status, hipStream_t s, bool one_launch = false);
+                   uint64_t *out_vals, uint8_t *out_status, hipStream_t s);
 void execute_batch(Index &ix, const BatchBuffers &buf, const uint8_t *ops, const uint64_t *keys,
-                   const uint64_t *vals, uint64_t n, uint64_t *out_vals, uint8_t *out_status, hipStream_t s,
-                   bool one_launch = false);
+                   const uint64_t *vals, uint64_t n, uint64_t *out_vals, uint8_t *out_status, hipStream_t s);
 // The two halves of execute_batch.  The ordering reads only the batch and
 // writes only buf.sort / buf.msd, so it may run on another stream beside the
 // steps of an earlier batch; finish_batch (the descent and everything after
@@ -241,7 +237,7 @@ void order_batch(const BatchBuffers &buf, const uint8_t *ops, const uint64_t *ke
                  const uint64_t **sk, const uint32_t **sidx, uint32_t pos_bits);
 void finish_batch(Index &ix, const BatchBuffers &buf, const uint64_t *sk, const uint32_t *sidx, const uint8_t *ops,
                   const uint64_t *vals, uint64_t n, uint64_t *out_vals, uint8_t *out_status, hipStream_t s,
-                  Profiler::Rec *prec, bool one_launch, uint32_t pos_bits);
+                  Profiler::Rec *prec, uint32_t pos_bits);
 // Width of a batch's range position: pi_config::order_bits, or 16 after a
 // batch without INSERT/DELETE (such a batch is ordered only for locality) and
 // 24 after one with them (a full order costs the fix-up less).

@@ -35,6 +35,7 @@ struct BatchView {
     uint64_t *out_vals;
     uint8_t *out_status;
     uint32_t unit;  // writer-check unit of the first workgroup chunk
+    uint32_t first; // 1: the first chunk of its batch (counts the batch, restarts its writer flag)
 };
 
 // Index entries of the upper levels a workgroup stages in LDS next to its
@@ -226,6 +227,7 @@ __device__ __forceinline__ void block_batch(const IndexView &v, const BatchView 
         op[e] = (mine && q[e] != KEY_MAX) ? b.ops[s_idx[i]] : (uint8_t)255;
         el[e].f = (mine && (i == 0 || s_key[i - 1] != q[e])) ? 1u : 0u;
         const bool w = op[e] == PI_OP_INSERT || op[e] == PI_OP_DELETE;
+        if (w) s_cnt[4] = 1;  // the batch has writers (same value from every writer)
         el[e].v = w ? (int32_t)i : -1;
         run = sseg_op(run, el[e]);
     }
@@ -344,7 +346,12 @@ __device__ __forceinline__ void block_batch(const IndexView &v, const BatchView 
         st->changes += nnew + d;
         if (nnew) st->has_links = 1;
         if (d) st->has_dead = 1;
-        st->batches += 1;
+        if (b.first) {
+            st->b_writers = s_cnt[4];
+            st->batches += 1;
+        } else {
+            st->b_writers |= s_cnt[4];
+        }
         st->queries += n;
         st->hits += s_cnt[0];
         st->invalid += s_cnt[1];

@@ -44,7 +44,7 @@ void execute_batch_small(Index &ix, const uint8_t *ops, const uint64_t *keys, co
     IndexView v = index_view(ix);
     const WriterCheck wc = writer_check(ix, 1);
     v.owner = wc.owner;
-    BatchView b{ops, keys, vals, (uint32_t)n, out_vals, out_status, wc.unit};
+    BatchView b{ops, keys, vals, (uint32_t)n, out_vals, out_status, wc.unit, 1};
     const uint32_t lds = SmallLds::bytes();
     // once per process (thread-safe: calls on different indices may run in
     // parallel threads)
