@@ -324,7 +324,7 @@ def run_write(args):
     d = [(to_device_u8(b.ops, dev), to_device_u64(b.keys, dev), to_device_u64(b.vals, dev)) for b in w.batches]
     out_v = torch.empty(Q, dtype=torch.int64, device=dev)
     out_s = torch.empty(Q, dtype=torch.uint8, device=dev)
-    ix = Index(device=0, profile=1, rebuild_policy=args.rebuild_policy)
+    ix = Index(device=0, profile=1, rebuild_policy=args.rebuild_policy, order_bits=args.order_bits)
     ix.bulk_load(w.load_keys, w.load_vals)
     for i in range(WU):
         ix.execute_raw(*d[i], out_v, out_s)
@@ -629,7 +629,7 @@ def main():
     ap.add_argument("--blocks-per-cu", type=int, default=0)
     ap.add_argument("--lds-budget", type=int, default=0)
     ap.add_argument("--descent-block", type=int, default=0)
-    ap.add_argument("--order-bits", type=int, default=0, choices=[0, 16, 24],
+    ap.add_argument("--order-bits", type=int, default=0, choices=[0, 16, 24, 32],
                     help="width of the ordering's range position (0 = chosen per batch)")
     ap.add_argument("--workload", choices=["search", "range", "write", "serve", "many"], default="search",
                     help="search: the 64M-key SEARCH batches (default); range: range searches; "

@@ -128,9 +128,10 @@ typedef struct {
                                  in every form; under graph capture the kernels are always separate */
     uint32_t order_bits;      /* width of the position inside the batch's key span that the ordering sorts
                                  by (Definition 3's order, then fixed up by key inside equal positions):
-                                 24, or 16 (one radix pass fewer; the descent then sorts each wave's 64
-                                 queries itself, which is all a batch without INSERT/DELETE needs for
-                                 locality), or 0 = chosen per batch like post_form (16 after a batch without
+                                 24, or 32 (one radix pass more, few equal positions left to fix up), or
+                                 16 (one radix pass fewer; the descent then sorts each wave's 64 queries
+                                 itself, which is all a batch without INSERT/DELETE needs for locality),
+                                 or 0 = chosen per batch like post_form (16 after a batch without
                                  INSERT/DELETE, 24 after one with them; default).  Results are the same */
 } pi_config;
 

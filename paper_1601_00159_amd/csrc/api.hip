@@ -310,7 +310,7 @@ pi_status pi_create(const pi_config *cfg_in, pi_index **out) {
         (cfg.graph_max_log2 != 0 && (cfg.graph_max_log2 < 12 || cfg.graph_max_log2 > 22)) ||
         (cfg.small_batch_log2 > 12 && cfg.small_batch_log2 != 255) || cfg.compact_percent > 1000 ||
         cfg.check_writers > 1 || cfg.post_form > 2 ||
-        (cfg.order_bits != 0 && cfg.order_bits != 16 && cfg.order_bits != 24)) {
+        (cfg.order_bits != 0 && cfg.order_bits != 16 && cfg.order_bits != 24 && cfg.order_bits != 32)) {
         set_err("invalid pi_config field");
         return PI_ERR_INVALID_ARG;
     }
@@ -429,7 +429,7 @@ void serve_step(pi::Index &ix, const uint8_t *d_ops, const uint64_t *d_keys, con
     if (set.used) PI_HIP(hipStreamWaitEvent(p.side, set.done, 0));
     const uint64_t *sk = nullptr;
     const uint32_t *sidx = nullptr;
-    const uint32_t bits = pi::order_bits(ix);
+    const uint32_t bits = pi::order_bits(ix, n);
     pi::order_batch(buf, d_ops, d_keys, n, p.side, &sk, &sidx, bits);
     PI_HIP(hipEventRecord(set.ordered, p.side));
     PI_HIP(hipStreamWaitEvent(s, set.ordered, 0));

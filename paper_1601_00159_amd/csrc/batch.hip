@@ -969,17 +969,19 @@ void execute_batch(Index &ix, const BatchBuffers &buf, const uint8_t *ops, const
     mark(0);
     const uint64_t *sk = nullptr;
     const uint32_t *sidx = nullptr;
-    const uint32_t bits = order_bits(ix);
+    const uint32_t bits = order_bits(ix, n);
     order_batch(buf, ops, keys, n, s, &sk, &sidx, bits);
     mark(1);
     finish_batch(ix, buf, sk, sidx, ops, vals, n, out_vals, out_status, s, ix.prof.on ? &rec : nullptr, bits);
 }
 
-uint32_t order_bits(const Index &ix) {
-    if (ix.cfg.queries_per_lane > 1) return 24;  // the wave sort serves one query per lane
+uint32_t order_bits(const Index &ix, uint64_t n) {
+    // (16 relies on the descent's wave sort, which serves one query per lane)
+    const uint32_t narrow = ix.cfg.queries_per_lane > 1 ? 24 : 16;
     const uint32_t b = ix.cfg.order_bits;
-    if (b) return b;
-    return ix.recent_writers ? 24 : 16;
+    if (b) return b == 16 ? narrow : b;
+    if (!ix.recent_writers) return narrow;
+    return n > (1u << 20) ? 32 : 24;
 }
 
 void order_batch(const BatchBuffers &buf, const uint8_t *ops, const uint64_t *keys, uint64_t n, hipStream_t so,

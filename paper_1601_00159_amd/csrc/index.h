@@ -238,10 +238,13 @@ void order_batch(const BatchBuffers &buf, const uint8_t *ops, const uint64_t *ke
 void finish_batch(Index &ix, const BatchBuffers &buf, const uint64_t *sk, const uint32_t *sidx, const uint8_t *ops,
                   const uint64_t *vals, uint64_t n, uint64_t *out_vals, uint8_t *out_status, hipStream_t s,
                   Profiler::Rec *prec, uint32_t pos_bits);
-// Width of a batch's range position: pi_config::order_bits, or 16 after a
-// batch without INSERT/DELETE (such a batch is ordered only for locality) and
-// 24 after one with them (a full order costs the fix-up less).
-uint32_t order_bits(const Index &ix);
+// Width of the range position of a batch of n queries: pi_config::order_bits,
+// or 16 after a batch without INSERT/DELETE (such a batch is ordered only for
+// locality), and after one with them 24, or 32 above 2^20 queries (a full
+// order is what the fix-up completes: about n^2 / 2^(bits+1) pairs of
+// queries share a position, which costs more than a fourth radix pass once
+// n passes 2^20).
+uint32_t order_bits(const Index &ix, uint64_t n);
 // Same result through a captured graph of the hot path for the smallest
 // power-of-two class >= n (padding with invalid queries).
 void execute_batch_graph(Index &ix, const uint8_t *ops, const uint64_t *keys, const uint64_t *vals, uint64_t n,

@@ -4,9 +4,9 @@
 // set by key range (Algorithm 1, Section 4.3.2).  Here the order is produced
 // range-first:
 //   1. [min, max] of the batch's keys (per-block partials, no atomics); every
-//      key gets a 24-bit position u inside that span (range_pos)
-//   2. three stable 8-bit radix passes on u: the batch is grouped by u, equal
-//      u in input order (coalesced writes: 256 destinations per pass)
+//      key gets a 16-, 24- or 32-bit position u inside that span (range_pos)
+//   2. one stable 8-bit radix pass per byte of u: the batch is grouped by u,
+//      equal u in input order (coalesced writes: 256 destinations per pass)
 //   3. k_fixup, in place: windows of ~1920 entries widened to whole groups;
 //      a group of equal u holds keys that may differ and must be ordered by
 //      (key, input position) -- insertion sort in LDS for the usual tiny
@@ -712,7 +712,9 @@ void MsdWorkspace::release() {
 void sort_batch_by_range(SortWorkspace &ws, MsdWorkspace &mw, const uint64_t *keys, const uint8_t *ops, uint64_t n,
                          bool batch, hipStream_t s, const uint64_t **out_keys, const uint32_t **out_idx,
                          uint32_t pos_bits) {
-    if (pos_bits != 16 && pos_bits != 24) throw Error{PI_ERR_INVALID_ARG, "internal error: range position width"};
+    if (pos_bits == 0) pos_bits = n > (1u << 20) ? 32 : 24;
+    if (pos_bits != 16 && pos_bits != 24 && pos_bits != 32)
+        throw Error{PI_ERR_INVALID_ARG, "internal error: range position width"};
     ws.ensure(n);
     mw.ensure(n);
     uint64_t *ka = ws.keys[0].as<uint64_t>(), *kb = ws.keys[1].as<uint64_t>();
@@ -730,7 +732,12 @@ void sort_batch_by_range(SortWorkspace &ws, MsdWorkspace &mw, const uint64_t *ke
     PI_LAUNCH_CHECK();
     // group by the position inside the span, one byte per pass; the result
     // lands in (ka, ia) either way
-    if (pos_bits == 24) {
+    if (pos_bits == 32) {
+        radix_pass(ws, keys, nullptr, ops, nn, 0, map, wf, kb, ib, s);
+        radix_pass(ws, kb, ib, nullptr, nn, 8, map, nullptr, ka, ia, s);
+        radix_pass(ws, ka, ia, nullptr, nn, 16, map, nullptr, kb, ib, s);
+        radix_pass(ws, kb, ib, nullptr, nn, 24, map, nullptr, ka, ia, s);
+    } else if (pos_bits == 24) {
         radix_pass(ws, keys, nullptr, ops, nn, 0, map, wf, ka, ia, s);
         radix_pass(ws, ka, ia, nullptr, nn, 8, map, nullptr, kb, ib, s);
         radix_pass(ws, kb, ib, nullptr, nn, 16, map, nullptr, ka, ia, s);

@@ -194,12 +194,11 @@ __device__ __forceinline__ uint32_t tower_height(uint64_t key, uint64_t seed, ui
     return 1 + extra;
 }
 
-// Key -> position of `bits` bits (24, or 16 for a batch ordered only for
-// locality) inside the batch's key span [lo, ...]: the top significant bits of
-// key - lo (keys below lo map to 0, above the span to the largest position).
-// Monotone in the key, so ordering by it, then by key among equal positions,
-// orders by key.
-constexpr uint32_t RANGE_BITS = 24;
+// Key -> position of `bits` bits (24 or 32, or 16 for a batch ordered only
+// for locality) inside the batch's key span [lo, ...]: the top significant
+// bits of key - lo (keys below lo map to 0, above the span to the largest
+// position).  Monotone in the key, so ordering by it, then by key among equal
+// positions, orders by key.
 struct RangeMap {
     uint64_t lo;
     uint32_t shift;
@@ -221,7 +220,7 @@ __device__ __forceinline__ RangeMap span_map(uint64_t lo, uint64_t hi, uint32_t 
     RangeMap m;
     m.lo = lo;
     m.shift = sbits > bits ? sbits - bits : 0;
-    m.top = (1u << bits) - 1;
+    m.top = (uint32_t)((1ull << bits) - 1);
     return m;
 }
 
@@ -312,13 +311,15 @@ struct MsdWorkspace {
     void ensure(uint64_t n);
     void release();
 };
-// pos_bits (24 or 16): the width of the range position, one radix pass per
-// byte.  16 orders by key only to 1/65536 of the span before the in-group
-// fix-up, which is all a batch without INSERT/DELETE needs (its order serves
-// locality; the descent then sorts each wave's queries itself).
+// pos_bits (16, 24 or 32; 0: 24 up to 2^20 keys, else 32): the width of the
+// range position, one radix pass per byte.  16 orders by key only to 1/65536
+// of the span before the in-group fix-up, which is all a batch without
+// INSERT/DELETE needs (its order serves locality; the descent then sorts each
+// wave's queries itself).  The wider the position, the fewer keys share one
+// and the less the fix-up has to sort.
 void sort_batch_by_range(SortWorkspace &ws, MsdWorkspace &mw, const uint64_t *keys, const uint8_t *ops, uint64_t n,
                          bool batch, hipStream_t s, const uint64_t **out_keys, const uint32_t **out_idx,
-                         uint32_t pos_bits = RANGE_BITS);
+                         uint32_t pos_bits = 0);
 
 // One stable 8-bit LSD pass (hist, column scan, scatter).  The digit is
 // (key >> shift) & 255, or, when map is not null, (range_pos(key) >> shift)

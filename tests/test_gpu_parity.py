@@ -180,13 +180,15 @@ def _random_batch(rng, pool, n, p_invalid=0.01):
 
 
 @pytest.mark.parametrize("policy,form,bits", [("never", 0, 0), ("always", 0, 0), ("threshold", 0, 0),
-                                              ("never", 1, 16), ("threshold", 2, 24), ("never", 2, 16)])
+                                              ("never", 1, 16), ("threshold", 2, 24), ("never", 2, 16),
+                                              ("always", 2, 32), ("never", 1, 32)])
 def test_mixed_batches_vs_oracle(policy, form, bits):
     """Mixed and SEARCH-only batches in turn (so that the default form of the
     post-descent steps, and the width of the ordering's range position,
     switch with them), and each form and width forced: batches with updates
     ordered by a 16-bit position leave larger groups to the in-group fix-up,
-    and SEARCH-only ones leave each wave's queries to the descent's sort."""
+    and SEARCH-only ones leave each wave's queries to the descent's sort;
+    a 32-bit position leaves few."""
     rng = np.random.default_rng({"never": 1, "always": 2, "threshold": 3}[policy] + 10 * form + bits)
     lk = rng.integers(0, 1 << 63, size=50_000, dtype=np.uint64)
     lv = rng.integers(0, 1 << 64, size=50_000, dtype=np.uint64, endpoint=False)
