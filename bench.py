@@ -772,7 +772,7 @@ def main():
         "config": {"workload": w.name, "loaded_keys": int(w.load_keys.size), "batch_queries": Q,
                    "op_mix": "100% SEARCH", "key_distribution": f"zipf {args.theta}" if args.theta else "uniform",
                    "ordering": (f"{args.order_bits}-bit range position" if args.order_bits else
-                                "range position of 16 bits after a batch without updates, else 24"),
+                                "range position of 16 bits after a batch without updates, else 24 (32 above 2^20 queries)"),
                    "parallelism": "single GPU"},
         "latency_ms": {"p50": round(float(np.percentile(lat, 50)), 4),
                        "p99": round(float(np.percentile(lat, 99)), 4)},
