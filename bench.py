@@ -550,7 +550,8 @@ def run_many(args):
                             torch.empty(len(b), dtype=torch.uint8, device=dev)) for b in batches])
     q_per_round = [sum(len(b) for b in batches) for batches in w.rounds]
     for mode in args.many_modes.split(","):
-        ixs = [Index(device=0, rebuild_policy=args.many_policy, post_form=args.many_post_form) for _ in w.loads]
+        ixs = [Index(device=0, rebuild_policy=args.many_policy, post_form=args.many_post_form,
+                     order_bits=args.order_bits) for _ in w.loads]
         for ix, (k, v) in zip(ixs, w.loads):
             ix.bulk_load(k, v)
         torch.cuda.synchronize()
