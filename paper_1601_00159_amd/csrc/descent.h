@@ -334,55 +334,69 @@ __device__ __forceinline__ Found walk_storage(uint64_t q, uint32_t cur, uint64_t
                                               const uint32_t *__restrict__ snext,
                                               const uint8_t *__restrict__ smeta, unsigned int *errors) {
     Found f;
-    uint8_t mc = 0;
-    if (!links) {
-        // base nodes only: the successor of slot i is i+1; same 8-entry window
-        // as the index levels, then the value of the node found
-        const ulonglong2 *S2 = reinterpret_cast<const ulonglong2 *>(skey + ((cur + 1) & ~1u));
+    // A step reads the window of the next 8 slots' keys (the same 8-entry
+    // window as the index levels).  Without linked nodes the successor of
+    // slot i is i+1, so the walk moves through the keys <= q of the window.
+    // With linked nodes (most are still base nodes, whose successor is the
+    // next slot) it also reads the flags of the slots before those keys,
+    // moves up to the first linked slot, and follows its link when it gets
+    // there.
+    uint32_t nxt = cur + 1;
+    for (uint32_t steps = 0;; steps++) {
+        if (steps >= WALK_LIMIT) {  // a well-formed list never gets here
+            atomicOr(errors, ERR_WALK);
+            break;
+        }
+        const uint32_t a = (cur + 1) & ~1u;  // keys of slots a .. a+7
+        const uint32_t skip = (cur + 1) & 1u;
+        const ulonglong2 *S2 = reinterpret_cast<const ulonglong2 *>(skey + a);
         ulonglong2 kp[4];
 #pragma unroll
         for (int i = 0; i < 4; i++) kp[i] = S2[i];
+        // offset of the first linked slot from cur (9: none of cur .. cur+7;
+        // a window of 8 successors ends on cur+8, whose flag the next step
+        // reads)
+        uint32_t firstlink = 9;
+        if (links) {
+            const uint32_t m0 = cur & ~7u;  // flags of slots m0 .. m0+15
+            const uint64_t *M8 = reinterpret_cast<const uint64_t *>(smeta + m0);
+            const uint64_t mlo = M8[0], mhi = M8[1];
+            const uint32_t sh = 8 * (cur - m0);
+            const uint64_t fl = sh ? (mlo >> sh) | (mhi << (64 - sh)) : mlo;  // slots cur .. cur+7
+            static_assert(META_LINK == 2, "the flag test below reads bit 1 of each byte");
+            const uint64_t lk = (fl >> 1) & 0x0101010101010101ull;
+            if (lk) firstlink = (uint32_t)__builtin_ctzll(lk) >> 3;
+        }
         const uint64_t keys[8] = {kp[0].x, kp[0].y, kp[1].x, kp[1].y, kp[2].x, kp[2].y, kp[3].x, kp[3].y};
-        const uint32_t skip = (cur + 1) & 1u;
-        const uint32_t cnt = leading_le<8>(keys, skip, q);  // stops at the tail's +infinity
+        const uint32_t avail = 8 - skip;                          // successor keys in the window
+        const uint32_t cons = firstlink < avail ? firstlink : avail;  // consecutive successors
+        uint32_t cnt = leading_le<8>(keys, skip, q);                 // stops at the tail's +infinity
+        cnt = cnt < cons ? cnt : cons;
         if (cnt > 0) {
             const uint32_t li = skip + cnt - 1;
-            uint64_t lk = keys[0];
+            uint64_t kk = keys[0];
 #pragma unroll
-            for (int i = 1; i < 8; i++) lk = ((uint32_t)i == li) ? keys[i] : lk;
-            ck = lk;
+            for (int i = 1; i < 8; i++) kk = ((uint32_t)i == li) ? keys[i] : kk;
+            ck = kk;
+            cur += cnt;
         }
-        cur += cnt;
-        if (cnt == 8 - skip) {
-            for (uint32_t steps = 0;; steps++) {
-                if (steps >= WALK_LIMIT) {
-                    atomicOr(errors, ERR_WALK);
-                    break;
-                }
-                const uint64_t kn = skey[cur + 1];
-                if (kn > q) break;
-                cur++;
-                ck = kn;
-            }
+        if (cnt < cons) {  // the next key along the list is > q
+            nxt = cur + 1;
+            break;
         }
-        if (dead && cur != HEAD_SLOT && ck == q) mc = smeta[cur];
-        f.next = cur + 1;
-    } else {
-        uint32_t nxt = cur + 1;
-        for (uint32_t steps = 0;; steps++) {
-            if (steps >= WALK_LIMIT) {  // a well-formed list never gets here
-                atomicOr(errors, ERR_WALK);
-                break;
-            }
-            mc = smeta[cur];
-            nxt = (mc & META_LINK) ? snext[cur] : cur + 1;
+        if (cons == firstlink) {  // at a linked slot: one step along its link
+            nxt = snext[cur];
             const uint64_t kn = skey[nxt];
             if (kn > q) break;
             cur = nxt;
             ck = kn;
         }
-        f.next = nxt;
+        // else the window ran out with no link: the next window
     }
+    // (flags matter only for a node that holds q, and only once some node is
+    // flagged deleted)
+    const uint8_t mc = dead && cur != HEAD_SLOT && ck == q ? smeta[cur] : (uint8_t)0;
+    f.next = nxt;
     f.node = cur;
     f.exists = cur != HEAD_SLOT && ck == q;
     f.live = f.exists && !(mc & META_DEL);
