@@ -134,7 +134,6 @@ void ensure_host(pi_group *g, uint32_t count) {
     g->cap_items = count;
 }
 
-// Counters of the previous call: storage use and the threshold rebuild.
 void ensure_lanes(pi_group *g) {
     if (g->ev_fork) return;
     for (int k = 0; k < pi_group::LANES; k++) {
@@ -148,11 +147,11 @@ void ensure_lanes(pi_group *g) {
 // Runs fn(j, lane) for every job j < njobs, the jobs touching disjoint
 // indices, on the group's lane streams (ordered after the work already on s,
 // joined back into s).  Up to host_threads host threads take the jobs from a
-// shared counter, each issuing on a lane stream of its own: a round over many
-// indices is bound by the host's launches (a large batch is ~16 launches, a
-// rebuild ~30 plus a wait for its index's counters), not by the device.  The
-// first error a job raises stops the taking of new jobs and is rethrown once
-// every thread has finished and the lanes are joined.
+// shared counter, each issuing on a lane stream of its own: a large batch is
+// ~16 launches and a rebuild ~30 plus a wait for its index's counters, and
+// one thread issuing all of them for hundreds of indices keeps the device
+// waiting.  The first error a job raises stops the taking of new jobs and is
+// rethrown once every thread has finished and the lanes are joined.
 // after: what the lanes wait for (null: everything on s so far).
 template <class F>
 void on_lanes(pi_group *g, hipStream_t s, uint32_t njobs, F &&fn, hipEvent_t after = nullptr) {
@@ -206,7 +205,8 @@ struct LentScratch {
         std::swap(ix.sortws, lb.sort);
         std::swap(ix.msdws, lb.msd);
         std::swap(ix.scanws, lb.scan);
-        for (int k = 0; k < 10; k++) std::swap(ix.tmp[k], lb.tmp[k]);
+        static_assert(sizeof(ix.tmp) == sizeof(lb.tmp), "the lent set mirrors the index's scratch");
+        for (size_t k = 0; k < sizeof(lb.tmp) / sizeof(lb.tmp[0]); k++) std::swap(ix.tmp[k], lb.tmp[k]);
     }
 };
 
@@ -249,10 +249,17 @@ void free_deferred(pi_group *g) {
     if (g->fstream) PI_HIP(hipStreamSynchronize(g->fstream));
     for (hipStream_t l : g->lane)
         if (l) PI_HIP(hipStreamSynchronize(l));
+    // every pointer leaves the lists before any free can fail (none freed twice)
+    hipError_t first = hipSuccess;
     for (auto &l : g->graveyard) {
-        for (void *p : l) PI_HIP(hipFree(p));
-        l.clear();
+        std::vector<void *> ps;
+        ps.swap(l);
+        for (void *p : ps) {
+            const hipError_t e = hipFree(p);
+            if (first == hipSuccess) first = e;
+        }
     }
+    PI_HIP(first);
 }
 
 // An index whose rebuild policy may act, and the counters it acts on.
@@ -282,7 +289,12 @@ std::vector<Due> settle_previous(pi_group *g) {
         // copy (group or single calls) bounds the storage in use now
         ix.used_upper = std::min<uint64_t>(ix.used_upper, st.nused + (ix.enq_queries - g->last_enq[k]));
         ix.recent_writers = st.b_writers != 0;  // the form of the next large batch's post-descent steps
-        if (ix.cfg.rebuild_policy != PI_REBUILD_NEVER) due.push_back(Due{g->last[k], st});
+        if (ix.cfg.rebuild_policy != PI_REBUILD_NEVER) {
+            // the policy may change the storage: no range search of an
+            // earlier call may reuse its ordering and interceptions
+            ix.epoch++;
+            due.push_back(Due{g->last[k], st});
+        }
     }
     g->last.clear();
     g->last_enq.clear();

@@ -478,6 +478,57 @@ def test_range_collect_after_other_counts():
             assert np.array_equal(to_numpy_u64(gk), wk) and np.array_equal(to_numpy_u64(gv), wv), j
 
 
+def test_range_collect_after_a_group_rebuild():
+    """A range count, then a group call in which the index sits out but its
+    rebuild policy acts on the counters of the call before (the storage is
+    merged, so slots move), then the collect of the same ranges: the collect
+    must not reuse the count's interceptions, and gives the oracle's pairs."""
+    from paper_1601_00159_amd.index import Group
+    from paper_1601_00159_amd.index import to_device_u8 as d8
+    rng = np.random.default_rng(21)
+    lk = np.unique(rng.integers(0, 1 << 63, size=40_000, dtype=np.uint64))
+    lv = rng.integers(0, 1 << 64, size=lk.size, dtype=np.uint64, endpoint=False)
+    orc = SkipList()
+    orc.bulk_load(lk, lv)
+    dev = torch.device("cuda", 0)
+
+    def batch(n):
+        ops = rng.choice(np.array([0, 1, 2], dtype=np.uint8), size=n, p=[0.4, 0.4, 0.2])
+        keys = np.where(ops == 1, rng.integers(0, 1 << 63, size=n, dtype=np.uint64), lk[rng.integers(0, lk.size, n)])
+        vals = rng.integers(0, 1 << 64, size=n, dtype=np.uint64, endpoint=False)
+        return ops, keys.astype(np.uint64), vals
+
+    def dev_batch(ops, keys, vals):
+        return (d8(ops, dev), to_device_u64(keys, dev), to_device_u64(vals, dev),
+                torch.empty(len(keys), dtype=torch.int64, device=dev),
+                torch.empty(len(keys), dtype=torch.uint8, device=dev))
+
+    with Index(rebuild_policy="threshold", rebuild_fraction=0.01, rebuild_min=1) as a, Index() as b, Group() as g:
+        a.bulk_load(lk, lv)
+        b.bulk_load(lk, lv)
+        ops, keys, vals = batch(30_000)  # ~12K new nodes: the next call rebuilds a
+        wv, ws = orc.execute_batch(ops, keys, vals)
+        ba = dev_batch(ops, keys, vals)
+        g.execute([a, b], [ba, dev_batch(*batch(1_000))])
+        torch.cuda.synchronize()
+        assert_same(to_numpy_u64(ba[3]), ba[4].cpu().numpy(), wv, ws, "group call")
+        rep0 = a.stats()["repairs"]
+        ok, _ = orc.export()
+        lo, hi = _ranges(rng, ok, 4_000)
+        dlo, dhi = to_device_u64(lo, a.device), to_device_u64(hi, a.device)
+        off = a.range_count(dlo, dhi)
+        torch.cuda.synchronize()
+        g.execute([b], [dev_batch(*batch(1_000))])  # a sits out; its policy rebuilds it
+        torch.cuda.synchronize()
+        assert a.stats()["repairs"] > rep0, "the call did not rebuild the index that sat out"
+        total = int(off[-1].item())
+        gk, gv = a.range_collect(dlo, dhi, off, total)
+        torch.cuda.synchronize()
+        wc, wk, wv2 = orc.range_batch(lo, hi)
+        assert np.array_equal((off[1:] - off[:-1]).cpu().numpy().astype(np.uint64), wc)
+        assert np.array_equal(to_numpy_u64(gk), wk) and np.array_equal(to_numpy_u64(gv), wv2)
+
+
 def test_range_search_edges():
     with Index() as ix:
         off = ix.range_count(np.zeros(0, dtype=np.uint64), np.zeros(0, dtype=np.uint64))
