@@ -626,7 +626,7 @@ uint64_t export_live(Index &ix, uint64_t *okeys, uint64_t *ovals, uint64_t cap, 
     return n;
 }
 
-void rebuild(Index &ix, hipStream_t s) {
+void rebuild(Index &ix, hipStream_t s, const DevState *known) {
     TraceRange tr("pi:rebuild");
     bg_quiesce(ix);  // a background index rebuild reads the storage about to be replaced
     Profiler::Rec rec{};
@@ -636,7 +636,10 @@ void rebuild(Index &ix, hipStream_t s) {
         PI_HIP(hipEventRecord(rec.e[0], s));
     }
     DevState cur;
-    read_state(ix, s, &cur);
+    if (known)
+        cur = *known;
+    else
+        read_state(ix, s, &cur);
     const uint64_t live = cur.n_live;
     // room for the largest batch the index has taken as well: a rebuilt
     // storage that the next such batch does not fit would grow again at once

@@ -84,6 +84,7 @@ struct pi_group {
     uint32_t cap_items = 0;
     std::vector<pi_index *> last;  // indices whose counters h_states holds
     std::vector<uint64_t> last_enq;  // their enq_queries when the copy was enqueued
+    std::vector<uint64_t> last_epoch;  // their epoch then (unchanged: no call has touched them since)
     hipEvent_t ev = nullptr;
     hipEvent_t ev_start = nullptr, ev_fused = nullptr;  // fork/join of the fused launch
     hipStream_t fstream = nullptr;                      // the fused launch runs beside the large batches
@@ -210,8 +211,10 @@ struct LentScratch {
     }
 };
 
-// The index's rebuild policy after a batch whose counters are st.
-void apply_policy(Index &ix, const DevState &st, hipStream_t s) {
+// The index's rebuild policy after a batch whose counters are st (exact:
+// nothing has run on the index since, so a rebuild need not read them again).
+void apply_policy(Index &ix, const DevState &st, bool exact, hipStream_t s) {
+    const DevState *known = exact ? &st : nullptr;
     const uint32_t pol = ix.cfg.rebuild_policy;
     const double thr = rebuild_threshold(ix);
     if (pol == PI_REBUILD_BACKGROUND || pol == PI_REBUILD_SLICES) {
@@ -219,14 +222,14 @@ void apply_policy(Index &ix, const DevState &st, hipStream_t s) {
         const double compact = (ix.cfg.compact_percent ? ix.cfg.compact_percent : 100) / 100.0 *
                                (double)std::max<uint64_t>(ix.nbase, 1);
         if ((double)st.changes >= std::max(compact, thr)) {
-            rebuild(ix, s);
+            rebuild(ix, s, known);
             ix.ring_seen = ix.ring_head;
         } else if (st.changes >= ix.changes_base && (double)(st.changes - ix.changes_base) >= thr) {
             if (pol == PI_REBUILD_BACKGROUND) {
                 bg_start(ix, st, s);
             } else if (slice_round(ix, st.nused, s)) {
                 ix.changes_base = st.changes;
-            } else {
+            } else {  // (after a slice round that gave up: counters read again)
                 rebuild(ix, s);
                 ix.ring_seen = ix.ring_head;
             }
@@ -234,7 +237,7 @@ void apply_policy(Index &ix, const DevState &st, hipStream_t s) {
         return;
     }
     if ((pol == PI_REBUILD_ALWAYS && st.changes > 0) || (double)st.changes >= thr) {
-        rebuild(ix, s);
+        rebuild(ix, s, known);
         ix.ring_seen = ix.ring_head;
     }
 }
@@ -266,6 +269,7 @@ void free_deferred(pi_group *g) {
 struct Due {
     pi_index *h;
     DevState st;
+    bool exact;  // no call has touched the index since the copy: st is its state now
 };
 
 // Waits for the previous call and takes up its counters: an index whose
@@ -290,14 +294,16 @@ std::vector<Due> settle_previous(pi_group *g) {
         ix.used_upper = std::min<uint64_t>(ix.used_upper, st.nused + (ix.enq_queries - g->last_enq[k]));
         ix.recent_writers = st.b_writers != 0;  // the form of the next large batch's post-descent steps
         if (ix.cfg.rebuild_policy != PI_REBUILD_NEVER) {
+            const bool exact = ix.epoch == g->last_epoch[k];
             // the policy may change the storage: no range search of an
             // earlier call may reuse its ordering and interceptions
             ix.epoch++;
-            due.push_back(Due{g->last[k], st});
+            due.push_back(Due{g->last[k], st, exact});
         }
     }
     g->last.clear();
     g->last_enq.clear();
+    g->last_epoch.clear();
     return due;
 }
 
@@ -339,8 +345,8 @@ void run_group(pi_group *g, pi_index *const *indices, const pi_batch *batches, u
 
 void run_group_body(pi_group *g, pi_index *const *indices, const pi_batch *batches, uint32_t count, hipStream_t s,
                     uint64_t fused_max, const uint8_t *ops_override) {
-    for (uint32_t i = 0; i < count; i++) indices[i]->ix.epoch++;
     const std::vector<Due> due = settle_previous(g);
+    for (uint32_t i = 0; i < count; i++) indices[i]->ix.epoch++;
     ensure_lanes(g);
     PI_HIP(hipEventRecord(g->ev_in, s));
     // A policy acts before its index's batch.  Before the fused launch: the
@@ -373,7 +379,7 @@ void run_group_body(pi_group *g, pi_index *const *indices, const pi_batch *batch
     on_lanes(g, s, (uint32_t)first.size(), [&](uint32_t j, int k) {
         const Due &d = due[first[j]];
         LentScratch lent(d.h->ix, g->lbuf[k]);
-        apply_policy(d.h->ix, d.st, g->lane[k]);
+        apply_policy(d.h->ix, d.st, d.exact, g->lane[k]);
     });
     for (uint32_t i = 0; i < count; i++)
         if (early(i)) group_capacity(indices[i]->ix, batches[i], s);
@@ -445,7 +451,7 @@ void run_group_body(pi_group *g, pi_index *const *indices, const pi_batch *batch
             if (jb.due >= 0) {
                 const Due &d = due[jb.due];
                 LentScratch lent(d.h->ix, lb);
-                apply_policy(d.h->ix, d.st, ls);
+                apply_policy(d.h->ix, d.st, d.exact, ls);
             }
             if (jb.batch < 0) return;
             const pi_batch &b = batches[jb.batch];
@@ -464,11 +470,13 @@ void run_group_body(pi_group *g, pi_index *const *indices, const pi_batch *batch
     uint32_t ns = 0;
     g->last.clear();
     g->last_enq.clear();
+    g->last_epoch.clear();
     for (uint32_t i = 0; i < count; i++) {
         if (!batches[i].n) continue;
         g->h_ptrs[ns++] = indices[i]->ix.dstate;
         g->last.push_back(indices[i]);
         g->last_enq.push_back(indices[i]->ix.enq_queries);
+        g->last_epoch.push_back(indices[i]->ix.epoch);
     }
     if (ns) {
         g->d_ptrs.ensure((size_t)g->cap_items * sizeof(DevState *));

@@ -207,7 +207,9 @@ inline double rebuild_threshold(const Index &ix) {
 // build.hip
 void init_empty(Index &ix, hipStream_t s);
 void bulk_load(Index &ix, const uint64_t *keys, const uint64_t *vals, uint64_t n, hipStream_t s);
-void rebuild(Index &ix, hipStream_t s);  // merge + drop deleted + rebuild levels
+// merge + drop deleted + rebuild levels; known: the index's counters when the
+// caller holds an exact copy (else they are read, a wait for the stream)
+void rebuild(Index &ix, hipStream_t s, const DevState *known = nullptr);
 uint64_t export_live(Index &ix, uint64_t *okeys, uint64_t *ovals, uint64_t cap, hipStream_t s);
 void read_state(Index &ix, hipStream_t s, DevState *out);  // synchronises s
 // Storage of at least need slots (the slots in use plus a batch), sized want
