@@ -345,13 +345,18 @@ pi_status pi_group_destroy(pi_group *g);
  * batches of at most fused_max queries in one persistent fused launch on a
  * stream of the group's own, the others on the multi-kernel path spread over
  * four lane streams of the group, issued by host_threads host threads (the
- * calling one and workers that live for the call); the rebuilds the indices'
- * policies start at the call (for the counters of the group's previous call)
- * run the same way; all of it is joined back into the caller's stream.  The indices must be distinct, live on one device and not be used
- * by other calls until this one completes.  Errors: PI_ERR_INVALID_ARG (NULL pointers,
- * count above max_indices, a repeated index, mixed devices, n above 2^31 - 1),
- * PI_ERR_CAPACITY (an index with a fixed capacity has no room; nothing is
- * enqueued). */
+ * calling one and workers that live for the call).  The rebuild policies of
+ * the indices of the group's previous call act on its counters at this call:
+ * for an index whose batch runs fused (or whose capacity is fixed) before
+ * the fused launch; for one with a larger batch on its lane right before
+ * that batch; for one without a batch in this call on a lane beside the
+ * rest.  All of it is joined back into the caller's stream.  The indices
+ * must be distinct, live on one device and not be used by other calls until
+ * this one completes (nor, until then, the indices of the group's previous
+ * call).  Errors: PI_ERR_INVALID_ARG (NULL pointers, count above
+ * max_indices, a repeated index, mixed devices, n above 2^31 - 1),
+ * PI_ERR_CAPACITY (an index with a fixed capacity has no room; nothing of
+ * this call's batches is enqueued). */
 pi_status pi_group_execute(pi_group *g, pi_index *const *indices, const pi_batch *batches, uint32_t count,
                            pi_stream stream);
 /* Autotuner: replays the given batches as SEARCH-only (the indices' contents
