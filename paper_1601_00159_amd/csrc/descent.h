@@ -5,6 +5,8 @@
 #pragma once
 
 #include <algorithm>
+#include <mutex>
+#include <unordered_map>
 
 #include "index.h"
 
@@ -404,13 +406,26 @@ __device__ __forceinline__ Found walk_storage(uint64_t q, uint32_t cur, uint64_t
     return f;
 }
 
+// Raises a kernel's dynamic LDS limit to at least lds, never lowers it:
+// several host threads (a group call's lanes) launch the same kernel with
+// different LDS sizes, and a limit lowered between another thread's setting
+// and its launch would refuse that launch.
+inline void raise_lds_limit(const void *kern, size_t lds) {
+    static std::mutex mu;
+    static std::unordered_map<const void *, size_t> limit;
+    std::lock_guard<std::mutex> lock(mu);
+    size_t &cur = limit[kern];
+    if (lds <= cur) return;
+    PI_HIP(hipFuncSetAttribute(kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+    cur = lds;
+}
+
 // Grid of a persistent kernel that stages the upper levels in LDS: as many
 // blocks as can be resident on all CUs, at most one per tile, a multiple of 8
 // (the XCD count) when there are enough tiles.
 template <class Kern>
 uint32_t persistent_grid(const Index &ix, Kern kern, int threads, size_t lds, uint64_t ntiles) {
-    if (lds > 65536)
-        PI_HIP(hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+    if (lds > 65536) raise_lds_limit((const void *)kern, lds);
     int per_cu = 0;
     PI_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, threads, lds));
     if (per_cu < 1)
